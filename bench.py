@@ -1,0 +1,199 @@
+"""Benchmark: adjoint-state FWI gradient throughput on one MI355X.
+
+One step = one complete gradient of the least-squares misfit for every shot
+of the workload (forward sweep with checkpoints, misfit, recompute + adjoint
+sweep with imaging, finalization), chain-ruled into the K-rho, Vp-rho, Ip-rho
+and Vp-Ip parameterizations.  value = padded cells x time steps x shots /
+seconds per step (Gcell-updates/s; each cell-step counted once although the
+forward, recompute and adjoint sweeps all touch it).
+
+Prints one JSON line.  Inputs are synthetic (workloads.py), generated and
+resident in HBM before the timed region.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+METRIC = "Gcell-updates/s (fwd+adjoint grad, FP32) vs plain; p50/p99 gradient latency"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3"])
+    ap.add_argument("--tile-z", type=int, default=0)
+    ap.add_argument("--shot-groups", type=int, default=0)
+    ap.add_argument("--ckpt-every", type=int, default=0)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=0, help="time steps of the CPU sample")
+    return ap.parse_args()
+
+
+def workload(name):
+    from paper_1804_01184_amd import workloads as W
+    if name == "c2":
+        return W.config2()
+    w = W.config3()
+    return w
+
+
+def algorithmic_bytes(plan_info, S, G):
+    """Bytes one launch of each batched kernel must move at least (FP32):
+    forward step: read and write vx, vz, p for every cell and shot, the pz
+    split in the absorbing layer, the model (K, bx, bz) once per shot group;
+    adjoint step: the same for the adjoint state, plus p^n and p^{n+1} (and
+    their layer splits), plus one read-modify-write of the three gradient
+    accumulators per group."""
+    N = plan_info["Nz"] * plan_info["Nx"]
+    fp = plan_info["pml_cells"] / N
+    fwd = N * S * (24 + 8 * fp) + G * N * 12
+    adj = N * S * (32 + 16 * fp) + G * N * (12 + 24)
+    return {"fwd_step": fwd, "adj_step": adj, "per_cell_fwd": fwd / (N * S),
+            "per_cell_adj": adj / (N * S), "pml_fraction": fp}
+
+
+def cpu_baseline(w, steps):
+    """The FP64 oracle on a bounded sample of the same workload: the full
+    grid, one shot per host thread (at most all shots), `steps` time steps;
+    observed data zero (same cost as any other)."""
+    import oracle as O
+    nth = O.num_threads()
+    S = min(w.nshots, nth)
+    sub = w.subset(shots=np.linspace(0, w.nshots - 1, S).round().astype(int), nt=steps)
+    g = O.Grid(sub.nz, sub.nx, sub.dz, sub.dx, sub.npml, sub.nt, sub.dt, sub.vmax, sub.pml_r)
+    f = sub.wavelet()
+    obs = np.zeros((S, sub.nrec, sub.nt))
+    t = time.perf_counter()
+    O.gradient(g, O.VP_RHO, sub.vp_start, sub.rho_start, sub.src_xz, sub.rec_xz, f, obs)
+    dt = time.perf_counter() - t
+    Nz, Nx = sub.padded
+    return {"value": Nz * Nx * sub.nt * S / dt / 1e9, "unit": "Gcell-updates/s", "cores": nth,
+            "kind": "oracle", "seconds": dt,
+            "sample": f"{S} shots x {steps} steps of the full {Nz}x{Nx} padded grid "
+                      f"(gradient in Vp-rho, FP64, OpenMP)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported (shots would "
+              "shard across GPUs with one all-reduce of the gradient; not built here)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1804_01184_amd import api
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    w = workload(args.workload)
+    grid = api.Grid.of(w)
+    f = torch.tensor(w.wavelet(), dtype=torch.float32, device=dev)
+    vp0 = torch.tensor(w.vp_start, dtype=torch.float32, device=dev)
+    rho0 = torch.tensor(w.rho_start, dtype=torch.float32, device=dev)
+    plan = api.Plan(grid, w.src_xz, w.rec_xz, tile_z=args.tile_z,
+                    shot_groups=args.shot_groups, ckpt_every=args.ckpt_every)
+    info = plan.info
+    obs = plan.forward("vp-rho", w.vp_true, w.rho_true, f)
+    K0, r0 = api.model_convert("vp-rho", "k-rho", vp0, rho0)
+    Jb = torch.empty(1, dtype=torch.float32, device=dev)
+    gK, gr = torch.empty_like(K0), torch.empty_like(K0)
+    others = {p: api.model_convert("k-rho", p, K0, r0) for p in ("vp-rho", "ip-rho", "vp-ip")}
+    out = {}
+
+    def step():
+        plan.gradient("k-rho", K0, r0, f, obs, out=(Jb, gK, gr))
+        for p, (m1, m2) in others.items():
+            out[p] = api.chain_rule(p, m1, m2, gK, gr)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    plan.timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for k in range(args.steps):
+        step()
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per_class = plan.timing_read(reset=True)
+    plan.timing(False)
+    lat = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)])
+    ms = wall / args.steps * 1e3
+    cells = w.cell_steps()
+    value = cells / (ms * 1e-3) / 1e9
+
+    S, G = w.nshots, info["shot_groups"]
+    ab = algorithmic_bytes(info, S, G)
+    dom = max(("fwd_step", "adj_step"), key=lambda k: per_class[k][1])
+    n_launch, dom_ms = per_class[dom]
+    avg_s = dom_ms / n_launch * 1e-3
+    achieved = ab[dom] / avg_s / 1e9
+    roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+            "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+            "traffic": None, "avg_launch_us": round(avg_s * 1e6, 2), "launches": n_launch,
+            "bytes_per_launch": int(ab[dom]),
+            "bytes_per_cell_step": round(ab["per_cell_" + dom.split("_")[0]], 2)}
+    classes = {k: {"launches": v[0], "ms": round(v[1], 3)} for k, v in per_class.items()
+               if v[0]}
+
+    plain = None
+    if not args.no_plain:
+        pp = api.Plan(grid, w.src_xz, w.rec_xz, mode="plain")
+        pp.gradient("k-rho", K0, r0, f, obs)          # warm
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        Jp, gKp, grp = pp.gradient("k-rho", K0, r0, f, obs)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t
+        rel = float((gKp - gK).abs().max() / gK.abs().max())
+        plain = {"value": round(cells / tp / 1e9, 3), "ms_per_step": round(tp * 1e3, 2),
+                 "speedup_batched_vs_plain": round(tp * 1e3 / ms, 3),
+                 "grad_K_maxrel_vs_batched": rel}
+        del pp
+
+    cpu = None
+    if not args.no_cpu:
+        nt_s = args.cpu_steps or max(50, min(w.nt, int(1.0e8 / (info["Nz"] * info["Nx"]))))
+        cpu = cpu_baseline(w, nt_s)
+        cpu["value"] = round(cpu["value"], 5)
+        cpu["seconds"] = round(cpu["seconds"], 2)
+
+    rec = {
+        "metric": METRIC, "value": round(value, 3), "unit": "Gcell-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: {w.nz}x{w.nx} at {w.dx:g} m + {w.npml} PML "
+                               f"({info['Nz']}x{info['Nx']} padded), {w.nt} steps, "
+                               f"{w.nshots} shots x {w.nrec} receivers, gradient in K-rho "
+                               f"chain-ruled to Vp-rho, Ip-rho, Vp-Ip",
+                   "cell_steps": cells, "tile_z": info["tile_z"], "shot_groups": G,
+                   "ckpt_every": info["ckpt_every"], "segments": info["segments"]},
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
+                       "p99": round(float(np.percentile(lat, 99)), 3)},
+        "roofline": roof,
+        "kernels": classes,
+        "plain": plain,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

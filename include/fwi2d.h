@@ -1,0 +1,227 @@
+/*
+ * fwi2d.h -- C ABI of the MI355X (gfx950) library for the scheme-III
+ * gradient path of Bharadwaj, Mulder & Drijkoningen, "A parameterization
+ * analysis for acoustic full-waveform inversion of sub-wavelength anomalies"
+ * (arXiv:1804.01184).
+ *
+ * The calls follow the paper's statement of the problem (section "Modelling
+ * and Inversion"): a model given by two parameters per point in one of the
+ * parameterizations of Table 1; sources and receivers at given positions; a
+ * known source wavelet; modelled data p; the least-squares misfit J between
+ * modelled and observed data; and the gradient of J with respect to the
+ * chosen parameters, obtained by the adjoint-state method with respect to
+ * bulk modulus and density and then the chain rule (scheme III: time-domain
+ * staggered-grid finite differences with absorbing boundaries on all sides).
+ *
+ * Discretisation (the paper leaves it open; these are the readings used):
+ * fourth-order staggered space derivatives and leapfrog time stepping of the
+ * first-order pressure / particle-velocity system; split-field PML with
+ * quadratic damping d0 (s/L)^2, d0 = 3 vmax ln(1/R) / (2L), Crank-Nicolson
+ * in time; the model continues into the PML by edge replication and the
+ * gradient is folded back onto the edge cells; buoyancy at staggered points
+ * is the inverse arithmetic mean of the two densities; the source forces
+ * (1/K) p_tt - div(grad p / rho) = f(t) delta(x - xs), injected and sampled
+ * bilinearly; trace sample n is the pressure at time (n+1) dt.  The misfit
+ * is J = 1/2 sum over shots, receivers and samples of (p - q)^2, and the
+ * gradient is the exact derivative of that discrete J.
+ *
+ * Conventions shared by all calls
+ *  - Arrays are FP32, row-major, x fastest.  Model and gradient arrays are
+ *    physical [nz][nx]; traces are [nshots][nrec][nt].
+ *  - Every float pointer is a DEVICE pointer on the plan's device, owned by
+ *    the caller.  Geometry in fwi_acq is read from HOST memory once, at plan
+ *    creation.
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL is the default
+ *    stream) and the calls return without waiting for it.  Scalars such as J
+ *    are written to device memory.
+ *  - Scratch memory comes from the caller's workspace `ws` of at least
+ *    fwi_workspace_bytes(plan, op) bytes, 256-byte aligned.  The plan owns
+ *    only small geometry tables, allocated at creation.
+ *  - Calls return a status and never throw.  Argument errors are reported
+ *    before any work is enqueued; fwi_last_error() then describes the
+ *    failure (thread-local).  Device faults surface from fwi_sync().
+ *  - Results do not depend on other work running on the device; a plan may
+ *    be used from one host thread at a time.
+ */
+#ifndef FWI2D_H
+#define FWI2D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FWI_OK = 0,
+    FWI_EINVAL = -1,      /* bad argument, shape or geometry                  */
+    FWI_ENOMEM = -2,      /* host or device allocation of plan tables failed */
+    FWI_EDEVICE = -3,     /* HIP runtime error                                */
+    FWI_EUNSTABLE = -4,   /* dt * vmax / min(dx, dz) above the stability limit */
+    FWI_ENONFINITE = -5,  /* non-finite value detected                        */
+    FWI_ESTATE = -6,      /* plan used on the wrong device or in a bad state  */
+    FWI_EWORKSPACE = -7   /* workspace missing, misaligned or too small       */
+} fwi_status;
+
+/* Parameterizations of Table 1 (m1, m2 are absolute values, SI units). */
+typedef enum {
+    FWI_K_RHO = 0,        /* (D) bulk modulus K (Pa), density rho (kg/m^3) */
+    FWI_VP_RHO = 1,       /* (A) P velocity Vp (m/s), density               */
+    FWI_IP_RHO = 2,       /* (B) P impedance Ip = rho Vp, density           */
+    FWI_VP_IP = 3,        /* (C) P velocity, P impedance                    */
+    FWI_INVK_INVRHO = 4   /* (E) 1/K, 1/rho                                 */
+} fwi_param;
+
+typedef enum {
+    FWI_EXEC_BATCHED = 0, /* all shots of a step in one fused launch          */
+    FWI_EXEC_PLAIN = 1    /* one shot per launch, separate velocity / pressure
+                             launches, whole history kept when it fits        */
+} fwi_exec_mode;
+
+typedef enum {
+    FWI_OP_FORWARD = 0,   /* fwi_forward                                      */
+    FWI_OP_MISFIT = 1,    /* fwi_misfit                                       */
+    FWI_OP_GRADIENT = 2   /* fwi_gradient and fwi_adjoint                     */
+} fwi_op;
+
+typedef struct {
+    int32_t nz, nx;       /* physical nodes, z slow, x fast (>= 5 each)       */
+    int32_t npml;         /* absorbing cells on every side (>= 0)             */
+    int32_t nt;           /* time steps (>= 1)                                */
+    double dz, dx;        /* grid spacing (m)                                 */
+    double dt;            /* time step (s)                                    */
+    double vmax;          /* velocity bound for stability check and damping   */
+    double pml_r;         /* PML target reflection, 0 < R < 1 (e.g. 1e-3)     */
+} fwi_grid;
+
+typedef struct {
+    int32_t nshots;       /* >= 1                                             */
+    int32_t nrec;         /* receivers per shot, >= 1                         */
+    int32_t wavelet_per_shot; /* 0: wavelet [nt]; 1: wavelet [nshots][nt]     */
+    const double *src_xz; /* HOST [nshots][2], (x, z) metres from node (0,0)  */
+    const double *rec_xz; /* HOST [nshots][nrec][2]                           */
+} fwi_acq;
+
+typedef struct {
+    int32_t mode;         /* fwi_exec_mode                                    */
+    int32_t ckpt_every;   /* forward states kept every k steps; 0: ceil(sqrt(nt));
+                             >= nt keeps the whole pressure history            */
+    int32_t tile_z;       /* batched kernels: tile rows 8, 16 or 32; 0: default */
+    int32_t shot_groups;  /* batched kernels: shots split into this many groups
+                             sweeping a tile (1..nshots); 0: default           */
+} fwi_exec;
+
+typedef struct {
+    int32_t Nz, Nx;           /* padded grid                                  */
+    int32_t ckpt_every;       /* k actually used                              */
+    int32_t segments;         /* ceil(nt / k)                                 */
+    int32_t tile_z, shot_groups;
+    int32_t mode;
+    int32_t device;           /* HIP device the plan lives on                 */
+    int64_t pml_cells;        /* cells of the absorbing layer                 */
+    double cfl;               /* vmax dt / min(dx, dz)                        */
+} fwi_plan_info;
+
+typedef struct fwi_plan fwi_plan;
+
+/* Creates a plan on the current HIP device.  Checks the grid (sizes, dt,
+ * stability: vmax dt / min(dx,dz) must not exceed 0.606, the limit of the
+ * fourth-order staggered scheme in 2-D, else FWI_EUNSTABLE) and the
+ * geometry: every source and receiver must have its four bilinear nodes
+ * inside the physical grid, outside the absorbing layer (else FWI_EINVAL).
+ * `exec` may be NULL (batched defaults).  On success *out owns small device
+ * tables; release with fwi_plan_destroy. */
+fwi_status fwi_plan_create(const fwi_grid *grid, const fwi_acq *acq,
+                           const fwi_exec *exec, fwi_plan **out);
+
+/* Releases a plan (NULL is ignored).  Work using it must have finished. */
+void fwi_plan_destroy(fwi_plan *plan);
+
+fwi_status fwi_plan_get_info(const fwi_plan *plan, fwi_plan_info *info);
+
+/* Workspace bytes the call `op` needs with this plan (0 on a bad argument). */
+size_t fwi_workspace_bytes(const fwi_plan *plan, int32_t op);
+
+/* Forward modelling (paper: p = S G for every source): traces [S][nrec][nt]
+ * of the model (m1, m2) in parameterization `param`, wavelet samples f(n dt)
+ * ([nt] or [S][nt] as declared in fwi_acq). */
+fwi_status fwi_forward(fwi_plan *plan, int32_t param, const float *m1, const float *m2,
+                       const float *wavelet, float *traces, void *ws, size_t ws_bytes,
+                       void *stream);
+
+/* Least-squares misfit of the paper's misfit equation: residual = traces -
+ * observed (may be NULL), J[0] = 1/2 sum residual^2 (FP32, fixed-order
+ * reduction: the same inputs give the same bits). */
+fwi_status fwi_misfit(fwi_plan *plan, const float *traces, const float *observed,
+                      float *residual, float *J, void *ws, size_t ws_bytes, void *stream);
+
+/* Misfit and gradient (scheme III): J[0] as fwi_misfit, and g1, g2 = dJ/dm1,
+ * dJ/dm2 per cell (no cell-area factor) at (m1, m2) in parameterization
+ * `param`.  traces may be NULL; if given it receives the modelled data. */
+fwi_status fwi_gradient(fwi_plan *plan, int32_t param, const float *m1, const float *m2,
+                        const float *wavelet, const float *observed, float *J, float *g1,
+                        float *g2, float *traces, void *ws, size_t ws_bytes, void *stream);
+
+/* Adjoint-state gradient for a given adjoint source: g = d<adj_src, p>/dm,
+ * adj_src [S][nrec][nt].  With adj_src = p - q this is the misfit gradient;
+ * any other data-space vector gives the gradient of a user-defined loss. */
+fwi_status fwi_adjoint(fwi_plan *plan, int32_t param, const float *m1, const float *m2,
+                       const float *wavelet, const float *adj_src, float *g1, float *g2,
+                       void *ws, size_t ws_bytes, void *stream);
+
+/* Exact conversion between parameterizations (parameter definitions Ip =
+ * rho Vp, K = rho Vp^2; Table 2 in absolute form), n cells. */
+fwi_status fwi_model_convert(int32_t from_param, int32_t to_param, int64_t n, const float *a1,
+                             const float *a2, float *b1, float *b2, void *stream);
+
+/* Chain rule: (gK, grho) = dJ/dK, dJ/drho at the model (m1, m2) given in
+ * `param` -> (g1, g2) = dJ/dm1, dJ/dm2.  n cells. */
+fwi_status fwi_chain_rule(int32_t param, int64_t n, const float *m1, const float *m2,
+                          const float *gK, const float *grho, float *g1, float *g2,
+                          void *stream);
+
+/* Gradient with respect to the contrasts xi = (m - m0)/m0 of Table 1:
+ * g_xi = m0 * g, elementwise, in place on g (n cells). */
+fwi_status fwi_contrast_scale(int64_t n, const float *m0, float *g, void *stream);
+
+/* Kernel classes of the per-launch timing below. */
+typedef enum {
+    FWI_KC_FWD_STEP = 0,   /* batched forward step (all shots)                 */
+    FWI_KC_ADJ_STEP = 1,   /* batched adjoint step with imaging                */
+    FWI_KC_PLAIN_VEL = 2,  /* plain velocity update (one shot)                 */
+    FWI_KC_PLAIN_PRES = 3, /* plain pressure update (one shot)                 */
+    FWI_KC_PLAIN_ADJ_A = 4,/* plain adjoint velocity half + imaging            */
+    FWI_KC_PLAIN_ADJ_B = 5,/* plain adjoint pressure half                      */
+    FWI_KC_SAMPLE = 6,     /* receiver sampling                                */
+    FWI_KC_INJECT = 7,     /* adjoint-source injection                         */
+    FWI_KC_OTHER = 8,      /* preparation, copies, misfit, finalization        */
+    FWI_KC_COUNT = 9
+} fwi_kernel_class;
+
+typedef struct {
+    int64_t launches[FWI_KC_COUNT];
+    double ms[FWI_KC_COUNT];   /* summed device time between the events
+                                  bracketing each launch                   */
+} fwi_timing;
+
+/* Instrumentation (not needed for results): while enabled, every kernel the
+ * plan launches is bracketed by a pair of HIP events recorded on the
+ * caller's stream, so that per-kernel-class device time can be read back.
+ * Enabling or disabling clears the record. */
+fwi_status fwi_timing_enable(fwi_plan *plan, int32_t enable);
+
+/* Waits for the recorded events and returns the per-class sums since the
+ * last reset; reset != 0 clears the record afterwards. */
+fwi_status fwi_timing_read(fwi_plan *plan, fwi_timing *out, int32_t reset);
+
+/* Waits for `stream` and reports any device error raised by earlier work. */
+fwi_status fwi_sync(void *stream);
+
+const char *fwi_status_str(fwi_status status);
+const char *fwi_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

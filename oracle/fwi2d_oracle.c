@@ -61,6 +61,12 @@ typedef struct {
     double w[4];
 } stencil4;
 
+/* Threads go over shots when there are at least as many shots as threads
+ * or the grid is small, otherwise over grid rows inside each step (same
+ * arithmetic either way). */
+static int inner_parallel = 0;
+static const long kInnerMinCells = 65536;
+
 typedef struct {
     double *vx, *vz, *px, *pz;
 } state_t;
@@ -303,14 +309,17 @@ static void step_forward(const ora_grid *g, const model_t *m, state_t *u,
                          double *p, const stencil4 *src, double q)
 {
     int Nz = m->Nz, Nx = m->Nx;
+#pragma omp parallel for if (inner_parallel)
     for (long c = 0; c < m->N; ++c)
         p[c] = u->px[c] + u->pz[c];
+#pragma omp parallel for if (inner_parallel)
     for (int i = 0; i < Nz; ++i)
         for (int j = 0; j < Nx; ++j) {
             long c = (long)i * Nx + j;
             u->vx[c] = m->ahx[j] * u->vx[c] - m->bthx[j] * m->bx[c] * dxp(p, Nz, Nx, i, j, g->dx);
             u->vz[c] = m->ahz[i] * u->vz[c] - m->bthz[i] * m->bz[c] * dzp(p, Nz, Nx, i, j, g->dz);
         }
+#pragma omp parallel for if (inner_parallel)
     for (int i = 0; i < Nz; ++i)
         for (int j = 0; j < Nx; ++j) {
             long c = (long)i * Nx + j;
@@ -395,7 +404,8 @@ int ora_forward(const ora_grid *g, const ora_acq *a, const double *K,
     stencil4 *src = NULL, *rec = NULL;
     int rc = geometry(g, a, &src, &rec);
     if (rc == 0) {
-#pragma omp parallel for schedule(dynamic, 1)
+        inner_parallel = a->nshots < ora_num_threads() && m.N >= kInnerMinCells;
+#pragma omp parallel for schedule(dynamic, 1) if (!inner_parallel)
         for (int s = 0; s < a->nshots; ++s) {
             state_t u;
             double *p = malloc(sizeof(double) * m.N);
@@ -441,6 +451,7 @@ int ora_forward_states(const ora_grid *g, const ora_acq *a, const double *K,
     double *p = malloc(sizeof(double) * m.N);
     double *Q = malloc(sizeof(double) * g->nt);
     int rc = (state_alloc(&u, m.N) == 0 && p && Q) ? 0 : -2;
+    inner_parallel = m.N >= kInnerMinCells;
     if (rc == 0) {
         cumulative_wavelet(g, wavelet + (a->wavelet_per_shot ? (size_t)shot * g->nt : 0), Q);
         int k = 0;
@@ -508,6 +519,7 @@ static void step_adjoint(const ora_grid *g, const model_t *m, state_t *lam,
     }
 
     /* dpx'/dK = -btx Dx- vx^{n+1/2} + dt Q w_s/(dx dz); dpz'/dK = -btz Dz- vz^{n+1/2} */
+#pragma omp parallel for if (inner_parallel)
     for (int i = 0; i < Nz; ++i)
         for (int j = 0; j < Nx; ++j) {
             long c = (long)i * Nx + j;
@@ -524,12 +536,14 @@ static void step_adjoint(const ora_grid *g, const model_t *m, state_t *lam,
     sens->gQ[n] = gq;
 
     /* T2^T: lambda_v += D+ (beta K mu_p); mu_p <- alpha mu_p */
+#pragma omp parallel for if (inner_parallel)
     for (int i = 0; i < Nz; ++i)
         for (int j = 0; j < Nx; ++j) {
             long c = (long)i * Nx + j;
             tmpx[c] = m->btx[j] * m->K[c] * lam->px[c];
             tmpz[c] = m->btz[i] * m->K[c] * lam->pz[c];
         }
+#pragma omp parallel for if (inner_parallel)
     for (int i = 0; i < Nz; ++i)
         for (int j = 0; j < Nx; ++j) {
             long c = (long)i * Nx + j;
@@ -540,8 +554,10 @@ static void step_adjoint(const ora_grid *g, const model_t *m, state_t *lam,
         }
 
     /* dvx'/dbx = -bthx Dx+ p^n;  dvz'/dbz = -bthz Dz+ p^n */
+#pragma omp parallel for if (inner_parallel)
     for (long c = 0; c < m->N; ++c)
         pn[c] = un->px[c] + un->pz[c];
+#pragma omp parallel for if (inner_parallel)
     for (int i = 0; i < Nz; ++i)
         for (int j = 0; j < Nx; ++j) {
             long c = (long)i * Nx + j;
@@ -551,12 +567,14 @@ static void step_adjoint(const ora_grid *g, const model_t *m, state_t *lam,
 
     /* T1^T: mu_p += Dx-(bthx bx lambda_vx) + Dz-(bthz bz lambda_vz) on both
      * components; lambda_v <- alpha_h lambda_v */
+#pragma omp parallel for if (inner_parallel)
     for (int i = 0; i < Nz; ++i)
         for (int j = 0; j < Nx; ++j) {
             long c = (long)i * Nx + j;
             tmpx[c] = m->bthx[j] * m->bx[c] * lam->vx[c];
             tmpz[c] = m->bthz[i] * m->bz[c] * lam->vz[c];
         }
+#pragma omp parallel for if (inner_parallel)
     for (int i = 0; i < Nz; ++i)
         for (int j = 0; j < Nx; ++j) {
             long c = (long)i * Nx + j;
@@ -564,6 +582,7 @@ static void step_adjoint(const ora_grid *g, const model_t *m, state_t *lam,
             lam->px[c] += t;
             lam->pz[c] += t;
         }
+#pragma omp parallel for if (inner_parallel)
     for (int i = 0; i < Nz; ++i)
         for (int j = 0; j < Nx; ++j) {
             long c = (long)i * Nx + j;
@@ -661,7 +680,8 @@ int ora_adjoint(const ora_grid *g, const ora_acq *a, const double *K,
     }
     if (rc == 0) {
         int fail = 0;
-#pragma omp parallel for schedule(dynamic, 1) reduction(| : fail)
+        inner_parallel = S < ora_num_threads() && N >= kInnerMinCells;
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : fail) if (!inner_parallel)
         for (int s = 0; s < S; ++s) {
             sens_t sens = { sK + (size_t)s * N, sbx + (size_t)s * N, sbz + (size_t)s * N,
                             sQ + (size_t)s * nt };

@@ -1,0 +1,942 @@
+// C ABI of libfwi2d: plans, workspace layout and the time-stepping schedule
+// (forward sweep with checkpoints, then per segment a recompute that stores
+// the pressure history followed by the adjoint sweep).
+#include "../../include/fwi2d.h"
+#include "fwi2d_internal.h"
+
+#include <algorithm>
+#include <cstdarg>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+using namespace fwi;
+
+namespace {
+
+thread_local std::string g_err;
+
+fwi_status fail(fwi_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+fwi_status fail(fwi_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+inline long long align64(long long v) { return (v + 63) / 64 * 64; }
+
+// Stability limit of the fourth-order staggered leapfrog scheme in 2-D:
+// vmax dt sqrt(1/dx^2 + 1/dz^2) (|c1| + |c2|) <= 1.
+double stability_number(const fwi_grid &g)
+{
+    return g.vmax * g.dt * std::sqrt(1.0 / (g.dx * g.dx) + 1.0 / (g.dz * g.dz)) *
+           (9.0 / 8.0 + 1.0 / 24.0);
+}
+
+}  // namespace
+
+struct fwi_plan {
+    fwi_grid grid;
+    int S, nrec, per_shot;
+    int mode, k, nseg, tile_z, groups;
+    int device;
+    Geo geo;
+    long long SS, ST;  // per-shot floats of a state record / a store record
+    // device tables (one allocation)
+    void *dev = nullptr;
+    float *pml = nullptr;
+    int2 *src_ij = nullptr;
+    float4 *src_w = nullptr;
+    long long *rec_idx = nullptr;
+    float4 *rec_w = nullptr;
+    long long *inj_node = nullptr;
+    int *inj_shot = nullptr, *inj_cptr = nullptr, *inj_crec = nullptr;
+    float *inj_cw = nullptr;
+    int inj_nodes = 0;
+    std::vector<int> shot_node_ptr;  // [S+1] node range of each shot
+    std::vector<int2> h_src_ij;
+    std::vector<float4> h_src_w;
+    // per-launch event timing (instrumentation)
+    bool timing = false;
+    struct Mark {
+        int cls;
+        hipEvent_t a, b;
+    };
+    std::vector<Mark> marks;
+    std::vector<hipEvent_t> spare;
+    fwi_timing acc{};
+};
+
+namespace {
+
+hipEvent_t take_event(fwi_plan *p)
+{
+    hipEvent_t e = nullptr;
+    if (!p->spare.empty()) {
+        e = p->spare.back();
+        p->spare.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+        e = nullptr;
+    }
+    return e;
+}
+
+// Brackets the launches issued in its scope with events when timing is on.
+struct Timed {
+    fwi_plan *p;
+    hipStream_t st;
+    int cls;
+    hipEvent_t b = nullptr, e = nullptr;
+    Timed(fwi_plan *p_, hipStream_t st_, int cls_) : p(p_), st(st_), cls(cls_)
+    {
+        if (!p->timing)
+            return;
+        b = take_event(p);
+        e = take_event(p);
+        if (b && e)
+            (void)hipEventRecord(b, st);
+    }
+    ~Timed()
+    {
+        if (!b || !e)
+            return;
+        (void)hipEventRecord(e, st);
+        p->marks.push_back({cls, b, e});
+    }
+};
+
+// Folds the recorded marks into the per-class sums.
+fwi_status collect_marks(fwi_plan *p)
+{
+    for (auto &m : p->marks) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(m.b) != hipSuccess ||
+            hipEventElapsedTime(&ms, m.a, m.b) != hipSuccess)
+            return FWI_EDEVICE;
+        p->acc.launches[m.cls] += 1;
+        p->acc.ms[m.cls] += ms;
+        p->spare.push_back(m.a);
+        p->spare.push_back(m.b);
+    }
+    p->marks.clear();
+    return FWI_OK;
+}
+
+struct Layout {
+    size_t Kphys, rhophys, Kpad, bx, bz, Q;
+    size_t work[2], lam[2];
+    size_t ckpt, store, gpart, traces, resid, partials;
+    size_t total;
+};
+
+int batch_of(const fwi_plan *p) { return p->mode == FWI_EXEC_PLAIN ? 1 : p->S; }
+int groups_of(const fwi_plan *p) { return p->mode == FWI_EXEC_PLAIN ? 1 : p->groups; }
+
+Layout layout(const fwi_plan *p, int op)
+{
+    Layout L{};
+    size_t off = 0;
+    auto take = [&](size_t floats) {
+        size_t o = off;
+        off = align_up(off + floats * sizeof(float), kAlign);
+        return o;
+    };
+    const Geo &g = p->geo;
+    long long nphys = (long long)g.nz * g.nx;
+    long long ntr = (long long)p->S * p->nrec * p->grid.nt;
+    int B = batch_of(p);
+    if (op == FWI_OP_MISFIT) {
+        L.partials = take(misfit_blocks(ntr));
+        L.total = off;
+        return L;
+    }
+    L.Kphys = take(nphys);
+    L.rhophys = take(nphys);
+    L.Kpad = take(g.N);
+    L.bx = take(g.N);
+    L.bz = take(g.N);
+    L.Q = take((size_t)p->S * p->grid.nt);
+    L.work[0] = take((size_t)B * p->SS);
+    L.work[1] = take((size_t)B * p->SS);
+    if (op == FWI_OP_GRADIENT) {
+        L.lam[0] = take((size_t)B * p->SS);
+        L.lam[1] = take((size_t)B * p->SS);
+        L.ckpt = take((size_t)(p->nseg - 1) * B * p->SS);
+        L.store = take((size_t)(p->k + 1) * B * p->ST);
+        L.gpart = take((size_t)groups_of(p) * 3 * g.N);
+        L.traces = take(ntr);
+        L.resid = take(ntr);
+        L.partials = take(misfit_blocks(ntr));
+    }
+    L.total = off;
+    return L;
+}
+
+// Pointers into a workspace for one batch of shots.
+struct State {
+    Fld vx, vz, p, pz;
+};
+
+State state_at(float *base, const fwi_plan *pl)
+{
+    const Geo &g = pl->geo;
+    State s;
+    s.vx = {base, pl->SS};
+    s.vz = {base + g.N, pl->SS};
+    s.p = {base + 2 * g.N, pl->SS};
+    s.pz = {base + 3 * g.N, pl->SS};
+    return s;
+}
+
+struct Ctx {
+    fwi_plan *pl;
+    hipStream_t st;
+    char *ws;
+    Layout L;
+    Pml t;
+    Mdl m;
+    float *f(size_t off) const { return (float *)(ws + off); }
+};
+
+Pml pml_tables(const fwi_plan *p)
+{
+    const Geo &g = p->geo;
+    const float *b = p->pml;
+    Pml t;
+    t.ax = b;
+    t.bx = b + g.Nx;
+    t.ahx = b + 2 * g.Nx;
+    t.bhx = b + 3 * g.Nx;
+    const float *z = b + 4 * g.Nx;
+    t.az = z;
+    t.bz = z + g.Nz;
+    t.ahz = z + 2 * g.Nz;
+    t.bhz = z + 3 * g.Nz;
+    return t;
+}
+
+// Copies the pressure and its absorbing-layer split of `nb` shots.
+__global__ void k_copy_p(Fld dp, Fld dpz, Fld sp, Fld spz, long long N, long long Npml, int nb)
+{
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long per = N + Npml;
+    long long total = per * nb;
+    long long stride = (long long)gridDim.x * blockDim.x;
+    for (; i < total; i += stride) {
+        int s = (int)(i / per);
+        long long r = i - (long long)s * per;
+        if (r < N)
+            dp.shot(s)[r] = sp.shot(s)[r];
+        else
+            dpz.shot(s)[r - N] = spz.shot(s)[r - N];
+    }
+}
+
+void copy_p(const Ctx &c, Fld dp, Fld dpz, Fld sp, Fld spz, int nb)
+{
+    const Geo &g = c.pl->geo;
+    long long total = (g.N + g.Npml) * nb;
+    unsigned blocks = (unsigned)std::min<long long>((total + 255) / 256, 8192);
+    Timed tm(c.pl, c.st, FWI_KC_OTHER);
+    hipLaunchKernelGGL(k_copy_p, dim3(blocks), dim3(256), 0, c.st, dp, dpz, sp, spz, g.N, g.Npml,
+                       nb);
+}
+
+// Source / receiver tables of shots [s0, s0 + nb).
+Src src_of(const Ctx &c, int s0)
+{
+    Src s;
+    s.ij = c.pl->src_ij + s0;
+    s.w = c.pl->src_w + s0;
+    s.Q = c.f(c.L.Q) + (size_t)s0 * c.pl->grid.nt;
+    s.nt = c.pl->grid.nt;
+    return s;
+}
+
+Rec rec_of(const Ctx &c, int s0)
+{
+    Rec r;
+    r.idx = c.pl->rec_idx + (size_t)s0 * c.pl->nrec;
+    r.w = c.pl->rec_w + (size_t)s0 * c.pl->nrec;
+    r.nrec = c.pl->nrec;
+    return r;
+}
+
+Inj inj_of(const Ctx &c, int s0, int nb)
+{
+    const fwi_plan *p = c.pl;
+    int a = p->shot_node_ptr[s0], b = p->shot_node_ptr[s0 + nb];
+    Inj in;
+    in.node = p->inj_node + a;
+    in.shot = p->inj_shot + a;
+    in.cptr = p->inj_cptr + a;
+    in.crec = p->inj_crec;
+    in.cw = p->inj_cw;
+    in.nnodes = b - a;
+    return in;
+}
+
+// One forward step n -> n+1 for shots [s0, s0+nb) from `in` to `out`.
+void step_fwd(const Ctx &c, int s0, int nb, const State &in, const State &out, int n)
+{
+    const fwi_plan *p = c.pl;
+    const Geo &g = p->geo;
+    Src src = src_of(c, s0);
+    if (p->mode == FWI_EXEC_PLAIN) {
+        {
+            Timed tm(c.pl, c.st, FWI_KC_PLAIN_VEL);
+            launch_plain_vel(g, c.t, c.m, in.vx.p, in.vz.p, out.vx.p, out.vz.p, in.p.p, c.st);
+        }
+        Timed tm(c.pl, c.st, FWI_KC_PLAIN_PRES);
+        launch_plain_pres(g, c.t, c.m, out.vx.p, out.vz.p, in.p.p, in.pz.p, out.p.p, out.pz.p,
+                          p->h_src_ij[s0], p->h_src_w[s0], src.Q, n, c.st);
+    } else {
+        FwdStep a{in.vx, in.vz, in.p, in.pz, out.vx, out.vz, out.p, out.pz, n};
+        Timed tm(c.pl, c.st, FWI_KC_FWD_STEP);
+        launch_fused_fwd(g, c.t, c.m, src, nb, p->groups, p->tile_z, a, c.st);
+    }
+}
+
+// One adjoint step n for shots [s0, s0+nb): injects R^T r^n into `in`, then
+// writes the adjoint state of step n into `out` and accumulates the
+// sensitivities into gpart.
+void step_adj(const Ctx &c, int s0, int nb, const State &in, const State &out, Fld pn, Fld pzn,
+              Fld pn1, Fld pzn1, const float *resid, float *gpart, int n)
+{
+    const fwi_plan *p = c.pl;
+    const Geo &g = p->geo;
+    {
+        Timed tm(c.pl, c.st, FWI_KC_INJECT);
+        launch_inject(g, inj_of(c, s0, nb), resid, p->nrec, p->grid.nt, n, in.p, s0, c.st);
+    }
+    if (p->mode == FWI_EXEC_PLAIN) {
+        {
+            Timed tm(c.pl, c.st, FWI_KC_PLAIN_ADJ_A);
+            launch_plain_adj_a(g, c.t, c.m, in.vx.p, in.vz.p, out.vx.p, out.vz.p, in.p.p,
+                               in.pz.p, pn.p, pzn.p, pn1.p, pzn1.p, gpart, gpart + g.N,
+                               gpart + 2 * g.N, c.st);
+        }
+        Timed tm(c.pl, c.st, FWI_KC_PLAIN_ADJ_B);
+        launch_plain_adj_b(g, c.t, c.m, out.vx.p, out.vz.p, in.p.p, in.pz.p, out.p.p, out.pz.p,
+                           c.st);
+    } else {
+        AdjStep a{in.vx, in.vz, in.p, in.pz, out.vx, out.vz, out.p, out.pz,
+                  pn, pzn, pn1, pzn1, gpart, n};
+        Timed tm(c.pl, c.st, FWI_KC_ADJ_STEP);
+        launch_fused_adj(g, c.t, c.m, src_of(c, s0), nb, p->groups, p->tile_z, a, c.st);
+    }
+}
+
+void zero_state(const Ctx &c, float *base, int nb)
+{
+    Timed tm(c.pl, c.st, FWI_KC_OTHER);
+    launch_fill(base, (long long)nb * c.pl->SS, 0.0f, c.st);
+}
+
+// Forward sweep over all steps for shots [s0, s0+nb).  With `keep`, the
+// states at multiples of k go to checkpoint slots and the pressure of the
+// last segment to the store (slot m holds p at step nlast + m).  `traces`
+// (may be null) receives the receiver samples of these shots.
+void sweep_forward(const Ctx &c, int s0, int nb, bool keep, float *traces)
+{
+    const fwi_plan *p = c.pl;
+    const int nt = p->grid.nt, k = p->k;
+    const int nlast = (p->nseg - 1) * k;
+    State w[2] = {state_at(c.f(c.L.work[0]), p), state_at(c.f(c.L.work[1]), p)};
+    zero_state(c, c.f(c.L.work[0]), nb);
+    State cur = w[0];
+    int cw = 0;  // work buffer holding cur's velocities (-1: a checkpoint slot)
+    Rec rec = rec_of(c, s0);
+    for (int n = 0; n < nt; ++n) {
+        int n1 = n + 1;
+        int nw = cw == 0 ? 1 : 0;
+        State out = w[nw];
+        int next_cw = nw;
+        if (keep && n >= nlast) {
+            float *slot0 = c.f(c.L.store);
+            if (n == nlast) {
+                Fld sp0 = {slot0, p->ST}, spz0 = {slot0 + p->geo.N, p->ST};
+                copy_p(c, sp0, spz0, cur.p, cur.pz, nb);
+            }
+            float *slot = slot0 + (size_t)(n1 - nlast) * nb * p->ST;
+            out.p = {slot, p->ST};
+            out.pz = {slot + p->geo.N, p->ST};
+        } else if (keep && n1 % k == 0) {
+            out = state_at(c.f(c.L.ckpt) + (size_t)(n1 / k - 1) * nb * p->SS, p);
+            next_cw = -1;
+        }
+        step_fwd(c, s0, nb, cur, out, n);
+        if (traces) {
+            Timed tm(c.pl, c.st, FWI_KC_SAMPLE);
+            launch_sample(p->geo, out.p, out.pz, rec, nb, traces, nt, n, c.st);
+        }
+        cur = out;
+        cw = next_cw;
+    }
+}
+
+// Backward sweep for shots [s0, s0+nb) after sweep_forward(keep = true).
+void sweep_backward(const Ctx &c, int s0, int nb, const float *resid, float *gpart)
+{
+    const fwi_plan *p = c.pl;
+    const Geo &g = p->geo;
+    const int nt = p->grid.nt, k = p->k;
+    float *store = c.f(c.L.store);
+    auto slot = [&](int m) {
+        float *b = store + (size_t)m * nb * p->ST;
+        return std::make_pair(Fld{b, p->ST}, Fld{b + g.N, p->ST});
+    };
+    State lam[2] = {state_at(c.f(c.L.lam[0]), p), state_at(c.f(c.L.lam[1]), p)};
+    zero_state(c, c.f(c.L.lam[0]), nb);
+    int li = 0;
+    for (int sg = p->nseg - 1; sg >= 0; --sg) {
+        int n0 = sg * k, n1 = std::min(n0 + k, nt);
+        if (sg != p->nseg - 1) {
+            // recompute the segment from its checkpoint, keeping the pressure
+            State w[2] = {state_at(c.f(c.L.work[0]), p), state_at(c.f(c.L.work[1]), p)};
+            State cur;
+            int cw;
+            if (n0 == 0) {
+                zero_state(c, c.f(c.L.work[0]), nb);
+                cur = w[0];
+                cw = 0;
+            } else {
+                cur = state_at(c.f(c.L.ckpt) + (size_t)(n0 / k - 1) * nb * p->SS, p);
+                cw = -1;
+            }
+            auto s0p = slot(0);
+            copy_p(c, s0p.first, s0p.second, cur.p, cur.pz, nb);
+            for (int n = n0; n < n1; ++n) {
+                int nw = cw == 0 ? 1 : 0;
+                State out = w[nw];
+                auto sl = slot(n + 1 - n0);
+                out.p = sl.first;
+                out.pz = sl.second;
+                step_fwd(c, s0, nb, cur, out, n);
+                cur = out;
+                cw = nw;
+            }
+        }
+        for (int n = n1 - 1; n >= n0; --n) {
+            auto a = slot(n - n0), b = slot(n + 1 - n0);
+            step_adj(c, s0, nb, lam[li], lam[li ^ 1], a.first, a.second, b.first, b.second, resid,
+                     gpart, n);
+            li ^= 1;
+        }
+    }
+}
+
+fwi_status check_call(const fwi_plan *p, void *ws, size_t ws_bytes, int op)
+{
+    if (!p)
+        return fail(FWI_EINVAL, "plan is NULL");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != p->device)
+        return fail(FWI_ESTATE, "current device %d differs from the plan's device %d", dev,
+                    p->device);
+    size_t need = layout(p, op).total;
+    if (need > 0) {
+        if (!ws)
+            return fail(FWI_EWORKSPACE, "workspace is NULL (needs %zu bytes)", need);
+        if ((uintptr_t)ws % kAlign)
+            return fail(FWI_EWORKSPACE, "workspace not %zu-byte aligned", kAlign);
+        if (ws_bytes < need)
+            return fail(FWI_EWORKSPACE, "workspace of %zu bytes, needs %zu", ws_bytes, need);
+    }
+    return FWI_OK;
+}
+
+fwi_status launched(const char *what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return fail(FWI_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+    return FWI_OK;
+}
+
+bool valid_param(int p) { return p >= FWI_K_RHO && p <= FWI_INVK_INVRHO; }
+
+Ctx make_ctx(fwi_plan *p, void *ws, void *stream, int op)
+{
+    Ctx c;
+    c.pl = p;
+    c.st = (hipStream_t)stream;
+    c.ws = (char *)ws;
+    c.L = layout(p, op);
+    c.t = pml_tables(p);
+    c.m.K = c.f(c.L.Kpad);
+    c.m.bx = c.f(c.L.bx);
+    c.m.bz = c.f(c.L.bz);
+    return c;
+}
+
+void prepare(const Ctx &c, int param, const float *m1, const float *m2, const float *wavelet)
+{
+    const fwi_plan *p = c.pl;
+    Timed tm(c.pl, c.st, FWI_KC_OTHER);
+    launch_prep_model(p->geo, param, m1, m2, c.f(c.L.Kphys), c.f(c.L.rhophys), c.f(c.L.Kpad),
+                      c.f(c.L.bx), c.f(c.L.bz), c.st);
+    launch_cumulative_wavelet(wavelet, p->per_shot, p->S, p->grid.nt, (float)p->grid.dt,
+                              c.f(c.L.Q), c.st);
+}
+
+// Gradient core: forward (traces), residual provider, backward, finalize.
+// `observed` given: misfit gradient (J written); else adj_src is the
+// adjoint source.
+fwi_status run_gradient(fwi_plan *p, int param, const float *m1, const float *m2,
+                        const float *wavelet, const float *observed, const float *adj_src,
+                        float *J, float *g1, float *g2, float *traces, void *ws, void *stream)
+{
+    Ctx c = make_ctx(p, ws, stream, FWI_OP_GRADIENT);
+    const Geo &g = p->geo;
+    prepare(c, param, m1, m2, wavelet);
+    float *gpart = c.f(c.L.gpart);
+    int G = groups_of(p);
+    {
+        Timed tm(p, c.st, FWI_KC_OTHER);
+        launch_fill(gpart, (long long)G * 3 * g.N, 0.0f, c.st);
+    }
+    float *tr = traces ? traces : c.f(c.L.traces);
+    long long per_shot = (long long)p->nrec * p->grid.nt;
+    long long ntr = per_shot * p->S;
+    float *resid = c.f(c.L.resid);
+    float *partials = c.f(c.L.partials);
+    if (p->mode == FWI_EXEC_PLAIN) {
+        for (int s = 0; s < p->S; ++s) {
+            float *trs = tr + s * per_shot;
+            const float *res = adj_src;
+            sweep_forward(c, s, 1, true, observed ? trs : nullptr);
+            if (observed) {
+                Timed tm(p, c.st, FWI_KC_OTHER);
+                launch_misfit(trs, observed + s * per_shot, resid + s * per_shot, per_shot,
+                              partials, misfit_blocks(per_shot), J, c.st);
+                res = resid;
+            }
+            sweep_backward(c, s, 1, res, gpart);
+        }
+        if (observed) {
+            Timed tm(p, c.st, FWI_KC_OTHER);
+            launch_misfit(tr, observed, nullptr, ntr, partials, misfit_blocks(ntr), J, c.st);
+        }
+    } else {
+        sweep_forward(c, 0, p->S, true, observed ? tr : nullptr);
+        const float *res = adj_src;
+        if (observed) {
+            Timed tm(p, c.st, FWI_KC_OTHER);
+            launch_misfit(tr, observed, resid, ntr, partials, misfit_blocks(ntr), J, c.st);
+            res = resid;
+        }
+        sweep_backward(c, 0, p->S, res, gpart);
+    }
+    {
+        Timed tm(p, c.st, FWI_KC_OTHER);
+        launch_finalize(g, param, m1, m2, c.m.bx, c.m.bz, gpart, G, g1, g2, c.st);
+    }
+    return launched("gradient");
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ C ABI
+
+extern "C" {
+
+const char *fwi_status_str(fwi_status s)
+{
+    switch (s) {
+    case FWI_OK: return "ok";
+    case FWI_EINVAL: return "invalid argument";
+    case FWI_ENOMEM: return "out of memory";
+    case FWI_EDEVICE: return "device error";
+    case FWI_EUNSTABLE: return "time step above the stability limit";
+    case FWI_ENONFINITE: return "non-finite value";
+    case FWI_ESTATE: return "bad state";
+    case FWI_EWORKSPACE: return "bad workspace";
+    }
+    return "unknown status";
+}
+
+const char *fwi_last_error(void) { return g_err.c_str(); }
+
+fwi_status fwi_plan_create(const fwi_grid *grid, const fwi_acq *acq, const fwi_exec *exec,
+                           fwi_plan **out)
+{
+    if (!grid || !acq || !out)
+        return fail(FWI_EINVAL, "NULL argument");
+    *out = nullptr;
+    const fwi_grid &G = *grid;
+    if (G.nz < 5 || G.nx < 5 || G.npml < 0 || G.nt < 1)
+        return fail(FWI_EINVAL, "grid sizes nz=%d nx=%d npml=%d nt=%d out of range", G.nz, G.nx,
+                    G.npml, G.nt);
+    if (!(G.dx > 0) || !(G.dz > 0) || !(G.dt > 0) || !(G.vmax > 0) || !std::isfinite(G.dx) ||
+        !std::isfinite(G.dz) || !std::isfinite(G.dt) || !std::isfinite(G.vmax))
+        return fail(FWI_EINVAL, "dx, dz, dt and vmax must be positive and finite");
+    if (G.npml > 0 && !(G.pml_r > 0 && G.pml_r < 1))
+        return fail(FWI_EINVAL, "pml_r must lie in (0, 1)");
+    long long Nz = G.nz + 2LL * G.npml, Nx = G.nx + 2LL * G.npml;
+    if (Nz * Nx > (1LL << 31) - 1)
+        return fail(FWI_EINVAL, "padded grid too large");
+    double sn = stability_number(G);
+    if (sn > 1.0)
+        return fail(FWI_EUNSTABLE, "vmax dt sqrt(1/dx^2+1/dz^2)(9/8+1/24) = %.4f > 1", sn);
+    if (acq->nshots < 1 || acq->nrec < 1 || !acq->src_xz || !acq->rec_xz)
+        return fail(FWI_EINVAL, "need at least one shot and one receiver with positions");
+    fwi_exec ex{FWI_EXEC_BATCHED, 0, 0, 0};
+    if (exec)
+        ex = *exec;
+    if (ex.mode != FWI_EXEC_BATCHED && ex.mode != FWI_EXEC_PLAIN)
+        return fail(FWI_EINVAL, "unknown exec mode %d", ex.mode);
+    if (ex.tile_z != 0 && !fused_tile_supported(ex.tile_z))
+        return fail(FWI_EINVAL, "tile_z %d not supported (8, 16 or 32)", ex.tile_z);
+    if (ex.shot_groups < 0 || ex.shot_groups > acq->nshots || ex.ckpt_every < 0)
+        return fail(FWI_EINVAL, "shot_groups or ckpt_every out of range");
+
+    fwi_plan *p = new fwi_plan();
+    p->grid = G;
+    p->S = acq->nshots;
+    p->nrec = acq->nrec;
+    p->per_shot = acq->wavelet_per_shot ? 1 : 0;
+    p->mode = ex.mode;
+    Geo &g = p->geo;
+    g.Nz = (int)Nz;
+    g.Nx = (int)Nx;
+    g.npml = G.npml;
+    g.nz = G.nz;
+    g.nx = G.nx;
+    g.rdx = (float)(1.0 / G.dx);
+    g.rdz = (float)(1.0 / G.dz);
+    g.dt = (float)G.dt;
+    g.N = Nz * Nx;
+    g.Npml = 2LL * G.npml * Nx + (Nz - 2LL * G.npml) * 2 * G.npml;
+    p->SS = align64(3 * g.N + g.Npml);
+    p->ST = align64(g.N + g.Npml);
+    int k = ex.ckpt_every > 0 ? ex.ckpt_every : (int)std::ceil(std::sqrt((double)G.nt));
+    if (p->mode == FWI_EXEC_PLAIN && ex.ckpt_every == 0) {
+        // plain: keep the whole history of one shot when it takes <= 64 GiB
+        double bytes = (double)(G.nt + 1) * p->ST * sizeof(float);
+        if (bytes <= 64.0 * (1ull << 30))
+            k = G.nt;
+    }
+    p->k = std::max(1, std::min(k, G.nt));
+    p->nseg = (G.nt + p->k - 1) / p->k;
+    p->tile_z = ex.tile_z ? ex.tile_z : 16;
+    int ntiles = (int)(((Nx + 63) / 64) * ((Nz + p->tile_z - 1) / p->tile_z));
+    int groups = ex.shot_groups;
+    if (groups == 0)
+        groups = std::max(1, std::min(p->S, (2048 + ntiles - 1) / ntiles));
+    p->groups = groups;
+
+    // geometry: bilinear cell and weights of every source and receiver
+    const int S = p->S, nr = p->nrec;
+    std::vector<long long> rec_idx((size_t)S * nr);
+    std::vector<float4> rec_w((size_t)S * nr);
+    p->h_src_ij.resize(S);
+    p->h_src_w.resize(S);
+    auto locate = [&](double x, double z, int &i, int &j, double w[4]) -> bool {
+        double fx = x / G.dx, fz = z / G.dz;
+        if (!std::isfinite(fx) || !std::isfinite(fz))
+            return false;
+        double jf = std::floor(fx), iff = std::floor(fz);
+        if (iff < 0 || jf < 0 || iff > G.nz - 2 || jf > G.nx - 2)
+            return false;
+        double tx = fx - jf, tz = fz - iff;
+        i = (int)iff + G.npml;
+        j = (int)jf + G.npml;
+        w[0] = (1 - tx) * (1 - tz);
+        w[1] = tx * (1 - tz);
+        w[2] = (1 - tx) * tz;
+        w[3] = tx * tz;
+        return true;
+    };
+    const double h2 = G.dx * G.dz;
+    for (int s = 0; s < S; ++s) {
+        int i, j;
+        double w[4];
+        if (!locate(acq->src_xz[2 * s], acq->src_xz[2 * s + 1], i, j, w)) {
+            delete p;
+            return fail(FWI_EINVAL, "source %d at (%g, %g) m is not inside the physical grid", s,
+                        acq->src_xz[2 * s], acq->src_xz[2 * s + 1]);
+        }
+        p->h_src_ij[s] = make_int2(i, j);
+        p->h_src_w[s] = make_float4((float)(w[0] / h2), (float)(w[1] / h2), (float)(w[2] / h2),
+                                    (float)(w[3] / h2));
+        for (int r = 0; r < nr; ++r) {
+            const double *xz = acq->rec_xz + 2 * ((size_t)s * nr + r);
+            if (!locate(xz[0], xz[1], i, j, w)) {
+                delete p;
+                return fail(FWI_EINVAL, "receiver %d of shot %d at (%g, %g) m is not inside the "
+                            "physical grid", r, s, xz[0], xz[1]);
+            }
+            rec_idx[(size_t)s * nr + r] = (long long)i * g.Nx + j;
+            rec_w[(size_t)s * nr + r] = make_float4((float)w[0], (float)w[1], (float)w[2],
+                                                    (float)w[3]);
+        }
+    }
+    // adjoint injection: per shot, the nodes touched by receivers (ascending
+    // node) with their (receiver, weight) contributions in receiver order
+    std::vector<long long> inj_node;
+    std::vector<int> inj_shot, inj_cptr, inj_crec;
+    std::vector<float> inj_cw;
+    p->shot_node_ptr.assign(S + 1, 0);
+    for (int s = 0; s < S; ++s) {
+        std::map<long long, std::vector<std::pair<int, float>>> nodes;
+        for (int r = 0; r < nr; ++r) {
+            long long c = rec_idx[(size_t)s * nr + r];
+            float4 w = rec_w[(size_t)s * nr + r];
+            long long cs[4] = {c, c + 1, c + g.Nx, c + g.Nx + 1};
+            float ws[4] = {w.x, w.y, w.z, w.w};
+            for (int q = 0; q < 4; ++q)
+                if (ws[q] != 0.0f)
+                    nodes[cs[q]].push_back({r, ws[q]});
+        }
+        for (auto &kv : nodes) {
+            inj_node.push_back(kv.first);
+            inj_shot.push_back(s);
+            inj_cptr.push_back((int)inj_crec.size());
+            for (auto &rw : kv.second) {
+                inj_crec.push_back(rw.first);
+                inj_cw.push_back(rw.second);
+            }
+        }
+        p->shot_node_ptr[s + 1] = (int)inj_node.size();
+    }
+    inj_cptr.push_back((int)inj_crec.size());
+    p->inj_nodes = (int)inj_node.size();
+
+    if (hipGetDevice(&p->device) != hipSuccess) {
+        delete p;
+        return fail(FWI_EDEVICE, "no HIP device");
+    }
+    // one device allocation for all tables
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + std::max<size_t>(bytes, 1), kAlign);
+        return o;
+    };
+    size_t o_pml = take(sizeof(float) * (4 * g.Nx + 4 * g.Nz));
+    size_t o_sij = take(sizeof(int2) * S), o_sw = take(sizeof(float4) * S);
+    size_t o_ri = take(sizeof(long long) * rec_idx.size()), o_rw = take(sizeof(float4) * rec_w.size());
+    size_t o_in = take(sizeof(long long) * inj_node.size());
+    size_t o_is = take(sizeof(int) * inj_shot.size());
+    size_t o_ip = take(sizeof(int) * inj_cptr.size());
+    size_t o_ir = take(sizeof(int) * inj_crec.size());
+    size_t o_iw = take(sizeof(float) * inj_cw.size());
+    if (hipMalloc(&p->dev, off) != hipSuccess) {
+        (void)hipGetLastError();
+        delete p;
+        return fail(FWI_ENOMEM, "device allocation of %zu bytes for plan tables failed", off);
+    }
+    char *d = (char *)p->dev;
+    p->pml = (float *)(d + o_pml);
+    p->src_ij = (int2 *)(d + o_sij);
+    p->src_w = (float4 *)(d + o_sw);
+    p->rec_idx = (long long *)(d + o_ri);
+    p->rec_w = (float4 *)(d + o_rw);
+    p->inj_node = (long long *)(d + o_in);
+    p->inj_shot = (int *)(d + o_is);
+    p->inj_cptr = (int *)(d + o_ip);
+    p->inj_crec = (int *)(d + o_ir);
+    p->inj_cw = (float *)(d + o_iw);
+    bool ok = true;
+    auto up = [&](void *dst, const void *src, size_t bytes) {
+        if (bytes && hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) != hipSuccess)
+            ok = false;
+    };
+    up(p->src_ij, p->h_src_ij.data(), sizeof(int2) * S);
+    up(p->src_w, p->h_src_w.data(), sizeof(float4) * S);
+    up(p->rec_idx, rec_idx.data(), sizeof(long long) * rec_idx.size());
+    up(p->rec_w, rec_w.data(), sizeof(float4) * rec_w.size());
+    up(p->inj_node, inj_node.data(), sizeof(long long) * inj_node.size());
+    up(p->inj_shot, inj_shot.data(), sizeof(int) * inj_shot.size());
+    up(p->inj_cptr, inj_cptr.data(), sizeof(int) * inj_cptr.size());
+    up(p->inj_crec, inj_crec.data(), sizeof(int) * inj_crec.size());
+    up(p->inj_cw, inj_cw.data(), sizeof(float) * inj_cw.size());
+    launch_pml_tables(g, G.vmax, G.npml > 0 ? G.pml_r : 0.5, G.dx, G.dz, G.dt, p->pml, nullptr);
+    if (!ok || hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+        (void)hipFree(p->dev);
+        delete p;
+        return fail(FWI_EDEVICE, "uploading plan tables failed");
+    }
+    *out = p;
+    return FWI_OK;
+}
+
+void fwi_plan_destroy(fwi_plan *p)
+{
+    if (!p)
+        return;
+    (void)collect_marks(p);
+    for (hipEvent_t e : p->spare)
+        (void)hipEventDestroy(e);
+    if (p->dev)
+        (void)hipFree(p->dev);
+    delete p;
+}
+
+fwi_status fwi_plan_get_info(const fwi_plan *p, fwi_plan_info *info)
+{
+    if (!p || !info)
+        return fail(FWI_EINVAL, "NULL argument");
+    info->Nz = p->geo.Nz;
+    info->Nx = p->geo.Nx;
+    info->ckpt_every = p->k;
+    info->segments = p->nseg;
+    info->tile_z = p->tile_z;
+    info->shot_groups = groups_of(p);
+    info->mode = p->mode;
+    info->device = p->device;
+    info->pml_cells = p->geo.Npml;
+    info->cfl = p->grid.vmax * p->grid.dt / std::min(p->grid.dx, p->grid.dz);
+    return FWI_OK;
+}
+
+size_t fwi_workspace_bytes(const fwi_plan *p, int32_t op)
+{
+    if (!p || op < FWI_OP_FORWARD || op > FWI_OP_GRADIENT)
+        return 0;
+    return layout(p, op).total;
+}
+
+fwi_status fwi_forward(fwi_plan *p, int32_t param, const float *m1, const float *m2,
+                       const float *wavelet, float *traces, void *ws, size_t ws_bytes,
+                       void *stream)
+{
+    fwi_status st = check_call(p, ws, ws_bytes, FWI_OP_FORWARD);
+    if (st != FWI_OK)
+        return st;
+    if (!valid_param(param) || !m1 || !m2 || !wavelet || !traces)
+        return fail(FWI_EINVAL, "bad parameterization or NULL array");
+    Ctx c = make_ctx(p, ws, stream, FWI_OP_FORWARD);
+    prepare(c, param, m1, m2, wavelet);
+    long long per_shot = (long long)p->nrec * p->grid.nt;
+    if (p->mode == FWI_EXEC_PLAIN) {
+        for (int s = 0; s < p->S; ++s)
+            sweep_forward(c, s, 1, false, traces + s * per_shot);
+    } else {
+        sweep_forward(c, 0, p->S, false, traces);
+    }
+    return launched("forward");
+}
+
+fwi_status fwi_misfit(fwi_plan *p, const float *traces, const float *observed, float *residual,
+                      float *J, void *ws, size_t ws_bytes, void *stream)
+{
+    fwi_status st = check_call(p, ws, ws_bytes, FWI_OP_MISFIT);
+    if (st != FWI_OK)
+        return st;
+    if (!traces || !observed || !J)
+        return fail(FWI_EINVAL, "NULL array");
+    long long n = (long long)p->S * p->nrec * p->grid.nt;
+    Layout L = layout(p, FWI_OP_MISFIT);
+    {
+        Timed tm(p, (hipStream_t)stream, FWI_KC_OTHER);
+        launch_misfit(traces, observed, residual, n, (float *)((char *)ws + L.partials),
+                      misfit_blocks(n), J, (hipStream_t)stream);
+    }
+    return launched("misfit");
+}
+
+fwi_status fwi_gradient(fwi_plan *p, int32_t param, const float *m1, const float *m2,
+                        const float *wavelet, const float *observed, float *J, float *g1,
+                        float *g2, float *traces, void *ws, size_t ws_bytes, void *stream)
+{
+    fwi_status st = check_call(p, ws, ws_bytes, FWI_OP_GRADIENT);
+    if (st != FWI_OK)
+        return st;
+    if (!valid_param(param) || !m1 || !m2 || !wavelet || !observed || !J || !g1 || !g2)
+        return fail(FWI_EINVAL, "bad parameterization or NULL array");
+    return run_gradient(p, param, m1, m2, wavelet, observed, nullptr, J, g1, g2, traces, ws,
+                        stream);
+}
+
+fwi_status fwi_adjoint(fwi_plan *p, int32_t param, const float *m1, const float *m2,
+                       const float *wavelet, const float *adj_src, float *g1, float *g2,
+                       void *ws, size_t ws_bytes, void *stream)
+{
+    fwi_status st = check_call(p, ws, ws_bytes, FWI_OP_GRADIENT);
+    if (st != FWI_OK)
+        return st;
+    if (!valid_param(param) || !m1 || !m2 || !wavelet || !adj_src || !g1 || !g2)
+        return fail(FWI_EINVAL, "bad parameterization or NULL array");
+    return run_gradient(p, param, m1, m2, wavelet, nullptr, adj_src, nullptr, g1, g2, nullptr,
+                        ws, stream);
+}
+
+fwi_status fwi_model_convert(int32_t from, int32_t to, int64_t n, const float *a1,
+                             const float *a2, float *b1, float *b2, void *stream)
+{
+    if (!valid_param(from) || !valid_param(to) || n < 0 || (n > 0 && (!a1 || !a2 || !b1 || !b2)))
+        return fail(FWI_EINVAL, "bad parameterization, size or NULL array");
+    if (n == 0)
+        return FWI_OK;
+    launch_convert(from, to, n, a1, a2, b1, b2, (hipStream_t)stream);
+    return launched("model_convert");
+}
+
+fwi_status fwi_chain_rule(int32_t param, int64_t n, const float *m1, const float *m2,
+                          const float *gK, const float *grho, float *g1, float *g2, void *stream)
+{
+    if (!valid_param(param) || n < 0 ||
+        (n > 0 && (!m1 || !m2 || !gK || !grho || !g1 || !g2)))
+        return fail(FWI_EINVAL, "bad parameterization, size or NULL array");
+    if (n == 0)
+        return FWI_OK;
+    launch_chain_rule(param, n, m1, m2, gK, grho, g1, g2, (hipStream_t)stream);
+    return launched("chain_rule");
+}
+
+fwi_status fwi_contrast_scale(int64_t n, const float *m0, float *g, void *stream)
+{
+    if (n < 0 || (n > 0 && (!m0 || !g)))
+        return fail(FWI_EINVAL, "bad size or NULL array");
+    if (n == 0)
+        return FWI_OK;
+    launch_contrast_scale(n, m0, g, (hipStream_t)stream);
+    return launched("contrast_scale");
+}
+
+fwi_status fwi_timing_enable(fwi_plan *p, int32_t enable)
+{
+    if (!p)
+        return fail(FWI_EINVAL, "plan is NULL");
+    if (collect_marks(p) != FWI_OK)
+        return fail(FWI_EDEVICE, "waiting for timing events failed");
+    p->timing = enable != 0;
+    p->acc = fwi_timing{};
+    return FWI_OK;
+}
+
+fwi_status fwi_timing_read(fwi_plan *p, fwi_timing *out, int32_t reset)
+{
+    if (!p || !out)
+        return fail(FWI_EINVAL, "NULL argument");
+    if (collect_marks(p) != FWI_OK)
+        return fail(FWI_EDEVICE, "waiting for timing events failed");
+    *out = p->acc;
+    if (reset)
+        p->acc = fwi_timing{};
+    return FWI_OK;
+}
+
+fwi_status fwi_sync(void *stream)
+{
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e == hipSuccess)
+        e = hipGetLastError();
+    if (e != hipSuccess)
+        return fail(FWI_EDEVICE, "%s", hipGetErrorString(e));
+    return FWI_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,157 @@
+// Internal declarations shared by the HIP translation units of libfwi2d.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace fwi {
+
+// Fourth-order staggered first-derivative weights.
+constexpr float kC1 = 9.0f / 8.0f;
+constexpr float kC2 = -1.0f / 24.0f;
+
+// A wavefield component for a batch of shots: shot s lives at p + s * ss.
+struct Fld {
+    float *p;
+    long long ss;
+    __host__ __device__ float *shot(int s) const { return p + (long long)s * ss; }
+};
+
+// Padded-grid geometry and time step.
+struct Geo {
+    int Nz, Nx;      // padded nodes
+    int npml;        // absorbing cells per side
+    int nz, nx;      // physical nodes
+    float rdx, rdz;  // 1/dx, 1/dz
+    float dt;
+    long long N;     // Nz * Nx
+    long long Npml;  // cells of the absorbing layer (compact aux storage)
+};
+
+__host__ __device__ inline bool in_pml(const Geo &g, int i, int j)
+{
+    return i < g.npml || i >= g.Nz - g.npml || j < g.npml || j >= g.Nx - g.npml;
+}
+
+// Index of an absorbing-layer cell in the compact aux arrays: the top and
+// bottom strips (full rows) first, then the left/right pieces of each
+// middle row.
+__host__ __device__ inline long long pml_index(const Geo &g, int i, int j)
+{
+    if (i < g.npml)
+        return (long long)i * g.Nx + j;
+    if (i >= g.Nz - g.npml)
+        return (long long)(i - (g.Nz - 2 * g.npml)) * g.Nx + j;
+    long long base = 2LL * g.npml * g.Nx + (long long)(i - g.npml) * 2 * g.npml;
+    return j < g.npml ? base + j : base + j - (g.Nx - 2 * g.npml);
+}
+
+// 1-D damping tables: alpha and beta of u' = alpha u + beta rhs, at integer
+// (node) and half (node + 1/2) positions along x and z.
+struct Pml {
+    const float *ax, *bx, *ahx, *bhx;  // [Nx]
+    const float *az, *bz, *ahz, *bhz;  // [Nz]
+};
+
+// Model on the padded grid.
+struct Mdl {
+    const float *K;    // bulk modulus at nodes
+    const float *bx;   // buoyancy at (i, j+1/2)
+    const float *bz;   // buoyancy at (i+1/2, j)
+};
+
+// Source of each shot: padded node (i, j) of the upper-left corner of its
+// bilinear cell and the four weights divided by dx dz, ordered
+// (i,j), (i,j+1), (i+1,j), (i+1,j+1).
+struct Src {
+    const int2 *ij;      // [S]
+    const float4 *w;     // [S]
+    const float *Q;      // [S][nt] time integral of the wavelet at n+1/2
+    int nt;
+};
+
+// Receivers of each shot: linear padded index of the upper-left node and
+// bilinear weights, same ordering.
+struct Rec {
+    const long long *idx;  // [S][nrec]
+    const float4 *w;       // [S][nrec]
+    int nrec;
+};
+
+// Nodes touched by receivers, per shot, with their receiver contributions
+// in ascending receiver order (for a deterministic adjoint injection).
+struct Inj {
+    const long long *node;   // [nnodes] padded linear index
+    const int *shot;         // [nnodes]
+    const int *cptr;         // [nnodes + 1] into crec / cw
+    const int *crec;         // receiver index
+    const float *cw;         // bilinear weight
+    int nnodes;
+};
+
+// ---------------------------------------------------------------- common
+void launch_fill(float *p, long long n, float v, hipStream_t st);
+void launch_pml_tables(const Geo &g, double vmax, double pml_r, double dx, double dz,
+                       double dt, float *tabs, hipStream_t st);
+void launch_prep_model(const Geo &g, int param, const float *m1, const float *m2,
+                       float *Kphys, float *rhophys, float *Kpad, float *bx, float *bz,
+                       hipStream_t st);
+void launch_cumulative_wavelet(const float *f, int per_shot, int S, int nt, float dt, float *Q,
+                               hipStream_t st);
+void launch_sample(const Geo &g, Fld p, Fld pz, const Rec &r, int S, float *traces, int nt,
+                   int n, hipStream_t st);
+// shot0: shot index of lp.shot(0) (the table holds global shot indices).
+void launch_inject(const Geo &g, const Inj &inj, const float *resid, int nrec, int nt, int n,
+                   Fld lp, int shot0, hipStream_t st);
+void launch_misfit(const float *d, const float *dobs, float *resid, long long n,
+                   float *partials, int nblocks, float *J, hipStream_t st);
+int misfit_blocks(long long n);
+void launch_finalize(const Geo &g, int param, const float *m1, const float *m2,
+                     const float *bx, const float *bz, const float *gpart, int groups,
+                     float *g1, float *g2, hipStream_t st);
+void launch_convert(int from, int to, long long n, const float *a1, const float *a2, float *b1,
+                    float *b2, hipStream_t st);
+void launch_chain_rule(int param, long long n, const float *m1, const float *m2,
+                       const float *gK, const float *grho, float *g1, float *g2,
+                       hipStream_t st);
+void launch_contrast_scale(long long n, const float *m0, float *g, hipStream_t st);
+
+// ----------------------------------------------------------------- plain
+// One shot per launch.  Output arrays may alias the inputs.
+void launch_plain_vel(const Geo &g, const Pml &t, const Mdl &m, const float *vx_in,
+                      const float *vz_in, float *vx_out, float *vz_out, const float *p,
+                      hipStream_t st);
+void launch_plain_pres(const Geo &g, const Pml &t, const Mdl &m, const float *vx,
+                       const float *vz, const float *p_in, const float *pz_in, float *p_out,
+                       float *pz_out, int2 sij, float4 sw, const float *Q, int n,
+                       hipStream_t st);
+// Adjoint, first half: lambda_v <- alpha_h lambda_v + D+(beta K mu_p), imaging.
+void launch_plain_adj_a(const Geo &g, const Pml &t, const Mdl &m, const float *lvx_in,
+                        const float *lvz_in, float *lvx_out, float *lvz_out, const float *lpx,
+                        const float *lpz, const float *pn, const float *pzn, const float *pn1,
+                        const float *pzn1, float *gK, float *gbx, float *gbz, hipStream_t st);
+// Adjoint, second half: mu_p <- alpha mu_p + D-(beta_h b lambda_v).
+void launch_plain_adj_b(const Geo &g, const Pml &t, const Mdl &m, const float *lvx,
+                        const float *lvz, const float *lpx_in, const float *lpz_in,
+                        float *lpx_out, float *lpz_out, hipStream_t st);
+
+// ----------------------------------------------------------------- fused
+struct FwdStep {
+    Fld vx_in, vz_in, p_in, pz_in;
+    Fld vx_out, vz_out, p_out, pz_out;
+    int n;              // time step being taken (n -> n+1)
+};
+struct AdjStep {
+    Fld lvx_in, lvz_in, lpx_in, lpz_in;      // adjoint state after step n+1
+    Fld lvx_out, lvz_out, lpx_out, lpz_out;  // adjoint state after step n
+    Fld pn, pzn, pn1, pzn1;                  // forward pressure at n and n+1
+    float *gpart;                            // [groups][3][N]
+    int n;
+};
+bool fused_tile_supported(int tile_z);
+void launch_fused_fwd(const Geo &g, const Pml &t, const Mdl &m, const Src &src, int S,
+                      int groups, int tile_z, const FwdStep &a, hipStream_t st);
+void launch_fused_adj(const Geo &g, const Pml &t, const Mdl &m, const Src &src, int S,
+                      int groups, int tile_z, const AdjStep &a, hipStream_t st);
+
+}  // namespace fwi

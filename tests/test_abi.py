@@ -1,0 +1,82 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, every
+symbol declared in include/fwi2d.h is exported, and argument validation
+reports errors before touching a device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1804_01184_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "fwi2d.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fwi_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.lib()
+    names = _declared()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(L.SYMBOLS) == names
+
+
+def test_status_strings():
+    lib = L.lib()
+    for s in L.STATUS:
+        assert lib.fwi_status_str(s)
+    assert lib.fwi_status_str(L.FWI_OK) == b"ok"
+
+
+def _create(nz=41, nx=41, dt=1e-3, dx=5.0, vmax=2000.0, src=((100.0, 100.0),),
+            rec=((50.0, 60.0),), npml=10, exec_=None):
+    src = np.ascontiguousarray(np.asarray(src, dtype=np.float64))
+    rec = np.ascontiguousarray(np.broadcast_to(np.asarray(rec, dtype=np.float64),
+                                               (src.shape[0], len(rec), 2)))
+    dp = ctypes.POINTER(ctypes.c_double)
+    g = L.FwiGrid(nz, nx, npml, 100, dx, dx, dt, vmax, 1e-3)
+    a = L.FwiAcq(src.shape[0], rec.shape[1], 0, src.ctypes.data_as(dp), rec.ctypes.data_as(dp))
+    h = ctypes.c_void_p()
+    ex = ctypes.byref(exec_) if exec_ is not None else None
+    rc = L.lib().fwi_plan_create(ctypes.byref(g), ctypes.byref(a), ex, ctypes.byref(h))
+    return rc, h
+
+
+def test_unstable_time_step_rejected():
+    # vmax dt / dx = 0.7 > 0.606
+    rc, h = _create(dt=0.7 * 5.0 / 2000.0)
+    assert rc == -4
+    assert b"stability" in L.lib().fwi_last_error() or b">" in L.lib().fwi_last_error()
+
+
+@pytest.mark.parametrize("kw", [dict(nz=3), dict(dx=-1.0), dict(npml=-1),
+                                dict(src=((-5.0, 10.0),)), dict(rec=((500.0, 10.0),)),
+                                dict(rec=((200.0, 200.0),))])
+def test_bad_arguments_rejected(kw):
+    rc, h = _create(**kw)
+    assert rc == -1, L.lib().fwi_last_error()
+
+
+def test_bad_exec_rejected():
+    rc, _ = _create(exec_=L.FwiExec(0, 0, 12, 0))
+    assert rc == -1
+    rc, _ = _create(exec_=L.FwiExec(7, 0, 0, 0))
+    assert rc == -1
+    rc, _ = _create(exec_=L.FwiExec(0, 0, 0, 5))
+    assert rc == -1
+
+
+def test_null_calls_rejected():
+    lib = L.lib()
+    assert lib.fwi_workspace_bytes(None, 0) == 0
+    assert lib.fwi_forward(None, 0, None, None, None, None, None, 0, None) == -1
+    assert lib.fwi_chain_rule(9, 10, None, None, None, None, None, None, None) == -1
+    assert lib.fwi_model_convert(0, 1, -1, None, None, None, None, None) == -1
+    assert lib.fwi_contrast_scale(0, None, None, None) == 0

@@ -1,0 +1,254 @@
+"""Parity of the HIP library (FP32) with the FP64 oracle, through the C ABI.
+
+Error measure: max |gpu - oracle| / max |oracle|, per shot gather for traces
+and per array for gradients.  Bound 1e-4.  Gradients are compared at a fixed
+adjoint source (the oracle's FP64 residual rounded to FP32, fed to both), so
+that the FP32 loss of significance in d - d_obs does not enter; the end-to-end
+gradient is checked with that cancellation factor stated.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1804_01184_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def api():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1804_01184_amd import api as A
+    return A
+
+
+def maxrel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def gather_err(gpu, ref):
+    return max(maxrel(gpu[s], ref[s]) for s in range(ref.shape[0]))
+
+
+def ogrid(w, nt=None):
+    return O.Grid(w.nz, w.nx, w.dz, w.dx, w.npml, w.nt if nt is None else nt, w.dt, w.vmax,
+                  w.pml_r)
+
+
+def agrid(api, w, nt=None):
+    g = api.Grid.of(w)
+    if nt is not None:
+        g.nt = nt
+    return g
+
+
+class Case:
+    """Oracle data for one workload: traces of the start model, observed
+    data of the true model, residual, gradients (K, rho)."""
+
+    def __init__(self, w, ckpt=0):
+        self.w = w
+        self.g = ogrid(w)
+        self.f = w.wavelet()
+        self.K0 = w.rho_start * w.vp_start ** 2
+        self.r0 = w.rho_start.copy()
+        Kt = w.rho_true * w.vp_true ** 2
+        self.obs = O.forward_krho(self.g, w.src_xz, w.rec_xz, Kt, w.rho_true, self.f)
+        self.d = O.forward_krho(self.g, w.src_xz, w.rec_xz, self.K0, self.r0, self.f)
+        self.J, self.r = O.misfit(self.d, self.obs)
+        self.adj = self.r.astype(np.float32)
+        self.gK, self.gr = O.adjoint_krho(self.g, w.src_xz, w.rec_xz, self.K0, self.r0, self.f,
+                                          self.adj.astype(np.float64), ckpt)
+
+
+@pytest.fixture(scope="module")
+def c1():
+    return Case(W.config1())
+
+
+def _small(n=149, shots=6, nrec=40, nt=300, npml=12, seed=3, rho_contrast=0.15):
+    w = W.gauss_problem(n, shots, nrec, nt, npml=npml, contrast=0.3, rho_contrast=rho_contrast,
+                        radius_frac=0.7, seed=seed)
+    # heterogeneous start model: smooth random perturbation of the background
+    rng = np.random.default_rng(seed)
+    vp, rho = W.random_model(rng, w.nz, w.nx, amp=0.05, corr=4.0)
+    w.vp_start, w.rho_start = vp, rho
+    w.vmax = float(max(w.vp_true.max(), vp.max()))
+    w.dt = 0.5 * w.dx / w.vmax
+    return w
+
+
+@pytest.fixture(scope="module")
+def small():
+    return Case(_small())
+
+
+# ------------------------------------------------------------------ forward
+
+@pytest.mark.parametrize("mode", ["plain", "batched"])
+def test_forward_config1(api, c1, mode):
+    w = c1.w
+    p = api.Plan(agrid(api, w), w.src_xz, w.rec_xz, mode=mode)
+    tr = p.forward("k-rho", c1.K0, c1.r0, c1.f).cpu().numpy()
+    assert gather_err(tr, c1.d) <= TOL
+
+
+@pytest.mark.parametrize("mode,tile_z,groups", [("plain", 0, 0), ("batched", 8, 1),
+                                                ("batched", 16, 2), ("batched", 32, 6),
+                                                ("batched", 16, 4)])
+def test_forward_multi_tile_ragged(api, small, mode, tile_z, groups):
+    w = small.w
+    p = api.Plan(agrid(api, w), w.src_xz, w.rec_xz, mode=mode, tile_z=tile_z,
+                 shot_groups=groups)
+    tr = p.forward("k-rho", small.K0, small.r0, small.f).cpu().numpy()
+    assert gather_err(tr, small.d) <= TOL
+
+
+@pytest.mark.parametrize("param", [0, 1, 2, 3, 4])
+def test_forward_every_parameterization(api, small, param):
+    w = small.w
+    m1, m2 = O.krho_to_model(param, small.K0, small.r0)
+    p = api.Plan(agrid(api, w), w.src_xz, w.rec_xz)
+    tr = p.forward(param, m1, m2, small.f).cpu().numpy()
+    assert gather_err(tr, small.d) <= TOL
+
+
+def test_forward_wavelet_per_shot(api, small):
+    w = small.w
+    rng = np.random.default_rng(11)
+    f = np.stack([np.roll(small.f, k) * (1 + 0.1 * k) for k in range(w.nshots)])
+    ref = O.forward_krho(small.g, w.src_xz, w.rec_xz, small.K0, small.r0, f)
+    p = api.Plan(agrid(api, w), w.src_xz, w.rec_xz, wavelet_per_shot=True)
+    tr = p.forward("k-rho", small.K0, small.r0, f).cpu().numpy()
+    assert gather_err(tr, ref) <= TOL
+    del rng
+
+
+# ----------------------------------------------------- gradient (fixed r)
+
+@pytest.mark.parametrize("mode", ["plain", "batched"])
+@pytest.mark.parametrize("param", [0, 1, 2, 3, 4])
+def test_adjoint_config1(api, c1, mode, param):
+    w = c1.w
+    m1, m2 = O.krho_to_model(param, c1.K0, c1.r0)
+    e1, e2 = O.chain_rule(param, c1.K0, c1.r0, c1.gK, c1.gr)
+    p = api.Plan(agrid(api, w), w.src_xz, w.rec_xz, mode=mode)
+    g1, g2 = p.adjoint(param, m1, m2, c1.f, c1.adj)
+    assert maxrel(g1.cpu().numpy(), e1) <= TOL
+    assert maxrel(g2.cpu().numpy(), e2) <= TOL
+
+
+@pytest.mark.parametrize("mode,tile_z,groups,ckpt", [("plain", 0, 0, 0), ("plain", 0, 0, 23),
+                                                     ("batched", 8, 3, 0),
+                                                     ("batched", 16, 2, 17),
+                                                     ("batched", 32, 1, 300),
+                                                     ("batched", 16, 6, 1)])
+def test_adjoint_multi_tile_ragged(api, small, mode, tile_z, groups, ckpt):
+    w = small.w
+    p = api.Plan(agrid(api, w), w.src_xz, w.rec_xz, mode=mode, tile_z=tile_z,
+                 shot_groups=groups, ckpt_every=ckpt)
+    gK, gr = p.adjoint("k-rho", small.K0, small.r0, small.f, small.adj)
+    assert maxrel(gK.cpu().numpy(), small.gK) <= TOL
+    assert maxrel(gr.cpu().numpy(), small.gr) <= TOL
+
+
+def test_checkpointed_equals_full_history_bitwise(api, small):
+    w = small.w
+    out = []
+    for k in (w.nt, 7):
+        p = api.Plan(agrid(api, w), w.src_xz, w.rec_xz, ckpt_every=k, tile_z=16,
+                     shot_groups=2)
+        out.append([x.cpu().numpy() for x in p.adjoint(0, small.K0, small.r0, small.f,
+                                                       small.adj)])
+    np.testing.assert_array_equal(out[0][0], out[1][0])
+    np.testing.assert_array_equal(out[0][1], out[1][1])
+
+
+def test_repeatable_bitwise(api, small):
+    w = small.w
+    p = api.Plan(agrid(api, w), w.src_xz, w.rec_xz)
+    a = [x.cpu().numpy() for x in p.gradient(1, w.vp_start, w.rho_start, small.f, small.obs)]
+    b = [x.cpu().numpy() for x in p.gradient(1, w.vp_start, w.rho_start, small.f, small.obs)]
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x, y)
+
+
+# ------------------------------------------------------------- end to end
+
+@pytest.mark.parametrize("mode", ["plain", "batched"])
+def test_gradient_end_to_end(api, small, mode):
+    """J and the misfit gradient from modelled FP32 data.  The residual
+    d - d_obs carries the FP32 trace error amplified by
+    kappa = max|d| / max|d - d_obs|, so the bound is 1e-4 * kappa."""
+    w = small.w
+    kappa = np.abs(small.d).max() / np.abs(small.r).max()
+    p = api.Plan(agrid(api, w), w.src_xz, w.rec_xz, mode=mode)
+    for param in range(5):
+        m1, m2 = O.krho_to_model(param, small.K0, small.r0)
+        J, g1, g2, tr = p.gradient(param, m1, m2, small.f, small.obs, want_traces=True)
+        e1, e2 = O.chain_rule(param, small.K0, small.r0, small.gK, small.gr)
+        assert gather_err(tr.cpu().numpy(), small.d) <= TOL
+        assert abs(float(J.item()) - small.J) <= TOL * kappa * small.J
+        assert maxrel(g1.cpu().numpy(), e1) <= TOL * kappa
+        assert maxrel(g2.cpu().numpy(), e2) <= TOL * kappa
+
+
+def test_misfit_kernel(api, small):
+    w = small.w
+    p = api.Plan(agrid(api, w), w.src_xz, w.rec_xz)
+    d32 = small.d.astype(np.float32)
+    o32 = small.obs.astype(np.float32)
+    J, r = p.misfit(d32, o32)
+    rr = d32.astype(np.float64) - o32.astype(np.float64)
+    np.testing.assert_array_equal(r.cpu().numpy(), (d32 - o32))
+    assert abs(float(J.item()) - 0.5 * np.sum(rr * rr)) <= 1e-5 * 0.5 * np.sum(rr * rr)
+
+
+def test_conversions_chain_rule_contrast(api):
+    import torch
+    rng = np.random.default_rng(5)
+    K = rng.uniform(4e9, 2e10, 4097)
+    rho = rng.uniform(1500, 2600, 4097)
+    gK, gr = rng.standard_normal(4097) * 1e-9, rng.standard_normal(4097)
+    dev = torch.device("cuda")
+    t = lambda x: torch.tensor(x, dtype=torch.float32, device=dev)
+    for param in range(5):
+        m1, m2 = O.krho_to_model(param, K, rho)
+        b1, b2 = api.model_convert("k-rho", param, t(K), t(rho))
+        assert maxrel(b1.cpu().numpy(), m1) <= 1e-6 and maxrel(b2.cpu().numpy(), m2) <= 1e-6
+        g1, g2 = api.chain_rule(param, t(m1), t(m2), t(gK), t(gr))
+        e1, e2 = O.chain_rule(param, K, rho, gK, gr)
+        assert maxrel(g1.cpu().numpy(), e1) <= 1e-5 and maxrel(g2.cpu().numpy(), e2) <= 1e-5
+    g = t(gK)
+    api.contrast_scale(t(K), g)
+    assert maxrel(g.cpu().numpy(), gK * K) <= 1e-6
+
+
+def test_single_shot_single_receiver_and_tiny_grid(api):
+    """Degenerate sizes: one shot, one receiver, a grid smaller than a tile,
+    no absorbing layer, one time step and a few."""
+    for npml, nt in ((0, 1), (0, 9), (3, 40)):
+        n = 9
+        g = O.Grid(n, n, 5.0, 5.0, npml, nt, 1e-3, 2000.0)
+        src = np.array([[17.0, 21.0]])
+        rec = np.array([[[23.0, 12.5]]])
+        rng = np.random.default_rng(npml + nt)
+        K = 8e9 * (1 + 0.1 * rng.random((n, n)))
+        r = 2000 * (1 + 0.1 * rng.random((n, n)))
+        f = rng.standard_normal(nt)
+        ref = O.forward_krho(g, src, rec, K, r, f)
+        adj = rng.standard_normal(ref.shape)
+        eK, er = O.adjoint_krho(g, src, rec, K, r, f, adj)
+        for mode in ("plain", "batched"):
+            p = api.Plan(api.Grid(n, n, 5.0, 5.0, npml, nt, 1e-3, 2000.0), src, rec, mode=mode)
+            tr = p.forward(0, K, r, f).cpu().numpy()
+            assert maxrel(tr, ref) <= TOL
+            gK, gr = p.adjoint(0, K, r, f, adj.astype(np.float32))
+            assert maxrel(gK.cpu().numpy(), eK) <= TOL
+            assert maxrel(gr.cpu().numpy(), er) <= TOL
