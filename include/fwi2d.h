@@ -170,6 +170,24 @@ fwi_status fwi_adjoint(fwi_plan *plan, int32_t param, const float *m1, const flo
                        const float *wavelet, const float *adj_src, float *g1, float *g2,
                        void *ws, size_t ws_bytes, void *stream);
 
+/* Forward modelling that also keeps, in the workspace (FWI_OP_GRADIENT
+ * size), what the adjoint needs: the prepared model, the checkpoints and the
+ * pressure history of the last segment.  traces as fwi_forward.  For use
+ * with fwi_adjoint_kept (e.g. a framework's autograd forward/backward); the
+ * workspace must not be used by another call in between. */
+fwi_status fwi_forward_keep(fwi_plan *plan, int32_t param, const float *m1, const float *m2,
+                            const float *wavelet, float *traces, void *ws, size_t ws_bytes,
+                            void *stream);
+
+/* Adjoint-state gradient from the state kept by the last fwi_forward_keep on
+ * this plan and workspace: g = d<adj_src, p>/dm at the model of that call
+ * (param, m1, m2 must be the same).  The kept state is consumed; without a
+ * preceding fwi_forward_keep on `ws` the call returns FWI_ESTATE.  A plain
+ * plan keeps nothing and recomputes the forward sweep shot by shot. */
+fwi_status fwi_adjoint_kept(fwi_plan *plan, int32_t param, const float *m1, const float *m2,
+                            const float *wavelet, const float *adj_src, float *g1, float *g2,
+                            void *ws, size_t ws_bytes, void *stream);
+
 /* Exact conversion between parameterizations (parameter definitions Ip =
  * rho Vp, K = rho Vp^2; Table 2 in absolute form), n cells. */
 fwi_status fwi_model_convert(int32_t from_param, int32_t to_param, int64_t n, const float *a1,

@@ -22,7 +22,8 @@ FWI_OP_FORWARD, FWI_OP_MISFIT, FWI_OP_GRADIENT = 0, 1, 2
 
 # exported symbols declared in include/fwi2d.h
 SYMBOLS = ["fwi_plan_create", "fwi_plan_destroy", "fwi_plan_get_info", "fwi_workspace_bytes",
-           "fwi_forward", "fwi_misfit", "fwi_gradient", "fwi_adjoint", "fwi_model_convert",
+           "fwi_forward", "fwi_misfit", "fwi_gradient", "fwi_adjoint", "fwi_forward_keep",
+           "fwi_adjoint_kept", "fwi_model_convert",
            "fwi_chain_rule", "fwi_contrast_scale", "fwi_timing_enable", "fwi_timing_read",
            "fwi_sync", "fwi_status_str", "fwi_last_error"]
 
@@ -98,6 +99,10 @@ def lib():
     L.fwi_gradient.restype = st
     L.fwi_adjoint.argtypes = [vp, i32, fp, fp, fp, fp, fp, fp, vp, sz, vp]
     L.fwi_adjoint.restype = st
+    L.fwi_forward_keep.argtypes = [vp, i32, fp, fp, fp, fp, vp, sz, vp]
+    L.fwi_forward_keep.restype = st
+    L.fwi_adjoint_kept.argtypes = [vp, i32, fp, fp, fp, fp, fp, fp, vp, sz, vp]
+    L.fwi_adjoint_kept.restype = st
     L.fwi_model_convert.argtypes = [i32, i32, i64, fp, fp, fp, fp, vp]
     L.fwi_model_convert.restype = st
     L.fwi_chain_rule.argtypes = [i32, i64, fp, fp, fp, fp, fp, fp, vp]

@@ -95,12 +95,10 @@ class Plan:
         self._ws = {}
 
     def __del__(self):
+        # fwi_plan_destroy frees the plan's device tables; hipFree waits for
+        # the device, so work still using them completes first
         h = getattr(self, "_h", None)
         if h is not None and h.value:
-            try:
-                torch.cuda.synchronize(self.device)
-            except Exception:
-                pass
             L.lib().fwi_plan_destroy(h)
             self._h = None
 
@@ -131,6 +129,11 @@ class Plan:
             ws = torch.empty(max(n, 256), dtype=torch.uint8, device=self.device)
             self._ws[op] = ws
         return ws
+
+    def new_workspace(self, op):
+        """A fresh workspace tensor for `op` (not cached by the plan)."""
+        return torch.empty(max(self.workspace_bytes(op), 256), dtype=torch.uint8,
+                           device=self.device)
 
     def release_workspace(self):
         self._ws = {}
@@ -189,6 +192,27 @@ class Plan:
         L.check(L.lib().fwi_adjoint(self._h, param_id(param), _ptr(m1), _ptr(m2), _ptr(w),
                                     _ptr(a), _ptr(g1), _ptr(g2), _ptr(ws), ws.numel(),
                                     _stream(stream)))
+        return g1, g2
+
+
+    def forward_keep(self, param, m1, m2, wavelet, ws, stream=None):
+        """Traces, keeping in `ws` what adjoint_kept needs."""
+        m1, m2 = _dev_f32(m1, self.device), _dev_f32(m2, self.device)
+        w = _dev_f32(wavelet, self.device)
+        traces = torch.empty(self._traces_shape(), dtype=torch.float32, device=self.device)
+        L.check(L.lib().fwi_forward_keep(self._h, param_id(param), _ptr(m1), _ptr(m2), _ptr(w),
+                                         _ptr(traces), _ptr(ws), ws.numel(), _stream(stream)))
+        return traces
+
+    def adjoint_kept(self, param, m1, m2, wavelet, adj_src, ws, stream=None):
+        """(g1, g2) from the state kept in `ws` by forward_keep."""
+        m1, m2 = _dev_f32(m1, self.device), _dev_f32(m2, self.device)
+        w = _dev_f32(wavelet, self.device)
+        a = _dev_f32(adj_src, self.device)
+        g1, g2 = torch.empty_like(m1), torch.empty_like(m1)
+        L.check(L.lib().fwi_adjoint_kept(self._h, param_id(param), _ptr(m1), _ptr(m2), _ptr(w),
+                                         _ptr(a), _ptr(g1), _ptr(g2), _ptr(ws), ws.numel(),
+                                         _stream(stream)))
         return g1, g2
 
 

@@ -64,6 +64,9 @@ struct fwi_plan {
     float *inj_cw = nullptr;
     int inj_nodes = 0;
     std::vector<int> shot_node_ptr;  // [S+1] node range of each shot
+    // per-(shot, tile) lists of the batched kernels
+    int *tl_samp_ptr = nullptr, *tl_samp_rec = nullptr;
+    int *tl_inj_ptr = nullptr, *tl_inj_node = nullptr;
     std::vector<int2> h_src_ij;
     std::vector<float4> h_src_w;
     // per-launch event timing (instrumentation)
@@ -75,6 +78,8 @@ struct fwi_plan {
     std::vector<Mark> marks;
     std::vector<hipEvent_t> spare;
     fwi_timing acc{};
+    // workspace holding the state kept by fwi_forward_keep (null: none)
+    void *kept_ws = nullptr;
 };
 
 namespace {
@@ -286,8 +291,15 @@ Inj inj_of(const Ctx &c, int s0, int nb)
     return in;
 }
 
-// One forward step n -> n+1 for shots [s0, s0+nb) from `in` to `out`.
-void step_fwd(const Ctx &c, int s0, int nb, const State &in, const State &out, int n)
+TileLists tiles_of(const fwi_plan *p)
+{
+    return TileLists{p->tl_samp_ptr, p->tl_samp_rec, p->tl_inj_ptr, p->tl_inj_node};
+}
+
+// One forward step n -> n+1 for shots [s0, s0+nb) from `in` to `out`.  The
+// batched kernel also writes trace sample n-1 (from `in`) when traces != 0.
+void step_fwd(const Ctx &c, int s0, int nb, const State &in, const State &out, int n,
+              float *traces = nullptr)
 {
     const fwi_plan *p = c.pl;
     const Geo &g = p->geo;
@@ -301,9 +313,11 @@ void step_fwd(const Ctx &c, int s0, int nb, const State &in, const State &out, i
         launch_plain_pres(g, c.t, c.m, out.vx.p, out.vz.p, in.p.p, in.pz.p, out.p.p, out.pz.p,
                           p->h_src_ij[s0], p->h_src_w[s0], src.Q, n, c.st);
     } else {
-        FwdStep a{in.vx, in.vz, in.p, in.pz, out.vx, out.vz, out.p, out.pz, n};
+        FwdStep a{in.vx, in.vz, in.p, in.pz, out.vx, out.vz, out.p, out.pz, n,
+                  (traces && n > 0) ? n - 1 : -1, traces};
         Timed tm(c.pl, c.st, FWI_KC_FWD_STEP);
-        launch_fused_fwd(g, c.t, c.m, src, nb, p->groups, p->tile_z, a, c.st);
+        launch_fused_fwd(g, c.t, c.m, src, rec_of(c, s0), tiles_of(p), nb, p->groups, p->tile_z,
+                         a, c.st);
     }
 }
 
@@ -315,7 +329,9 @@ void step_adj(const Ctx &c, int s0, int nb, const State &in, const State &out, F
 {
     const fwi_plan *p = c.pl;
     const Geo &g = p->geo;
-    {
+    // the batched kernel of step n+1 already added R^T r^n to its output,
+    // except for the first adjoint step
+    if (p->mode == FWI_EXEC_PLAIN || n == p->grid.nt - 1) {
         Timed tm(c.pl, c.st, FWI_KC_INJECT);
         launch_inject(g, inj_of(c, s0, nb), resid, p->nrec, p->grid.nt, n, in.p, s0, c.st);
     }
@@ -331,9 +347,10 @@ void step_adj(const Ctx &c, int s0, int nb, const State &in, const State &out, F
                            c.st);
     } else {
         AdjStep a{in.vx, in.vz, in.p, in.pz, out.vx, out.vz, out.p, out.pz,
-                  pn, pzn, pn1, pzn1, gpart, n};
+                  pn, pzn, pn1, pzn1, gpart, n, n > 0 ? n - 1 : -1, resid};
         Timed tm(c.pl, c.st, FWI_KC_ADJ_STEP);
-        launch_fused_adj(g, c.t, c.m, src_of(c, s0), nb, p->groups, p->tile_z, a, c.st);
+        launch_fused_adj(g, c.t, c.m, src_of(c, s0), inj_of(c, s0, nb), p->nrec, tiles_of(p), nb,
+                         p->groups, p->tile_z, a, c.st);
     }
 }
 
@@ -375,8 +392,9 @@ void sweep_forward(const Ctx &c, int s0, int nb, bool keep, float *traces)
             out = state_at(c.f(c.L.ckpt) + (size_t)(n1 / k - 1) * nb * p->SS, p);
             next_cw = -1;
         }
-        step_fwd(c, s0, nb, cur, out, n);
-        if (traces) {
+        bool batched = p->mode != FWI_EXEC_PLAIN;
+        step_fwd(c, s0, nb, cur, out, n, batched ? traces : nullptr);
+        if (traces && (!batched || n == nt - 1)) {
             Timed tm(c.pl, c.st, FWI_KC_SAMPLE);
             launch_sample(p->geo, out.p, out.pz, rec, nb, traces, nt, n, c.st);
         }
@@ -490,36 +508,66 @@ void prepare(const Ctx &c, int param, const float *m1, const float *m2, const fl
                               c.f(c.L.Q), c.st);
 }
 
-// Gradient core: forward (traces), residual provider, backward, finalize.
-// `observed` given: misfit gradient (J written); else adj_src is the
-// adjoint source.
-fwi_status run_gradient(fwi_plan *p, int param, const float *m1, const float *m2,
-                        const float *wavelet, const float *observed, const float *adj_src,
-                        float *J, float *g1, float *g2, float *traces, void *ws, void *stream)
+// Backward half of the gradient: zero the partial sensitivities, sweep
+// backward from the kept forward state (batched) or per shot (plain, which
+// redoes each shot's forward sweep first), finalize.
+fwi_status run_backward(const Ctx &c, int param, const float *m1, const float *m2,
+                        const float *res, float *g1, float *g2)
 {
-    Ctx c = make_ctx(p, ws, stream, FWI_OP_GRADIENT);
+    fwi_plan *p = c.pl;
     const Geo &g = p->geo;
-    prepare(c, param, m1, m2, wavelet);
     float *gpart = c.f(c.L.gpart);
     int G = groups_of(p);
     {
         Timed tm(p, c.st, FWI_KC_OTHER);
         launch_fill(gpart, (long long)G * 3 * g.N, 0.0f, c.st);
     }
+    if (p->mode == FWI_EXEC_PLAIN) {
+        for (int s = 0; s < p->S; ++s) {
+            sweep_forward(c, s, 1, true, nullptr);
+            sweep_backward(c, s, 1, res, gpart);
+        }
+    } else {
+        sweep_backward(c, 0, p->S, res, gpart);
+    }
+    {
+        Timed tm(p, c.st, FWI_KC_OTHER);
+        launch_finalize(g, param, m1, m2, c.m.bx, c.m.bz, gpart, G, g1, g2, c.st);
+    }
+    return launched("gradient");
+}
+
+// Misfit gradient (observed given, J written) or adjoint for a given
+// adjoint source (adj_src given).
+fwi_status run_gradient(fwi_plan *p, int param, const float *m1, const float *m2,
+                        const float *wavelet, const float *observed, const float *adj_src,
+                        float *J, float *g1, float *g2, float *traces, void *ws, void *stream)
+{
+    if (p->kept_ws == ws)
+        p->kept_ws = nullptr;
+    Ctx c = make_ctx(p, ws, stream, FWI_OP_GRADIENT);
+    prepare(c, param, m1, m2, wavelet);
     float *tr = traces ? traces : c.f(c.L.traces);
     long long per_shot = (long long)p->nrec * p->grid.nt;
     long long ntr = per_shot * p->S;
     float *resid = c.f(c.L.resid);
     float *partials = c.f(c.L.partials);
     if (p->mode == FWI_EXEC_PLAIN) {
+        // shot after shot: forward keeping its history, its residual, its
+        // backward sweep; J over all shots at the end
+        const Geo &g = p->geo;
+        float *gpart = c.f(c.L.gpart);
+        {
+            Timed tm(p, c.st, FWI_KC_OTHER);
+            launch_fill(gpart, 3 * g.N, 0.0f, c.st);
+        }
         for (int s = 0; s < p->S; ++s) {
-            float *trs = tr + s * per_shot;
             const float *res = adj_src;
-            sweep_forward(c, s, 1, true, observed ? trs : nullptr);
+            sweep_forward(c, s, 1, true, observed ? tr + s * per_shot : nullptr);
             if (observed) {
                 Timed tm(p, c.st, FWI_KC_OTHER);
-                launch_misfit(trs, observed + s * per_shot, resid + s * per_shot, per_shot,
-                              partials, misfit_blocks(per_shot), J, c.st);
+                launch_misfit(tr + s * per_shot, observed + s * per_shot, resid + s * per_shot,
+                              per_shot, partials, misfit_blocks(per_shot), J, c.st);
                 res = resid;
             }
             sweep_backward(c, s, 1, res, gpart);
@@ -528,21 +576,20 @@ fwi_status run_gradient(fwi_plan *p, int param, const float *m1, const float *m2
             Timed tm(p, c.st, FWI_KC_OTHER);
             launch_misfit(tr, observed, nullptr, ntr, partials, misfit_blocks(ntr), J, c.st);
         }
-    } else {
-        sweep_forward(c, 0, p->S, true, observed ? tr : nullptr);
-        const float *res = adj_src;
-        if (observed) {
+        {
             Timed tm(p, c.st, FWI_KC_OTHER);
-            launch_misfit(tr, observed, resid, ntr, partials, misfit_blocks(ntr), J, c.st);
-            res = resid;
+            launch_finalize(g, param, m1, m2, c.m.bx, c.m.bz, gpart, 1, g1, g2, c.st);
         }
-        sweep_backward(c, 0, p->S, res, gpart);
+        return launched("gradient");
     }
-    {
+    sweep_forward(c, 0, p->S, true, observed ? tr : nullptr);
+    const float *res = adj_src;
+    if (observed) {
         Timed tm(p, c.st, FWI_KC_OTHER);
-        launch_finalize(g, param, m1, m2, c.m.bx, c.m.bz, gpart, G, g1, g2, c.st);
+        launch_misfit(tr, observed, resid, ntr, partials, misfit_blocks(ntr), J, c.st);
+        res = resid;
     }
-    return launched("gradient");
+    return run_backward(c, param, m1, m2, res, g1, g2);
 }
 
 }  // namespace
@@ -713,6 +760,37 @@ fwi_status fwi_plan_create(const fwi_grid *grid, const fwi_acq *acq, const fwi_e
     inj_cptr.push_back((int)inj_crec.size());
     p->inj_nodes = (int)inj_node.size();
 
+    // per-(shot, tile) lists for the batched kernels
+    int ntx;
+    const int ntl = fused_tiles(g, p->tile_z, &ntx);
+    auto tile_of = [&](long long c) {
+        int i = (int)(c / g.Nx), j = (int)(c % g.Nx);
+        return (i / p->tile_z) * ntx + j / 64;
+    };
+    std::vector<int> samp_ptr((size_t)S * ntl + 1, 0), samp_rec;
+    std::vector<int> tinj_ptr((size_t)S * ntl + 1, 0), tinj_node;
+    {
+        std::vector<std::vector<int>> bucket(ntl);
+        for (int s = 0; s < S; ++s) {
+            for (auto &b : bucket)
+                b.clear();
+            for (int r = 0; r < nr; ++r)
+                bucket[tile_of(rec_idx[(size_t)s * nr + r])].push_back(r);
+            for (int t = 0; t < ntl; ++t) {
+                samp_rec.insert(samp_rec.end(), bucket[t].begin(), bucket[t].end());
+                samp_ptr[(size_t)s * ntl + t + 1] = (int)samp_rec.size();
+            }
+            for (auto &b : bucket)
+                b.clear();
+            for (int k = p->shot_node_ptr[s]; k < p->shot_node_ptr[s + 1]; ++k)
+                bucket[tile_of(inj_node[k])].push_back(k);
+            for (int t = 0; t < ntl; ++t) {
+                tinj_node.insert(tinj_node.end(), bucket[t].begin(), bucket[t].end());
+                tinj_ptr[(size_t)s * ntl + t + 1] = (int)tinj_node.size();
+            }
+        }
+    }
+
     if (hipGetDevice(&p->device) != hipSuccess) {
         delete p;
         return fail(FWI_EDEVICE, "no HIP device");
@@ -732,6 +810,8 @@ fwi_status fwi_plan_create(const fwi_grid *grid, const fwi_acq *acq, const fwi_e
     size_t o_ip = take(sizeof(int) * inj_cptr.size());
     size_t o_ir = take(sizeof(int) * inj_crec.size());
     size_t o_iw = take(sizeof(float) * inj_cw.size());
+    size_t o_tsp = take(sizeof(int) * samp_ptr.size()), o_tsr = take(sizeof(int) * samp_rec.size());
+    size_t o_tip = take(sizeof(int) * tinj_ptr.size()), o_tin = take(sizeof(int) * tinj_node.size());
     if (hipMalloc(&p->dev, off) != hipSuccess) {
         (void)hipGetLastError();
         delete p;
@@ -748,6 +828,10 @@ fwi_status fwi_plan_create(const fwi_grid *grid, const fwi_acq *acq, const fwi_e
     p->inj_cptr = (int *)(d + o_ip);
     p->inj_crec = (int *)(d + o_ir);
     p->inj_cw = (float *)(d + o_iw);
+    p->tl_samp_ptr = (int *)(d + o_tsp);
+    p->tl_samp_rec = (int *)(d + o_tsr);
+    p->tl_inj_ptr = (int *)(d + o_tip);
+    p->tl_inj_node = (int *)(d + o_tin);
     bool ok = true;
     auto up = [&](void *dst, const void *src, size_t bytes) {
         if (bytes && hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) != hipSuccess)
@@ -762,6 +846,10 @@ fwi_status fwi_plan_create(const fwi_grid *grid, const fwi_acq *acq, const fwi_e
     up(p->inj_cptr, inj_cptr.data(), sizeof(int) * inj_cptr.size());
     up(p->inj_crec, inj_crec.data(), sizeof(int) * inj_crec.size());
     up(p->inj_cw, inj_cw.data(), sizeof(float) * inj_cw.size());
+    up(p->tl_samp_ptr, samp_ptr.data(), sizeof(int) * samp_ptr.size());
+    up(p->tl_samp_rec, samp_rec.data(), sizeof(int) * samp_rec.size());
+    up(p->tl_inj_ptr, tinj_ptr.data(), sizeof(int) * tinj_ptr.size());
+    up(p->tl_inj_node, tinj_node.data(), sizeof(int) * tinj_node.size());
     launch_pml_tables(g, G.vmax, G.npml > 0 ? G.pml_r : 0.5, G.dx, G.dz, G.dt, p->pml, nullptr);
     if (!ok || hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
         (void)hipFree(p->dev);
@@ -817,6 +905,8 @@ fwi_status fwi_forward(fwi_plan *p, int32_t param, const float *m1, const float 
         return st;
     if (!valid_param(param) || !m1 || !m2 || !wavelet || !traces)
         return fail(FWI_EINVAL, "bad parameterization or NULL array");
+    if (p->kept_ws == ws)
+        p->kept_ws = nullptr;
     Ctx c = make_ctx(p, ws, stream, FWI_OP_FORWARD);
     prepare(c, param, m1, m2, wavelet);
     long long per_shot = (long long)p->nrec * p->grid.nt;
@@ -871,6 +961,44 @@ fwi_status fwi_adjoint(fwi_plan *p, int32_t param, const float *m1, const float 
         return fail(FWI_EINVAL, "bad parameterization or NULL array");
     return run_gradient(p, param, m1, m2, wavelet, nullptr, adj_src, nullptr, g1, g2, nullptr,
                         ws, stream);
+}
+
+fwi_status fwi_forward_keep(fwi_plan *p, int32_t param, const float *m1, const float *m2,
+                            const float *wavelet, float *traces, void *ws, size_t ws_bytes,
+                            void *stream)
+{
+    fwi_status st = check_call(p, ws, ws_bytes, FWI_OP_GRADIENT);
+    if (st != FWI_OK)
+        return st;
+    if (!valid_param(param) || !m1 || !m2 || !wavelet || !traces)
+        return fail(FWI_EINVAL, "bad parameterization or NULL array");
+    Ctx c = make_ctx(p, ws, stream, FWI_OP_GRADIENT);
+    prepare(c, param, m1, m2, wavelet);
+    long long per_shot = (long long)p->nrec * p->grid.nt;
+    if (p->mode == FWI_EXEC_PLAIN) {
+        for (int s = 0; s < p->S; ++s)
+            sweep_forward(c, s, 1, false, traces + s * per_shot);
+    } else {
+        sweep_forward(c, 0, p->S, true, traces);
+    }
+    p->kept_ws = ws;
+    return launched("forward_keep");
+}
+
+fwi_status fwi_adjoint_kept(fwi_plan *p, int32_t param, const float *m1, const float *m2,
+                            const float *wavelet, const float *adj_src, float *g1, float *g2,
+                            void *ws, size_t ws_bytes, void *stream)
+{
+    fwi_status st = check_call(p, ws, ws_bytes, FWI_OP_GRADIENT);
+    if (st != FWI_OK)
+        return st;
+    if (!valid_param(param) || !m1 || !m2 || !wavelet || !adj_src || !g1 || !g2)
+        return fail(FWI_EINVAL, "bad parameterization or NULL array");
+    if (p->kept_ws != ws)
+        return fail(FWI_ESTATE, "no forward state kept on this workspace");
+    p->kept_ws = nullptr;
+    Ctx c = make_ctx(p, ws, stream, FWI_OP_GRADIENT);
+    return run_backward(c, param, m1, m2, adj_src, g1, g2);
 }
 
 fwi_status fwi_model_convert(int32_t from, int32_t to, int64_t n, const float *a1,

@@ -136,10 +136,23 @@ void launch_plain_adj_b(const Geo &g, const Pml &t, const Mdl &m, const float *l
                         float *lpx_out, float *lpz_out, hipStream_t st);
 
 // ----------------------------------------------------------------- fused
+// Per-(shot, tile) work lists of the batched kernels, CSR over shot * ntiles
+// + tile: receivers whose bilinear cell starts in the tile (sampling), and
+// receiver-touched nodes the tile owns (adjoint injection; entries index the
+// Inj node table).
+struct TileLists {
+    const int *samp_ptr;   // [S * ntiles + 1]
+    const int *samp_rec;   // receiver index
+    const int *inj_ptr;    // [S * ntiles + 1]
+    const int *inj_node;   // index into Inj
+};
+
 struct FwdStep {
     Fld vx_in, vz_in, p_in, pz_in;
     Fld vx_out, vz_out, p_out, pz_out;
     int n;              // time step being taken (n -> n+1)
+    int sample_n;       // >= 0: write trace sample sample_n from p_in
+    float *traces;      // [S][nrec][nt]
 };
 struct AdjStep {
     Fld lvx_in, lvz_in, lpx_in, lpz_in;      // adjoint state after step n+1
@@ -147,11 +160,16 @@ struct AdjStep {
     Fld pn, pzn, pn1, pzn1;                  // forward pressure at n and n+1
     float *gpart;                            // [groups][3][N]
     int n;
+    int inject_n;           // >= 0: add R^T r^{inject_n} to the output pressure
+    const float *resid;     // [S][nrec][nt]
 };
 bool fused_tile_supported(int tile_z);
-void launch_fused_fwd(const Geo &g, const Pml &t, const Mdl &m, const Src &src, int S,
-                      int groups, int tile_z, const FwdStep &a, hipStream_t st);
-void launch_fused_adj(const Geo &g, const Pml &t, const Mdl &m, const Src &src, int S,
-                      int groups, int tile_z, const AdjStep &a, hipStream_t st);
+int fused_tiles(const Geo &g, int tile_z, int *ntx);
+void launch_fused_fwd(const Geo &g, const Pml &t, const Mdl &m, const Src &src, const Rec &rec,
+                      const TileLists &tl, int S, int groups, int tile_z, const FwdStep &a,
+                      hipStream_t st);
+void launch_fused_adj(const Geo &g, const Pml &t, const Mdl &m, const Src &src, const Inj &inj,
+                      int nrec, const TileLists &tl, int S, int groups, int tile_z,
+                      const AdjStep &a, hipStream_t st);
 
 }  // namespace fwi

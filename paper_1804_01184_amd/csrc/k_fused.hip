@@ -43,7 +43,8 @@ __device__ inline bool inside(const Geo &g, int i, int j)
 
 template <int TZ>
 __global__ void __launch_bounds__(NTHR)
-    k_fwd(Geo g, Pml t, Mdl m, Src src, int S, int groups, int ntx, int ntiles, FwdStep a)
+    k_fwd(Geo g, Pml t, Mdl m, Src src, Rec rec, TileLists tl, int S, int groups, int ntx,
+          int ntiles, FwdStep a)
 {
     constexpr int PH = TZ + 6;      // pressure rows i0-3 .. i0+TZ+2
     constexpr int PW = TX + 6;      // pressure cols j0-3 .. j0+66
@@ -133,6 +134,19 @@ __global__ void __launch_bounds__(NTHR)
             vzo[k] = okz[k] ? vzin[(long long)(i0 - 2 + wave + 4 * k) * g.Nx + jm] : 0.f;
         __syncthreads();
 
+        // receivers whose bilinear cell starts in this tile: sample p_in
+        if (a.sample_n >= 0) {
+            int lo = tl.samp_ptr[s * ntiles + tile], hi = tl.samp_ptr[s * ntiles + tile + 1];
+            for (int e = lo + (int)threadIdx.x; e < hi; e += NTHR) {
+                long long q = (long long)s * rec.nrec + tl.samp_rec[e];
+                long long c = rec.idx[q];
+                float4 w = rec.w[q];
+                int li = (int)(c / g.Nx) - i0 + 3, lj = (int)(c % g.Nx) - j0 + 3;
+                a.traces[q * src.nt + a.sample_n] = w.x * sp[li][lj] + w.y * sp[li][lj + 1] +
+                                                    w.z * sp[li + 1][lj] + w.w * sp[li + 1][lj + 1];
+            }
+        }
+
         // particle velocities at n+1/2 (vx at (i, j+1/2), vz at (i+1/2, j))
         float *vxout = a.vx_out.shot(s);
         float *vzout = a.vz_out.shot(s);
@@ -216,7 +230,8 @@ __global__ void __launch_bounds__(NTHR)
 //   mu_p' = alpha mu_p + D-(beta_h b lv_mid);  lv' = alpha_h lv_mid   (T1^T)
 template <int TZ>
 __global__ void __launch_bounds__(NTHR)
-    k_adj(Geo g, Pml t, Mdl m, Src src, int S, int groups, int ntx, int ntiles, AdjStep a)
+    k_adj(Geo g, Pml t, Mdl m, Inj inj, int nrec, int nt, TileLists tl, int S, int groups,
+          int ntx, int ntiles, AdjStep a)
 {
     constexpr int XW = TX + 6;      // qx cols j0-3 .. j0+66 (tile rows)
     constexpr int ZH = TZ + 6;      // qz rows i0-3 .. i0+TZ+2 (tile cols)
@@ -234,6 +249,7 @@ __global__ void __launch_bounds__(NTHR)
     __shared__ float spn[NH][NW];
     __shared__ float swx[TZ][VW];
     __shared__ float swz[VH][TX];
+    __shared__ float sinj[TZ][TX];   // R^T r for the nodes of the tile
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int item = xcd_item(blockIdx.x, gridDim.x);
@@ -318,6 +334,7 @@ __global__ void __launch_bounds__(NTHR)
             int r = wave + 4 * k;
             long long c = (long long)(i0 + r) * g.Nx;
             mux[k] = okm[k] ? lpx[c + jm] : 0.f;
+            sinj[r][lane] = 0.f;
             sqx[r][lane + 3] = btxm * Km[k] * mux[k];
             if (has_q)
                 sqx[r][eq] = okq[k] ? btxq * Kq[k] * lpx[c + jq] : 0.f;
@@ -364,6 +381,19 @@ __global__ void __launch_bounds__(NTHR)
         for (int k = 0; k < NV; ++k)
             nvz[k] = okw[k] ? lvzi[(long long)(i0 - 2 + wave + 4 * k) * g.Nx + jm] : 0.f;
         __syncthreads();
+
+        // adjoint source of the next (earlier) step at the nodes this tile owns
+        if (a.inject_n >= 0) {
+            int lo = tl.inj_ptr[s * ntiles + tile], hi = tl.inj_ptr[s * ntiles + tile + 1];
+            for (int e = lo + (int)threadIdx.x; e < hi; e += NTHR) {
+                int k = tl.inj_node[e];
+                float acc = 0.f;
+                for (int q = inj.cptr[k]; q < inj.cptr[k + 1]; ++q)
+                    acc += inj.cw[q] * a.resid[((long long)s * nrec + inj.crec[q]) * nt + a.inject_n];
+                long long c = inj.node[k];
+                sinj[(int)(c / g.Nx) - i0][(int)(c % g.Nx) - j0] = acc;
+            }
+        }
 
         float *lvxo = a.lvx_out.shot(s);
         float *lvzo = a.lvz_out.shot(s);
@@ -434,11 +464,11 @@ __global__ void __launch_bounds__(NTHR)
                 float mz = lpz[qi];
                 float z0 = pzn[qi], z1 = pzn1[qi];
                 accK[k] += (mx * ((p1 - z1) - axm * (p0 - z0)) + mz * (z1 - azr[k] * z0)) / Km[k];
-                lpxo[cc] = axm * mx + tsum;
-                lpzo[qi] = azr[k] * mz + tsum;
+                lpxo[cc] = axm * mx + tsum + sinj[r][lane];
+                lpzo[qi] = azr[k] * mz + tsum + sinj[r][lane];
             } else {
                 accK[k] += mx * (p1 - p0) / Km[k];
-                lpxo[cc] = mx + tsum;
+                lpxo[cc] = mx + tsum + sinj[r][lane];
             }
         }
         __syncthreads();
@@ -465,46 +495,53 @@ __global__ void __launch_bounds__(NTHR)
 }
 
 template <int TZ>
-void fwd_launch(const Geo &g, const Pml &t, const Mdl &m, const Src &src, int S, int groups,
-                const FwdStep &a, hipStream_t st)
+void fwd_launch(const Geo &g, const Pml &t, const Mdl &m, const Src &src, const Rec &rec,
+                const TileLists &tl, int S, int groups, const FwdStep &a, hipStream_t st)
 {
-    int ntx = (g.Nx + TX - 1) / TX, ntz = (g.Nz + TZ - 1) / TZ;
-    int ntiles = ntx * ntz;
-    hipLaunchKernelGGL(k_fwd<TZ>, dim3(ntiles * groups), dim3(NTHR), 0, st, g, t, m, src, S,
-                       groups, ntx, ntiles, a);
+    int ntx, ntiles = fused_tiles(g, TZ, &ntx);
+    hipLaunchKernelGGL(k_fwd<TZ>, dim3(ntiles * groups), dim3(NTHR), 0, st, g, t, m, src, rec,
+                       tl, S, groups, ntx, ntiles, a);
 }
 
 template <int TZ>
-void adj_launch(const Geo &g, const Pml &t, const Mdl &m, const Src &src, int S, int groups,
-                const AdjStep &a, hipStream_t st)
+void adj_launch(const Geo &g, const Pml &t, const Mdl &m, const Src &src, const Inj &inj,
+                int nrec, const TileLists &tl, int S, int groups, const AdjStep &a,
+                hipStream_t st)
 {
-    int ntx = (g.Nx + TX - 1) / TX, ntz = (g.Nz + TZ - 1) / TZ;
-    int ntiles = ntx * ntz;
-    hipLaunchKernelGGL(k_adj<TZ>, dim3(ntiles * groups), dim3(NTHR), 0, st, g, t, m, src, S,
-                       groups, ntx, ntiles, a);
+    int ntx, ntiles = fused_tiles(g, TZ, &ntx);
+    hipLaunchKernelGGL(k_adj<TZ>, dim3(ntiles * groups), dim3(NTHR), 0, st, g, t, m, inj, nrec,
+                       src.nt, tl, S, groups, ntx, ntiles, a);
 }
 
 }  // namespace
 
 bool fused_tile_supported(int tz) { return tz == 8 || tz == 16 || tz == 32; }
 
-void launch_fused_fwd(const Geo &g, const Pml &t, const Mdl &m, const Src &src, int S,
-                      int groups, int tz, const FwdStep &a, hipStream_t st)
+int fused_tiles(const Geo &g, int tz, int *ntx)
+{
+    *ntx = (g.Nx + TX - 1) / TX;
+    return *ntx * ((g.Nz + tz - 1) / tz);
+}
+
+void launch_fused_fwd(const Geo &g, const Pml &t, const Mdl &m, const Src &src, const Rec &rec,
+                      const TileLists &tl, int S, int groups, int tz, const FwdStep &a,
+                      hipStream_t st)
 {
     switch (tz) {
-    case 8: fwd_launch<8>(g, t, m, src, S, groups, a, st); break;
-    case 32: fwd_launch<32>(g, t, m, src, S, groups, a, st); break;
-    default: fwd_launch<16>(g, t, m, src, S, groups, a, st); break;
+    case 8: fwd_launch<8>(g, t, m, src, rec, tl, S, groups, a, st); break;
+    case 32: fwd_launch<32>(g, t, m, src, rec, tl, S, groups, a, st); break;
+    default: fwd_launch<16>(g, t, m, src, rec, tl, S, groups, a, st); break;
     }
 }
 
-void launch_fused_adj(const Geo &g, const Pml &t, const Mdl &m, const Src &src, int S,
-                      int groups, int tz, const AdjStep &a, hipStream_t st)
+void launch_fused_adj(const Geo &g, const Pml &t, const Mdl &m, const Src &src, const Inj &inj,
+                      int nrec, const TileLists &tl, int S, int groups, int tz,
+                      const AdjStep &a, hipStream_t st)
 {
     switch (tz) {
-    case 8: adj_launch<8>(g, t, m, src, S, groups, a, st); break;
-    case 32: adj_launch<32>(g, t, m, src, S, groups, a, st); break;
-    default: adj_launch<16>(g, t, m, src, S, groups, a, st); break;
+    case 8: adj_launch<8>(g, t, m, src, inj, nrec, tl, S, groups, a, st); break;
+    case 32: adj_launch<32>(g, t, m, src, inj, nrec, tl, S, groups, a, st); break;
+    default: adj_launch<16>(g, t, m, src, inj, nrec, tl, S, groups, a, st); break;
     }
 }
 

@@ -1,0 +1,32 @@
+"""Autotuner: picks a supported configuration, caches it, and the tuned plan
+computes the same gradient as the default one (within FP32 rounding)."""
+import numpy as np
+import pytest
+
+from paper_1804_01184_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def test_tune_and_cache(tmp_path, monkeypatch):
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1804_01184_amd import api, autotune
+    monkeypatch.setenv("FWI2D_TUNE_CACHE", str(tmp_path / "tune.json"))
+    w = W.gauss_problem(181, 6, 40, 200, npml=16, seed=4)
+    g = api.Grid.of(w)
+    tz, G = autotune.tune(g, w.src_xz, w.rec_xz)
+    Nz, Nx = g.padded
+    assert (tz, G) in autotune.candidates(Nz, Nx, w.nshots)
+    assert (tmp_path / "tune.json").exists()
+    assert autotune.tune(g, w.src_xz, w.rec_xz) == (tz, G)
+    f = w.wavelet()
+    plan_d = api.Plan(g, w.src_xz, w.rec_xz)
+    plan_t = autotune.tuned_plan(g, w.src_xz, w.rec_xz)
+    obs = plan_d.forward("vp-rho", w.vp_true, w.rho_true, f)
+    a = plan_d.gradient("vp-rho", w.vp_start, w.rho_start, f, obs)
+    b = plan_t.gradient("vp-rho", w.vp_start, w.rho_start, f, obs)
+    for x, y in zip(a[1:], b[1:]):
+        x, y = x.cpu().numpy(), y.cpu().numpy()
+        assert np.abs(x - y).max() <= 1e-5 * np.abs(y).max()

@@ -1,0 +1,60 @@
+"""Continuous-batching gradient server: results are the same alone and in the
+mix, admission respects the HBM budget, every request completes."""
+import numpy as np
+import pytest
+
+from paper_1804_01184_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1804_01184_amd import serve
+    return torch, serve
+
+
+def _specs(n=6, seed=21):
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n):
+        out.append({"id": k, "arrival": 0.02 * k, "n": int(rng.integers(81, 161)),
+                    "shots": int(rng.integers(2, 7)), "nt": int(rng.integers(150, 320)),
+                    "contrast": float(rng.uniform(0.05, 0.4)), "seed": int(rng.integers(1 << 30))})
+    return out
+
+
+def test_alone_equals_in_the_mix(env):
+    torch, serve = env
+    reqs = serve.make_requests(_specs(), nrec=48, npml=12)
+    srv = serve.GradientServer(max_slots=3)
+    mixed = srv.run(reqs)
+    assert [r.id for r in mixed] == list(range(len(reqs)))
+    for k in (0, 3, 5):
+        q = reqs[k]
+        q_alone = serve.Request(q.id, 0.0, q.grid, q.src_xz, q.rec_xz, q.param, q.m1, q.m2,
+                                q.wavelet, q.observed)
+        alone = serve.GradientServer(max_slots=1).run([q_alone])[0]
+        np.testing.assert_array_equal(alone.g1.cpu().numpy(), mixed[k].g1.cpu().numpy())
+        np.testing.assert_array_equal(alone.g2.cpu().numpy(), mixed[k].g2.cpu().numpy())
+        assert alone.J == mixed[k].J
+    s = serve.summary(mixed, srv.makespan)
+    assert s["p99_ms"] >= s["p50_ms"] > 0 and s["aggregate_gcells"] > 0
+
+
+def test_admission_respects_budget(env):
+    torch, serve = env
+    reqs = serve.make_requests(_specs(5, seed=3), nrec=32, npml=10)
+    from paper_1804_01184_amd.api import Plan
+    fps = [serve.footprint(Plan(q.grid, q.src_xz, q.rec_xz), q) for q in reqs]
+    budget = int(max(fps) * 1.5)          # at most one big request at a time
+    srv = serve.GradientServer(max_slots=4, hbm_budget=budget)
+    res = srv.run(reqs)
+    assert len(res) == len(reqs)
+    # at any admission instant, the footprints of overlapping jobs fit
+    for r in res:
+        live = [x for x in res if x.admitted <= r.admitted < x.done]
+        assert sum(x.footprint for x in live) <= budget

@@ -1,0 +1,40 @@
+"""Host-side logic that needs no GPU: autotuner candidate sets, workload
+generators (seeded, reproducible, shapes of the configurations)."""
+import numpy as np
+
+from paper_1804_01184_amd import workloads as W
+
+
+def test_candidates_cover_tiles_and_groups():
+    from paper_1804_01184_amd import autotune
+    c = autotune.candidates(481, 481, 40)
+    assert {tz for tz, _ in c} == {8, 16, 32}
+    for tz, G in c:
+        assert 1 <= G <= 40
+    assert autotune.candidates(21, 21, 1) == [(8, 1), (16, 1), (32, 1)]
+
+
+def test_workloads_seeded_and_shaped():
+    a, b = W.config2(), W.config2()
+    np.testing.assert_array_equal(a.vp_true, b.vp_true)
+    assert a.padded == (481, 481) and a.nshots == 40 and a.nrec == 360 and a.nt == 2000
+    assert 0.05 <= abs(a.meta["contrast"]) <= 0.40
+    assert abs(a.vmax * a.dt / a.dx - 0.5) < 1e-12
+    c1 = W.config1()
+    assert c1.padded == (141, 141) and c1.nt == 600 and c1.nrec == 180
+    K = c1.rho_true * c1.vp_true ** 2
+    K0 = c1.rho_start * c1.vp_start ** 2
+    assert np.isclose(K[50, 50] / K0[50, 50], 1.1) and np.count_nonzero(K != K0) == 1
+    # every receiver and source inside the physical grid with a margin
+    for w in (a, c1):
+        for xz in (w.src_xz.reshape(-1, 2), w.rec_xz.reshape(-1, 2)):
+            assert xz.min() >= 2 * w.dx and xz.max() <= (w.nx - 3) * w.dx
+
+
+def test_serving_request_stream_seeded():
+    r1 = W.serving_requests(50)
+    r2 = W.serving_requests(50)
+    assert r1 == r2
+    assert all(201 <= r["n"] <= 1201 and 8 <= r["shots"] <= 64 and 1000 <= r["nt"] <= 4000
+               for r in r1)
+    assert all(r1[k]["arrival"] < r1[k + 1]["arrival"] for k in range(49))
