@@ -32,8 +32,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2", choices=["c2", "c3"])
-    ap.add_argument("--tile-z", type=int, default=0)
-    ap.add_argument("--shot-groups", type=int, default=0)
+    ap.add_argument("--band-rows", type=int, default=0)
+    ap.add_argument("--shots-per-group", type=int, default=0)
     ap.add_argument("--ckpt-every", type=int, default=0)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
@@ -102,8 +102,8 @@ def main():
     f = torch.tensor(w.wavelet(), dtype=torch.float32, device=dev)
     vp0 = torch.tensor(w.vp_start, dtype=torch.float32, device=dev)
     rho0 = torch.tensor(w.rho_start, dtype=torch.float32, device=dev)
-    plan = api.Plan(grid, w.src_xz, w.rec_xz, tile_z=args.tile_z,
-                    shot_groups=args.shot_groups, ckpt_every=args.ckpt_every)
+    plan = api.Plan(grid, w.src_xz, w.rec_xz, band_rows=args.band_rows,
+                    shots_per_group=args.shots_per_group, ckpt_every=args.ckpt_every)
     info = plan.info
     obs = plan.forward("vp-rho", w.vp_true, w.rho_true, f)
     K0, r0 = api.model_convert("vp-rho", "k-rho", vp0, rho0)
@@ -183,7 +183,8 @@ def main():
                                f"({info['Nz']}x{info['Nx']} padded), {w.nt} steps, "
                                f"{w.nshots} shots x {w.nrec} receivers, gradient in K-rho "
                                f"chain-ruled to Vp-rho, Ip-rho, Vp-Ip",
-                   "cell_steps": cells, "tile_z": info["tile_z"], "shot_groups": G,
+                   "cell_steps": cells, "band_rows": info["band_rows"],
+                   "shots_per_group": info["shots_per_group"], "shot_groups": G,
                    "ckpt_every": info["ckpt_every"], "segments": info["segments"]},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
                        "p99": round(float(np.percentile(lat, 99)), 3)},

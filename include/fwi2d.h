@@ -107,16 +107,18 @@ typedef struct {
     int32_t mode;         /* fwi_exec_mode                                    */
     int32_t ckpt_every;   /* forward states kept every k steps; 0: ceil(sqrt(nt));
                              >= nt keeps the whole pressure history            */
-    int32_t tile_z;       /* batched kernels: tile rows 8, 16 or 32; 0: default */
-    int32_t shot_groups;  /* batched kernels: shots split into this many groups
-                             sweeping a tile (1..nshots); 0: default           */
+    int32_t band_rows;    /* batched kernels: rows each wave sweeps (4..4096);
+                             0: chosen from the grid and shot count          */
+    int32_t shots_per_group; /* batched kernels: shots a wave advances together,
+                             1, 2, 4 or 8; 0: default                         */
 } fwi_exec;
 
 typedef struct {
     int32_t Nz, Nx;           /* padded grid                                  */
     int32_t ckpt_every;       /* k actually used                              */
     int32_t segments;         /* ceil(nt / k)                                 */
-    int32_t tile_z, shot_groups;
+    int32_t band_rows, shots_per_group;
+    int32_t shot_groups;      /* ceil(nshots / shots_per_group)               */
     int32_t mode;
     int32_t device;           /* HIP device the plan lives on                 */
     int64_t pml_cells;        /* cells of the absorbing layer                 */

@@ -1,11 +1,12 @@
-"""Tile-shape / shot-group autotuner for the batched kernels.
+"""Decomposition autotuner for the batched kernels.
 
 For a problem shape (padded grid, shots) it times the batched forward and
-adjoint step kernels of each candidate (tile rows, shot groups) on a short run
-of the real grid and shot count, using the library's per-launch HIP event
-timing, and keeps the configuration with the lowest cost of one gradient
-time step (two forward-type steps — forward and recompute — plus one adjoint
-step).  Results are cached in a JSON file keyed by the shape and the GPU.
+adjoint step kernels of each candidate (band rows swept per wave, shots
+advanced together per wave) on a short run of the real grid and shot count,
+using the library's per-launch HIP event timing, and keeps the configuration
+with the lowest cost of one gradient time step (two forward-type steps —
+forward and recompute — plus one adjoint step).  Results are cached in a JSON
+file keyed by the shape and the GPU.
 """
 from __future__ import annotations
 
@@ -19,7 +20,9 @@ import torch
 from . import _lib as L
 from .api import Grid, Plan
 
-TILES = (8, 16, 32)
+ROWS = (8, 12, 16, 24, 32, 48, 64, 96, 128)
+SPGS = (1, 2, 4, 8)
+STRIP = 58    # output columns per wave strip
 
 
 def cache_path():
@@ -39,18 +42,19 @@ def _arch():
 
 
 def candidates(Nz, Nx, S):
+    """(band_rows, shots_per_group) pairs giving between 512 and 32768 waves."""
     out = []
-    for tz in TILES:
-        ntiles = ((Nx + 63) // 64) * ((Nz + tz - 1) // tz)
-        g = 1
-        while g <= S:
-            blocks = ntiles * g
-            if 128 <= blocks <= 32768 or (g == 1 and blocks > 32768) or \
-                    (g == S and blocks < 128):
-                out.append((tz, g))
-            g *= 2
-        if S not in [c[1] for c in out if c[0] == tz] and 128 <= ntiles * S <= 32768:
-            out.append((tz, S))
+    strips = (Nx + STRIP - 1) // STRIP
+    for spg in SPGS:
+        if spg > 1 and spg > 2 * S:
+            continue
+        groups = (S + spg - 1) // spg
+        for H in ROWS:
+            waves = strips * ((Nz + H - 1) // H) * groups
+            if 512 <= waves <= 32768:
+                out.append((H, spg))
+        if not [c for c in out if c[1] == spg]:
+            out.append((min(ROWS), spg))
     return sorted(set(out))
 
 
@@ -71,11 +75,11 @@ def save_cache(c):
     os.replace(tmp, p)
 
 
-def measure(grid: Grid, src_xz, rec_xz, tile_z, groups, nt_probe=24, reps=2, device=None):
+def measure(grid: Grid, src_xz, rec_xz, band_rows, spg, nt_probe=24, reps=2, device=None):
     """Per-step device time (ms) of the batched forward and adjoint kernels."""
     g = Grid(grid.nz, grid.nx, grid.dz, grid.dx, grid.npml, nt_probe, grid.dt, grid.vmax,
              grid.pml_r)
-    plan = Plan(g, src_xz, rec_xz, tile_z=tile_z, shot_groups=groups,
+    plan = Plan(g, src_xz, rec_xz, band_rows=band_rows, shots_per_group=spg,
                 ckpt_every=max(2, nt_probe // 4), device=device)
     dev = plan.device
     K = torch.full((grid.nz, grid.nx), 2000.0 * 2000.0 ** 2, device=dev)
@@ -96,7 +100,7 @@ def measure(grid: Grid, src_xz, rec_xz, tile_z, groups, nt_probe=24, reps=2, dev
 
 
 def tune(grid: Grid, src_xz, rec_xz, force=False, verbose=False, device=None):
-    """(tile_z, shot_groups) for this shape, from the cache or by measuring."""
+    """(band_rows, shots_per_group) for this shape, from the cache or by measuring."""
     src = np.asarray(src_xz).reshape(-1, 2)
     S = src.shape[0]
     Nz, Nx = grid.padded
@@ -106,25 +110,26 @@ def tune(grid: Grid, src_xz, rec_xz, force=False, verbose=False, device=None):
         return tuple(cache[key]["best"])
     results = []
     t0 = time.perf_counter()
-    for tz, G in candidates(Nz, Nx, S):
-        fwd, adj = measure(grid, src_xz, rec_xz, tz, G, device=device)
+    for H, spg in candidates(Nz, Nx, S):
+        fwd, adj = measure(grid, src_xz, rec_xz, H, spg, device=device)
         cost = 2.0 * fwd + adj
-        results.append({"tile_z": tz, "groups": G, "fwd_ms": fwd, "adj_ms": adj, "cost": cost})
+        results.append({"band_rows": H, "spg": spg, "fwd_ms": fwd, "adj_ms": adj,
+                        "cost": cost})
         if verbose:
-            print(f"  tile_z={tz:2d} groups={G:3d}: fwd {fwd * 1e3:8.1f} us  "
+            print(f"  band_rows={H:4d} spg={spg}: fwd {fwd * 1e3:8.1f} us  "
                   f"adj {adj * 1e3:8.1f} us", flush=True)
     best = min(results, key=lambda r: r["cost"])
     cache = load_cache()
-    cache[key] = {"best": [best["tile_z"], best["groups"]], "results": results,
+    cache[key] = {"best": [best["band_rows"], best["spg"]], "results": results,
                   "seconds": time.perf_counter() - t0}
     save_cache(cache)
-    return best["tile_z"], best["groups"]
+    return best["band_rows"], best["spg"]
 
 
 def tuned_plan(grid: Grid, src_xz, rec_xz, **kw):
-    """A batched Plan with the tuned tile shape and shot groups."""
-    tz, G = tune(grid, src_xz, rec_xz, device=kw.get("device"))
-    return Plan(grid, src_xz, rec_xz, tile_z=tz, shot_groups=G, **kw)
+    """A batched Plan with the tuned decomposition."""
+    H, spg = tune(grid, src_xz, rec_xz, device=kw.get("device"))
+    return Plan(grid, src_xz, rec_xz, band_rows=H, shots_per_group=spg, **kw)
 
 
 __all__ = ["tune", "tuned_plan", "candidates", "measure", "L"]

@@ -48,7 +48,9 @@ double stability_number(const fwi_grid &g)
 struct fwi_plan {
     fwi_grid grid;
     int S, nrec, per_shot;
-    int mode, k, nseg, tile_z, groups;
+    int Spad;   // shots of a batched launch: S padded to whole shot groups
+    int mode, k, nseg;
+    Sweep sweep;   // batched decomposition (band rows, shots per group)
     int device;
     Geo geo;
     long long SS, ST;  // per-shot floats of a state record / a store record
@@ -64,9 +66,10 @@ struct fwi_plan {
     float *inj_cw = nullptr;
     int inj_nodes = 0;
     std::vector<int> shot_node_ptr;  // [S+1] node range of each shot
-    // per-(shot, tile) lists of the batched kernels
-    int *tl_samp_ptr = nullptr, *tl_samp_rec = nullptr;
-    int *tl_inj_ptr = nullptr, *tl_inj_node = nullptr;
+    // per-(shot, band, strip) lists of the batched kernels
+    int *wl_samp_ptr = nullptr, *wl_inj_ptr = nullptr;
+    int4 *wl_samp = nullptr, *wl_inj = nullptr;
+    SweepTables *sweep_tabs = nullptr;   // device copy of the table pointers
     std::vector<int2> h_src_ij;
     std::vector<float4> h_src_w;
     // per-launch event timing (instrumentation)
@@ -140,12 +143,12 @@ fwi_status collect_marks(fwi_plan *p)
 struct Layout {
     size_t Kphys, rhophys, Kpad, bx, bz, Q;
     size_t work[2], lam[2];
-    size_t ckpt, store, gpart, traces, resid, partials;
+    size_t ckpt, store, gpart, fold, traces, resid, partials;
     size_t total;
 };
 
-int batch_of(const fwi_plan *p) { return p->mode == FWI_EXEC_PLAIN ? 1 : p->S; }
-int groups_of(const fwi_plan *p) { return p->mode == FWI_EXEC_PLAIN ? 1 : p->groups; }
+int batch_of(const fwi_plan *p) { return p->mode == FWI_EXEC_PLAIN ? 1 : p->Spad; }
+int groups_of(const fwi_plan *p) { return p->mode == FWI_EXEC_PLAIN ? 1 : p->sweep.ngroups; }
 
 Layout layout(const fwi_plan *p, int op)
 {
@@ -167,9 +170,10 @@ Layout layout(const fwi_plan *p, int op)
     }
     L.Kphys = take(nphys);
     L.rhophys = take(nphys);
-    L.Kpad = take(g.N);
-    L.bx = take(g.N);
-    L.bz = take(g.N);
+    // K, bx, bz as one block (the batched kernels address them from K)
+    L.Kpad = take(3 * g.N);
+    L.bx = L.Kpad + g.N * sizeof(float);
+    L.bz = L.Kpad + 2 * g.N * sizeof(float);
     L.Q = take((size_t)p->S * p->grid.nt);
     L.work[0] = take((size_t)B * p->SS);
     L.work[1] = take((size_t)B * p->SS);
@@ -179,6 +183,7 @@ Layout layout(const fwi_plan *p, int op)
         L.ckpt = take((size_t)(p->nseg - 1) * B * p->SS);
         L.store = take((size_t)(p->k + 1) * B * p->ST);
         L.gpart = take((size_t)groups_of(p) * 3 * g.N);
+        L.fold = take(2 * (size_t)g.N);
         L.traces = take(ntr);
         L.resid = take(ntr);
         L.partials = take(misfit_blocks(ntr));
@@ -291,9 +296,14 @@ Inj inj_of(const Ctx &c, int s0, int nb)
     return in;
 }
 
-TileLists tiles_of(const fwi_plan *p)
+// Real (not padding) shots among [s0, s0 + nb).
+int real_shots(const fwi_plan *p, int s0, int nb) { return std::max(0, std::min(nb, p->S - s0)); }
+
+// Record descriptor of a batch: `f` is the first field of the record, the
+// record spans `floats` floats from there.
+Recd recd(const Fld &f, long long floats)
 {
-    return TileLists{p->tl_samp_ptr, p->tl_samp_rec, p->tl_inj_ptr, p->tl_inj_node};
+    return Recd{f.p, (unsigned)(f.ss * sizeof(float)), (unsigned)(floats * sizeof(float))};
 }
 
 // One forward step n -> n+1 for shots [s0, s0+nb) from `in` to `out`.  The
@@ -313,11 +323,19 @@ void step_fwd(const Ctx &c, int s0, int nb, const State &in, const State &out, i
         launch_plain_pres(g, c.t, c.m, out.vx.p, out.vz.p, in.p.p, in.pz.p, out.p.p, out.pz.p,
                           p->h_src_ij[s0], p->h_src_w[s0], src.Q, n, c.st);
     } else {
-        FwdStep a{in.vx, in.vz, in.p, in.pz, out.vx, out.vz, out.p, out.pz, n,
-                  (traces && n > 0) ? n - 1 : -1, traces};
+        // velocity records: vx then vz; pressure records: p then its split,
+        // N floats apart in state records and store slots alike
+        FwdStep a;
+        a.vin = recd(in.vx, 2 * g.N);
+        a.pin = recd(in.p, g.N + g.Npml);
+        a.vout = recd(out.vx, 2 * g.N);
+        a.pout = recd(out.p, g.N + g.Npml);
+        a.Q = src.Q;
+        a.traces = traces;
+        a.n = n;
+        a.sample_n = (traces && n > 0) ? n - 1 : -1;
         Timed tm(c.pl, c.st, FWI_KC_FWD_STEP);
-        launch_fused_fwd(g, c.t, c.m, src, rec_of(c, s0), tiles_of(p), nb, p->groups, p->tile_z,
-                         a, c.st);
+        launch_fused_fwd(g, p->pml, c.m.K, p->sweep_tabs, p->S, p->sweep, a, c.st);
     }
 }
 
@@ -333,7 +351,8 @@ void step_adj(const Ctx &c, int s0, int nb, const State &in, const State &out, F
     // except for the first adjoint step
     if (p->mode == FWI_EXEC_PLAIN || n == p->grid.nt - 1) {
         Timed tm(c.pl, c.st, FWI_KC_INJECT);
-        launch_inject(g, inj_of(c, s0, nb), resid, p->nrec, p->grid.nt, n, in.p, s0, c.st);
+        launch_inject(g, inj_of(c, s0, real_shots(p, s0, nb)), resid, p->nrec, p->grid.nt, n,
+                      in.p, s0, c.st);
     }
     if (p->mode == FWI_EXEC_PLAIN) {
         {
@@ -346,11 +365,20 @@ void step_adj(const Ctx &c, int s0, int nb, const State &in, const State &out, F
         launch_plain_adj_b(g, c.t, c.m, out.vx.p, out.vz.p, in.p.p, in.pz.p, out.p.p, out.pz.p,
                            c.st);
     } else {
-        AdjStep a{in.vx, in.vz, in.p, in.pz, out.vx, out.vz, out.p, out.pz,
-                  pn, pzn, pn1, pzn1, gpart, n, n > 0 ? n - 1 : -1, resid};
+        // adjoint records: lvx, lvz, lpx, lpz; pressure history: p then split
+        (void)pzn;
+        (void)pzn1;
+        AdjStep a;
+        a.lin = recd(in.vx, 3 * g.N + g.Npml);
+        a.lout = recd(out.vx, 3 * g.N + g.Npml);
+        a.pn = recd(pn, g.N + g.Npml);
+        a.pn1 = recd(pn1, g.N + g.Npml);
+        a.gpart = gpart;
+        a.resid = resid;
+        a.n = n;
+        a.inject_n = n > 0 ? n - 1 : -1;
         Timed tm(c.pl, c.st, FWI_KC_ADJ_STEP);
-        launch_fused_adj(g, c.t, c.m, src_of(c, s0), inj_of(c, s0, nb), p->nrec, tiles_of(p), nb,
-                         p->groups, p->tile_z, a, c.st);
+        launch_fused_adj(g, p->pml, c.m.K, p->sweep_tabs, p->S, p->sweep, a, c.st);
     }
 }
 
@@ -396,7 +424,7 @@ void sweep_forward(const Ctx &c, int s0, int nb, bool keep, float *traces)
         step_fwd(c, s0, nb, cur, out, n, batched ? traces : nullptr);
         if (traces && (!batched || n == nt - 1)) {
             Timed tm(c.pl, c.st, FWI_KC_SAMPLE);
-            launch_sample(p->geo, out.p, out.pz, rec, nb, traces, nt, n, c.st);
+            launch_sample(p->geo, out.p, out.pz, rec, real_shots(p, s0, nb), traces, nt, n, c.st);
         }
         cur = out;
         cw = next_cw;
@@ -528,11 +556,11 @@ fwi_status run_backward(const Ctx &c, int param, const float *m1, const float *m
             sweep_backward(c, s, 1, res, gpart);
         }
     } else {
-        sweep_backward(c, 0, p->S, res, gpart);
+        sweep_backward(c, 0, p->Spad, res, gpart);
     }
     {
         Timed tm(p, c.st, FWI_KC_OTHER);
-        launch_finalize(g, param, m1, m2, c.m.bx, c.m.bz, gpart, G, g1, g2, c.st);
+        launch_finalize(g, param, m1, m2, c.m.bx, c.m.bz, gpart, G, c.f(c.L.fold), g1, g2, c.st);
     }
     return launched("gradient");
 }
@@ -578,11 +606,12 @@ fwi_status run_gradient(fwi_plan *p, int param, const float *m1, const float *m2
         }
         {
             Timed tm(p, c.st, FWI_KC_OTHER);
-            launch_finalize(g, param, m1, m2, c.m.bx, c.m.bz, gpart, 1, g1, g2, c.st);
+            launch_finalize(g, param, m1, m2, c.m.bx, c.m.bz, gpart, 1, c.f(c.L.fold), g1, g2,
+                            c.st);
         }
         return launched("gradient");
     }
-    sweep_forward(c, 0, p->S, true, observed ? tr : nullptr);
+    sweep_forward(c, 0, p->Spad, true, observed ? tr : nullptr);
     const float *res = adj_src;
     if (observed) {
         Timed tm(p, c.st, FWI_KC_OTHER);
@@ -643,10 +672,13 @@ fwi_status fwi_plan_create(const fwi_grid *grid, const fwi_acq *acq, const fwi_e
         ex = *exec;
     if (ex.mode != FWI_EXEC_BATCHED && ex.mode != FWI_EXEC_PLAIN)
         return fail(FWI_EINVAL, "unknown exec mode %d", ex.mode);
-    if (ex.tile_z != 0 && !fused_tile_supported(ex.tile_z))
-        return fail(FWI_EINVAL, "tile_z %d not supported (8, 16 or 32)", ex.tile_z);
-    if (ex.shot_groups < 0 || ex.shot_groups > acq->nshots || ex.ckpt_every < 0)
-        return fail(FWI_EINVAL, "shot_groups or ckpt_every out of range");
+    if (ex.band_rows != 0 && (ex.band_rows < 4 || ex.band_rows > 4096))
+        return fail(FWI_EINVAL, "band_rows %d out of range (4..4096)", ex.band_rows);
+    if (ex.shots_per_group != 0 && !fused_spg_supported(ex.shots_per_group))
+        return fail(FWI_EINVAL, "shots_per_group %d not supported (1, 2, 4 or 8)",
+                    ex.shots_per_group);
+    if (ex.ckpt_every < 0)
+        return fail(FWI_EINVAL, "ckpt_every out of range");
 
     fwi_plan *p = new fwi_plan();
     p->grid = G;
@@ -676,12 +708,31 @@ fwi_status fwi_plan_create(const fwi_grid *grid, const fwi_acq *acq, const fwi_e
     }
     p->k = std::max(1, std::min(k, G.nt));
     p->nseg = (G.nt + p->k - 1) / p->k;
-    p->tile_z = ex.tile_z ? ex.tile_z : 16;
-    int ntiles = (int)(((Nx + 63) / 64) * ((Nz + p->tile_z - 1) / p->tile_z));
-    int groups = ex.shot_groups;
-    if (groups == 0)
-        groups = std::max(1, std::min(p->S, (2048 + ntiles - 1) / ntiles));
-    p->groups = groups;
+    {
+        // shots advanced together by a wave; band height so that the launch
+        // has about 2048 waves (8 per CU)
+        int spg = ex.shots_per_group;
+        if (spg == 0)
+            spg = p->S >= 4 ? 4 : (p->S >= 2 ? 2 : 1);
+        int H = ex.band_rows;
+        if (H == 0) {
+            Sweep one = sweep_of(g, p->S, (int)Nz, spg);
+            long long per_band = (long long)one.nstrips * one.ngroups;
+            long long bands = std::max<long long>(1, (2048 + per_band - 1) / per_band);
+            H = (int)std::min<long long>(256, std::max<long long>(8, (Nz + bands - 1) / bands));
+        }
+        p->sweep = sweep_of(g, p->S, H, spg);
+        p->Spad = p->mode == FWI_EXEC_PLAIN ? p->S : p->sweep.ngroups * spg;
+        // the batched kernels address a shot group's records, the model and
+        // a partial gradient with 32-bit byte offsets below 2^31
+        const long long lim = (1LL << 31) - 64LL * Nx;
+        if (p->mode != FWI_EXEC_PLAIN &&
+            ((long long)spg * p->SS * 4 >= lim || 3 * g.N * 4 >= lim)) {
+            delete p;
+            return fail(FWI_EINVAL, "grid of %lld cells too large for %d shots per group "
+                        "(records of a group must stay below 2 GiB)", (long long)g.N, spg);
+        }
+    }
 
     // geometry: bilinear cell and weights of every source and receiver
     const int S = p->S, nr = p->nrec;
@@ -760,37 +811,40 @@ fwi_status fwi_plan_create(const fwi_grid *grid, const fwi_acq *acq, const fwi_e
     inj_cptr.push_back((int)inj_crec.size());
     p->inj_nodes = (int)inj_node.size();
 
-    // per-(shot, tile) lists for the batched kernels
-    int ntx;
-    const int ntl = fused_tiles(g, p->tile_z, &ntx);
-    auto tile_of = [&](long long c) {
-        int i = (int)(c / g.Nx), j = (int)(c % g.Nx);
-        return (i / p->tile_z) * ntx + j / 64;
-    };
-    std::vector<int> samp_ptr((size_t)S * ntl + 1, 0), samp_rec;
-    std::vector<int> tinj_ptr((size_t)S * ntl + 1, 0), tinj_node;
+    // per-(shot, band, strip) lists for the batched kernels, sorted by row
+    const Sweep &sw = p->sweep;
+    const int nlist = S * sw.nbands * sw.nstrips;
+    std::vector<int> samp_ptr((size_t)nlist + 1, 0), inj_ptr2((size_t)nlist + 1, 0);
+    std::vector<int4> samp_e, inj_e;
     {
-        std::vector<std::vector<int>> bucket(ntl);
-        for (int s = 0; s < S; ++s) {
-            for (auto &b : bucket)
+        std::vector<std::vector<int4>> bucket(nlist);
+        auto place = [&](int s, long long c, int idx) {
+            int i = (int)(c / g.Nx), j = (int)(c % g.Nx);
+            int strip = j / kStripOut, band = i / sw.H;
+            int lane = j - strip * kStripOut + 3;
+            bucket[((size_t)s * sw.nbands + band) * sw.nstrips + strip].push_back(
+                make_int4(i, lane, idx, 0));
+        };
+        auto flatten = [&](std::vector<int> &ptr, std::vector<int4> &out) {
+            for (int l = 0; l < nlist; ++l) {
+                auto &b = bucket[l];
+                std::stable_sort(b.begin(), b.end(), [](const int4 &x, const int4 &y) {
+                    return x.x != y.x ? x.x < y.x : x.y < y.y;
+                });
+                out.insert(out.end(), b.begin(), b.end());
+                ptr[l + 1] = (int)out.size();
                 b.clear();
+            }
+        };
+        for (int s = 0; s < S; ++s)
             for (int r = 0; r < nr; ++r)
-                bucket[tile_of(rec_idx[(size_t)s * nr + r])].push_back(r);
-            for (int t = 0; t < ntl; ++t) {
-                samp_rec.insert(samp_rec.end(), bucket[t].begin(), bucket[t].end());
-                samp_ptr[(size_t)s * ntl + t + 1] = (int)samp_rec.size();
-            }
-            for (auto &b : bucket)
-                b.clear();
+                place(s, rec_idx[(size_t)s * nr + r], r);
+        flatten(samp_ptr, samp_e);
+        for (int s = 0; s < S; ++s)
             for (int k = p->shot_node_ptr[s]; k < p->shot_node_ptr[s + 1]; ++k)
-                bucket[tile_of(inj_node[k])].push_back(k);
-            for (int t = 0; t < ntl; ++t) {
-                tinj_node.insert(tinj_node.end(), bucket[t].begin(), bucket[t].end());
-                tinj_ptr[(size_t)s * ntl + t + 1] = (int)tinj_node.size();
-            }
-        }
+                place(s, inj_node[k], k);
+        flatten(inj_ptr2, inj_e);
     }
-
     if (hipGetDevice(&p->device) != hipSuccess) {
         delete p;
         return fail(FWI_EDEVICE, "no HIP device");
@@ -810,8 +864,9 @@ fwi_status fwi_plan_create(const fwi_grid *grid, const fwi_acq *acq, const fwi_e
     size_t o_ip = take(sizeof(int) * inj_cptr.size());
     size_t o_ir = take(sizeof(int) * inj_crec.size());
     size_t o_iw = take(sizeof(float) * inj_cw.size());
-    size_t o_tsp = take(sizeof(int) * samp_ptr.size()), o_tsr = take(sizeof(int) * samp_rec.size());
-    size_t o_tip = take(sizeof(int) * tinj_ptr.size()), o_tin = take(sizeof(int) * tinj_node.size());
+    size_t o_wsp = take(sizeof(int) * samp_ptr.size()), o_ws = take(sizeof(int4) * samp_e.size());
+    size_t o_wip = take(sizeof(int) * inj_ptr2.size()), o_wi = take(sizeof(int4) * inj_e.size());
+    size_t o_st = take(sizeof(SweepTables));
     if (hipMalloc(&p->dev, off) != hipSuccess) {
         (void)hipGetLastError();
         delete p;
@@ -828,10 +883,24 @@ fwi_status fwi_plan_create(const fwi_grid *grid, const fwi_acq *acq, const fwi_e
     p->inj_cptr = (int *)(d + o_ip);
     p->inj_crec = (int *)(d + o_ir);
     p->inj_cw = (float *)(d + o_iw);
-    p->tl_samp_ptr = (int *)(d + o_tsp);
-    p->tl_samp_rec = (int *)(d + o_tsr);
-    p->tl_inj_ptr = (int *)(d + o_tip);
-    p->tl_inj_node = (int *)(d + o_tin);
+    p->wl_samp_ptr = (int *)(d + o_wsp);
+    p->wl_samp = (int4 *)(d + o_ws);
+    p->wl_inj_ptr = (int *)(d + o_wip);
+    p->wl_inj = (int4 *)(d + o_wi);
+    p->sweep_tabs = (SweepTables *)(d + o_st);
+    SweepTables st_host;
+    st_host.src_ij = p->src_ij;
+    st_host.src_w = p->src_w;
+    st_host.rec_w = p->rec_w;
+    st_host.samp_ptr = p->wl_samp_ptr;
+    st_host.samp = p->wl_samp;
+    st_host.inj_ptr = p->wl_inj_ptr;
+    st_host.inj = p->wl_inj;
+    st_host.inj_cptr = p->inj_cptr;
+    st_host.inj_crec = p->inj_crec;
+    st_host.inj_cw = p->inj_cw;
+    st_host.nrec = p->nrec;
+    st_host.nt = G.nt;
     bool ok = true;
     auto up = [&](void *dst, const void *src, size_t bytes) {
         if (bytes && hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) != hipSuccess)
@@ -846,10 +915,11 @@ fwi_status fwi_plan_create(const fwi_grid *grid, const fwi_acq *acq, const fwi_e
     up(p->inj_cptr, inj_cptr.data(), sizeof(int) * inj_cptr.size());
     up(p->inj_crec, inj_crec.data(), sizeof(int) * inj_crec.size());
     up(p->inj_cw, inj_cw.data(), sizeof(float) * inj_cw.size());
-    up(p->tl_samp_ptr, samp_ptr.data(), sizeof(int) * samp_ptr.size());
-    up(p->tl_samp_rec, samp_rec.data(), sizeof(int) * samp_rec.size());
-    up(p->tl_inj_ptr, tinj_ptr.data(), sizeof(int) * tinj_ptr.size());
-    up(p->tl_inj_node, tinj_node.data(), sizeof(int) * tinj_node.size());
+    up(p->wl_samp_ptr, samp_ptr.data(), sizeof(int) * samp_ptr.size());
+    up(p->wl_samp, samp_e.data(), sizeof(int4) * samp_e.size());
+    up(p->wl_inj_ptr, inj_ptr2.data(), sizeof(int) * inj_ptr2.size());
+    up(p->wl_inj, inj_e.data(), sizeof(int4) * inj_e.size());
+    up(p->sweep_tabs, &st_host, sizeof(SweepTables));
     launch_pml_tables(g, G.vmax, G.npml > 0 ? G.pml_r : 0.5, G.dx, G.dz, G.dt, p->pml, nullptr);
     if (!ok || hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
         (void)hipFree(p->dev);
@@ -880,7 +950,8 @@ fwi_status fwi_plan_get_info(const fwi_plan *p, fwi_plan_info *info)
     info->Nx = p->geo.Nx;
     info->ckpt_every = p->k;
     info->segments = p->nseg;
-    info->tile_z = p->tile_z;
+    info->band_rows = p->sweep.H;
+    info->shots_per_group = p->mode == FWI_EXEC_PLAIN ? 1 : p->sweep.spg;
     info->shot_groups = groups_of(p);
     info->mode = p->mode;
     info->device = p->device;
@@ -914,7 +985,7 @@ fwi_status fwi_forward(fwi_plan *p, int32_t param, const float *m1, const float 
         for (int s = 0; s < p->S; ++s)
             sweep_forward(c, s, 1, false, traces + s * per_shot);
     } else {
-        sweep_forward(c, 0, p->S, false, traces);
+        sweep_forward(c, 0, p->Spad, false, traces);
     }
     return launched("forward");
 }
@@ -979,7 +1050,7 @@ fwi_status fwi_forward_keep(fwi_plan *p, int32_t param, const float *m1, const f
         for (int s = 0; s < p->S; ++s)
             sweep_forward(c, s, 1, false, traces + s * per_shot);
     } else {
-        sweep_forward(c, 0, p->S, true, traces);
+        sweep_forward(c, 0, p->Spad, true, traces);
     }
     p->kept_ws = ws;
     return launched("forward_keep");

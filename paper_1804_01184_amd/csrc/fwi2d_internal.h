@@ -106,9 +106,10 @@ void launch_inject(const Geo &g, const Inj &inj, const float *resid, int nrec, i
 void launch_misfit(const float *d, const float *dobs, float *resid, long long n,
                    float *partials, int nblocks, float *J, hipStream_t st);
 int misfit_blocks(long long n);
+// fold: scratch of 2 N floats.
 void launch_finalize(const Geo &g, int param, const float *m1, const float *m2,
                      const float *bx, const float *bz, const float *gpart, int groups,
-                     float *g1, float *g2, hipStream_t st);
+                     float *fold, float *g1, float *g2, hipStream_t st);
 void launch_convert(int from, int to, long long n, const float *a1, const float *a2, float *b1,
                     float *b2, hipStream_t st);
 void launch_chain_rule(int param, long long n, const float *m1, const float *m2,
@@ -136,40 +137,73 @@ void launch_plain_adj_b(const Geo &g, const Pml &t, const Mdl &m, const float *l
                         float *lpx_out, float *lpz_out, hipStream_t st);
 
 // ----------------------------------------------------------------- fused
-// Per-(shot, tile) work lists of the batched kernels, CSR over shot * ntiles
-// + tile: receivers whose bilinear cell starts in the tile (sampling), and
-// receiver-touched nodes the tile owns (adjoint injection; entries index the
-// Inj node table).
-struct TileLists {
-    const int *samp_ptr;   // [S * ntiles + 1]
-    const int *samp_rec;   // receiver index
-    const int *inj_ptr;    // [S * ntiles + 1]
-    const int *inj_node;   // index into Inj
+// Decomposition of the batched kernels: each wave64 owns a strip of
+// kStripOut output columns (plus a 3-column halo each side) and a band of H
+// rows, for a group of spg shots.  Wave w -> (group, band, strip), strip
+// fastest.
+constexpr int kStripOut = 58;
+struct Sweep {
+    int nstrips, nbands, ngroups, nwaves;
+    int H;     // band rows
+    int spg;   // shots per group
+};
+
+// Geometry tables of a plan for the batched kernels, kept in device memory
+// so that the kernels take one pointer to them.  samp / inj are per-(shot,
+// band, strip) work lists, CSR over (shot * nbands + band) * nstrips +
+// strip, entries (row, lane, index, 0) sorted by row: receivers whose
+// bilinear cell starts at (row, lane) (index = receiver), and
+// receiver-touched nodes (index = entry of inj_cptr).
+struct SweepTables {
+    const int2 *src_ij;
+    const float4 *src_w;
+    const float4 *rec_w;      // [S][nrec]
+    const int *samp_ptr;
+    const int4 *samp;
+    const int *inj_ptr;
+    const int4 *inj;
+    const int *inj_cptr;
+    const int *inj_crec;
+    const float *inj_cw;
+    int nrec, nt;
+};
+
+// The records of a batch of shots: shot s starts at base + s * sbytes bytes
+// and spans `bytes`.  A velocity record holds vx and vz N floats apart; a
+// pressure record holds p and its absorbing-layer split N floats apart (a
+// state record from its p field, or a store slot); an adjoint record holds
+// lvx, lvz, lpx, lpz at 0, N, 2N, 3N.  One buffer resource covers all
+// fields of the records of a shot group.
+struct Recd {
+    float *base;
+    unsigned sbytes;
+    unsigned bytes;
 };
 
 struct FwdStep {
-    Fld vx_in, vz_in, p_in, pz_in;
-    Fld vx_out, vz_out, p_out, pz_out;
-    int n;              // time step being taken (n -> n+1)
-    int sample_n;       // >= 0: write trace sample sample_n from p_in
+    Recd vin, pin, vout, pout;
+    const float *Q;     // [S][nt] time integral of the wavelet at n+1/2
     float *traces;      // [S][nrec][nt]
+    int n;              // time step being taken (n -> n+1)
+    int sample_n;       // >= 0: write trace sample sample_n from pin
 };
 struct AdjStep {
-    Fld lvx_in, lvz_in, lpx_in, lpz_in;      // adjoint state after step n+1
-    Fld lvx_out, lvz_out, lpx_out, lpz_out;  // adjoint state after step n
-    Fld pn, pzn, pn1, pzn1;                  // forward pressure at n and n+1
-    float *gpart;                            // [groups][3][N]
+    Recd lin, lout, pn, pn1;
+    float *gpart;           // [groups][3][N]: gK, gbx, gbz
+    const float *resid;     // [S][nrec][nt]
     int n;
     int inject_n;           // >= 0: add R^T r^{inject_n} to the output pressure
-    const float *resid;     // [S][nrec][nt]
 };
-bool fused_tile_supported(int tile_z);
-int fused_tiles(const Geo &g, int tile_z, int *ntx);
-void launch_fused_fwd(const Geo &g, const Pml &t, const Mdl &m, const Src &src, const Rec &rec,
-                      const TileLists &tl, int S, int groups, int tile_z, const FwdStep &a,
+
+bool fused_spg_supported(int spg);
+Sweep sweep_of(const Geo &g, int S, int band_rows, int spg);
+// tabs: the 8 damping tables (x: alpha, beta, alpha_h, beta_h; then z) in
+// one block; model: K, bx, bz as one block of 3N floats.
+void launch_fused_fwd(const Geo &g, const float *tabs, const float *model,
+                      const SweepTables *tab_dev, int S, const Sweep &sw, const FwdStep &a,
                       hipStream_t st);
-void launch_fused_adj(const Geo &g, const Pml &t, const Mdl &m, const Src &src, const Inj &inj,
-                      int nrec, const TileLists &tl, int S, int groups, int tile_z,
-                      const AdjStep &a, hipStream_t st);
+void launch_fused_adj(const Geo &g, const float *tabs, const float *model,
+                      const SweepTables *tab_dev, int S, const Sweep &sw, const AdjStep &a,
+                      hipStream_t st);
 
 }  // namespace fwi

@@ -262,47 +262,85 @@ __global__ void k_misfit_final(const float *partials, int nblocks, float *J)
 // cells that replicate it; density sensitivity from the two buoyancies
 // each density enters (d(2/(a+b))/da = -b_x^2/2; at the last node the
 // replicated neighbour is the node itself); then the chain rule.
-__global__ void k_finalize(Geo g, int param, const float *m1, const float *m2,
-                           const float *bx, const float *bz, const float *gpart, int groups,
-                           float *g1, float *g2)
+// Gradient finalisation in three passes over device arrays (no long serial
+// loops): per padded cell, the sum of the shot groups' partials (tK) and the
+// density sensitivity of the cell (tr) from the buoyancy sensitivities,
+// with d b / d rho = -b^2 / 2 split over the two nodes averaged into each
+// buoyancy and the ghost node past the last row / column folded back onto
+// it; then the absorbing layer is folded onto the physical border columns
+// and rows (the layer takes the model of the nearest physical node).
+__global__ void k_fin_cells(Geo g, const float *bx, const float *bz, const float *gpart,
+                            int groups, float *tK, float *tr)
 {
-    int pj = blockIdx.x * blockDim.x + threadIdx.x;
-    int pi = blockIdx.y;
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= g.N)
+        return;
+    const int r = (int)(q / g.Nx), c = (int)(q - (long long)r * g.Nx);
+    const long long N = g.N;
+    float sK = 0.0f, sx = 0.0f, sz = 0.0f, sxl = 0.0f, szu = 0.0f;
+    for (int k = 0; k < groups; ++k) {
+        const float *G = gpart + (long long)k * 3 * N;
+        sK += G[q];
+        sx += G[N + q];
+        sz += G[2 * N + q];
+        if (c > 0)
+            sxl += G[N + q - 1];
+        if (r > 0)
+            szu += G[2 * N + q - g.Nx];
+    }
+    const float tx = -0.5f * sx * bx[q] * bx[q];
+    const float tz = -0.5f * sz * bz[q] * bz[q];
+    float d = tx + tz;
+    if (c > 0)
+        d += -0.5f * sxl * bx[q - 1] * bx[q - 1];
+    if (r > 0)
+        d += -0.5f * szu * bz[q - g.Nx] * bz[q - g.Nx];
+    if (c == g.Nx - 1)
+        d += tx;
+    if (r == g.Nz - 1)
+        d += tz;
+    tK[q] = sK;
+    tr[q] = d;
+}
+
+// Physical column pj of padded row r takes the layer columns beside it, in
+// place: each thread writes only column pj + npml, which no other thread
+// reads.
+__global__ void k_fin_cols(Geo g, float *tK, float *tr)
+{
+    const int pj = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
     if (pj >= g.nx)
         return;
-    int r0 = pi == 0 ? 0 : pi + g.npml, r1 = pi == g.nz - 1 ? g.Nz - 1 : pi + g.npml;
-    int c0 = pj == 0 ? 0 : pj + g.npml, c1 = pj == g.nx - 1 ? g.Nx - 1 : pj + g.npml;
-    const long long N = g.N;
+    const int c0 = pj == 0 ? 0 : pj + g.npml, c1 = pj == g.nx - 1 ? g.Nx - 1 : pj + g.npml;
+    if (c0 == c1)
+        return;
+    const long long row = (long long)r * g.Nx;
+    float a = 0.0f, b = 0.0f;
+    for (int c = c0; c <= c1; ++c) {
+        a += tK[row + c];
+        b += tr[row + c];
+    }
+    tK[row + pj + g.npml] = a;
+    tr[row + pj + g.npml] = b;
+}
+
+// Physical row pi takes the layer rows above / below it; chain rule.
+__global__ void k_fin_rows(Geo g, int param, const float *m1, const float *m2, const float *tK,
+                           const float *tr, float *g1, float *g2)
+{
+    const int pj = blockIdx.x * blockDim.x + threadIdx.x;
+    const int pi = blockIdx.y;
+    if (pj >= g.nx)
+        return;
+    const int r0 = pi == 0 ? 0 : pi + g.npml, r1 = pi == g.nz - 1 ? g.Nz - 1 : pi + g.npml;
+    const int c = pj + g.npml;
     float gK = 0.0f, gr = 0.0f;
-    for (int r = r0; r <= r1; ++r)
-        for (int c = c0; c <= c1; ++c) {
-            long long q = (long long)r * g.Nx + c;
-            float sK = 0.0f, sx = 0.0f, sz = 0.0f, sxl = 0.0f, szu = 0.0f;
-            for (int k = 0; k < groups; ++k) {
-                const float *G = gpart + (long long)k * 3 * N;
-                sK += G[q];
-                sx += G[N + q];
-                sz += G[2 * N + q];
-                if (c > 0)
-                    sxl += G[N + q - 1];
-                if (r > 0)
-                    szu += G[2 * N + q - g.Nx];
-            }
-            float tx = -0.5f * sx * bx[q] * bx[q];
-            float tz = -0.5f * sz * bz[q] * bz[q];
-            float d = tx + tz;
-            if (c > 0)
-                d += -0.5f * sxl * bx[q - 1] * bx[q - 1];
-            if (r > 0)
-                d += -0.5f * szu * bz[q - g.Nx] * bz[q - g.Nx];
-            if (c == g.Nx - 1)
-                d += tx;
-            if (r == g.Nz - 1)
-                d += tz;
-            gK += sK;
-            gr += d;
-        }
-    long long pc = (long long)pi * g.nx + pj;
+    for (int r = r0; r <= r1; ++r) {
+        gK += tK[(long long)r * g.Nx + c];
+        gr += tr[(long long)r * g.Nx + c];
+    }
+    const long long pc = (long long)pi * g.nx + pj;
     float a, b;
     chain(param, m1[pc], m2[pc], gK, gr, a, b);
     g1[pc] = a;
@@ -416,10 +454,14 @@ void launch_misfit(const float *d, const float *dobs, float *resid, long long n,
 
 void launch_finalize(const Geo &g, int param, const float *m1, const float *m2,
                      const float *bx, const float *bz, const float *gpart, int groups,
-                     float *g1, float *g2, hipStream_t st)
+                     float *fold, float *g1, float *g2, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_finalize, dim3(blocks_for(g.nx, 64), g.nz), dim3(64), 0, st, g, param,
-                       m1, m2, bx, bz, gpart, groups, g1, g2);
+    float *tK = fold, *tr = fold + g.N;
+    hipLaunchKernelGGL(k_fin_cells, dim3(blocks_for(g.N)), dim3(kBlock), 0, st, g, bx, bz, gpart,
+                       groups, tK, tr);
+    hipLaunchKernelGGL(k_fin_cols, dim3(blocks_for(g.nx, 64), g.Nz), dim3(64), 0, st, g, tK, tr);
+    hipLaunchKernelGGL(k_fin_rows, dim3(blocks_for(g.nx, 64), g.nz), dim3(64), 0, st, g, param,
+                       m1, m2, (const float *)tK, (const float *)tr, g1, g2);
 }
 
 void launch_convert(int from, int to, long long n, const float *a1, const float *a2, float *b1,

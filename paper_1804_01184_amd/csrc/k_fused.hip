@@ -1,33 +1,77 @@
 // Batched path: one launch per time step covers every shot of the model.
 //
-// A workgroup (256 threads = 4 wave64) owns a tile of TZ x 64 nodes and a
-// group of shots, which it sweeps one after the other.  For each shot the
-// velocity half-step and the pressure half-step are fused: the pressure
-// tile plus a 3-node halo is staged in LDS, the new particle velocities are
-// computed on the tile plus the 2-node halo the pressure stencil needs
-// (recomputing the halo instead of exchanging it), and the new pressure is
-// formed from LDS.  Each wavefield value is therefore read once and written
-// once per step (ping-pong buffers: the halo of a neighbour must still hold
-// the old time level).  Model coefficients sit in registers for the whole
-// shot sweep, and the gradient of the adjoint kernel is accumulated in
-// registers across the group's shots and written once per step, so model
-// and gradient traffic is divided by the shots per group.
+// Each wave64 owns a strip of 64 consecutive columns (58 output columns and
+// a 3-column halo on each side) and a band of rows, and marches down the
+// band one row at a time.  The vertical parts of the stencils live in
+// per-lane register windows (the rows above and below the current one), the
+// horizontal parts are exchanged between lanes with DPP wave shifts, so the
+// kernels use no LDS and no barriers: waves are independent and occupancy is
+// limited only by registers.  Velocity and pressure half-steps are fused:
+// the new velocities of a row are formed and consumed by the new pressure of
+// the same row in registers, so every wavefield value is read once and
+// written once per step (ping-pong buffers, since neighbouring strips and
+// bands still read the old level).
 //
-// Lane l of a wave works on column j0 + l of the tile (plus a few halo
-// columns on low lanes); wave w works on rows w, w + 4, ...  Workgroups are
-// numbered so that each XCD receives a contiguous range of tiles, keeping
-// neighbouring halos in the same L2.
+// A wave advances SPG shots of the same model together, row by row: the
+// model coefficients of a row are read once for all of them, and in the
+// adjoint kernel the gradient contributions of the SPG shots are summed in
+// registers and added to the group's partial gradient once per row.  The
+// shot count of a launch is padded to a multiple of SPG with all-zero shots
+// (no source, no receivers), so every group is full.
+//
+// The loads of row i+1 are issued before the arithmetic and the stores of
+// row i into one of two alternating register sets, so their latency overlaps
+// a row of work and no register copies (which would wait for them) are
+// needed.  Loads are unconditional: rows outside the grid or past the band
+// are read through an out-of-range lane offset, which returns zero without
+// touching memory, so the memory counters see the same sequence on every
+// row.
+//
+// Receiver sampling (forward) and the adjoint-source injection (adjoint,
+// for the next, earlier step) are done by the wave owning the node, from
+// per-(shot, strip, band) lists sorted by row.  Workgroups are numbered so
+// that each XCD receives a contiguous range of waves (neighbouring strips
+// and bands share its L2).
 #include "fwi2d_internal.h"
 
 namespace fwi {
 
 namespace {
 
-constexpr int TX = 64;
-constexpr int NTHR = 256;
+constexpr int WAVE = 64;
+constexpr int HALO = 3;
+constexpr int NTHR = 256;  // 4 independent waves per workgroup
 
-// Workgroup id -> work item, giving XCD x (= id mod 8 under round-robin
-// dispatch) the contiguous items [x q, (x + 1) q).
+// Buffer accesses: a uniform resource per record group, a uniform byte
+// offset for the row (scalar offset) and a per-lane byte offset for the
+// column.  A lane offset of kOOB lies past every resource, so its loads
+// return 0 (ghost cells outside the grid, cells without an absorbing-layer
+// split, rows past the band) and its stores are dropped (halo lanes).  The
+// host keeps every resource and every row offset below 2^31 bytes.
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+constexpr unsigned kOOB = 0x80000000u;
+constexpr int kRsrcWord3 = 0x00020000;
+
+__device__ inline rsrc_t res(const float *p, unsigned bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc((void *)p, (short)0, (int)bytes, kRsrcWord3);
+}
+// (the b32 builtins move raw 32-bit words: bit casts, not conversions)
+__device__ inline float bld(rsrc_t r, unsigned voff, unsigned soff)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+__device__ inline void bst(rsrc_t r, unsigned voff, unsigned soff, float v)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)voff, (int)soff, 0);
+}
+
+// by-value min / max (reference-returning overloads applied to kernel
+// arguments would force a private copy of the argument struct)
+__device__ inline int imin(int a, int b) { return a < b ? a : b; }
+__device__ inline int imax(int a, int b) { return a > b ? a : b; }
+__device__ inline int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
 __device__ inline int xcd_item(int b, int nb)
 {
     int q = nb >> 3;
@@ -36,512 +80,611 @@ __device__ inline int xcd_item(int b, int nb)
     return (b & 7) * q + (b >> 3);
 }
 
-__device__ inline bool inside(const Geo &g, int i, int j)
+// Neighbour exchange by whole-wave DPP shifts (register moves, no LDS):
+// lane l receives the value of lane l + 1 (shift left) or l - 1 (shift
+// right); the end lanes, which have no such neighbour, receive 0, and only
+// halo lanes ever use it.
+constexpr int kDppWaveShl1 = 0x130, kDppWaveShr1 = 0x138;
+template <int CTRL>
+__device__ inline float wave_shift(float v)
 {
-    return i >= 0 && j >= 0 && i < g.Nz && j < g.Nx;
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL,
+                                                              0xf, 0xf, true));
+}
+__device__ inline float from_right(float v) { return wave_shift<kDppWaveShl1>(v); }
+__device__ inline float from_left(float v) { return wave_shift<kDppWaveShr1>(v); }
+__device__ inline float from_right2(float v) { return from_right(from_right(v)); }
+__device__ inline float from_left2(float v) { return from_left(from_left(v)); }
+
+struct WaveGeo {
+    int lane, j;
+    bool colok;       // column inside the grid
+    unsigned vcol;    // lane column byte offset, kOOB outside the grid
+    unsigned vcolw;   // same for stores: kOOB unless an output lane
+    unsigned vside;   // column part of the split index on middle rows
+    unsigned vsidew;  // same for stores
+    int i0, i1;       // owned rows [i0, i1)
+    int s0;           // shots [s0, s0 + SPG)
+    int strip, band, grp;
+};
+
+__device__ inline bool wave_geo(const Geo &g, const Sweep &sw, WaveGeo &w)
+{
+    w.lane = threadIdx.x & (WAVE - 1);
+    // wave index, made provably uniform so that everything derived from it
+    // (rows, shots, buffer resources) lives in scalar registers
+    int wid = uni(xcd_item(blockIdx.x, gridDim.x) * (NTHR / WAVE) + (int)(threadIdx.x / WAVE));
+    if (wid >= sw.nwaves)
+        return false;
+    w.strip = wid % sw.nstrips;
+    int rest = wid / sw.nstrips;
+    w.band = rest % sw.nbands;
+    w.grp = rest / sw.nbands;
+    w.j = w.strip * kStripOut - HALO + w.lane;
+    w.colok = w.j >= 0 && w.j < g.Nx;
+    const bool outl = w.colok && w.lane >= HALO && w.lane < WAVE - HALO;
+    w.vcol = w.colok ? 4u * (unsigned)w.j : kOOB;
+    w.vcolw = outl ? w.vcol : kOOB;
+    unsigned side = kOOB;
+    if (w.colok && w.j < g.npml)
+        side = 4u * (unsigned)w.j;
+    else if (w.colok && w.j >= g.Nx - g.npml)
+        side = 4u * (unsigned)(w.j - (g.Nx - 2 * g.npml));
+    w.vside = side;
+    w.vsidew = outl ? side : kOOB;
+    w.i0 = w.band * sw.H;
+    w.i1 = imin(w.i0 + sw.H, g.Nz);
+    w.s0 = w.grp * sw.spg;
+    return true;
 }
 
-template <int TZ>
+__device__ inline int list_index(const Sweep &sw, const WaveGeo &w, int s)
+{
+    return (s * sw.nbands + w.band) * sw.nstrips + w.strip;
+}
+
+__device__ inline bool row_ok(const Geo &g, int i) { return (unsigned)i < (unsigned)g.Nz; }
+
+// Byte offset of row i (uniform).
+__device__ inline unsigned rowb(const Geo &g, int i) { return 4u * (unsigned)i * (unsigned)g.Nx; }
+
+// Split (absorbing-layer) index of row i: uniform row base + lane part.  On
+// the top and bottom strips every column has a split (full rows); on middle
+// rows only the side columns.  With no layer every lane part is kOOB.
+struct ZRow {
+    unsigned base;
+    bool full;
+};
+__device__ inline ZRow zrow(const Geo &g, int i)
+{
+    const bool top = i < g.npml, bot = i >= g.Nz - g.npml;
+    ZRow z;
+    z.full = top || bot;
+    const int fr = top ? i : i - (g.Nz - 2 * g.npml);
+    z.base = z.full ? 4u * (unsigned)fr * (unsigned)g.Nx
+                    : 4u * (unsigned)(2 * g.npml * g.Nx + (i - g.npml) * 2 * g.npml);
+    return z;
+}
+
+// One resource for the records of shots [s0, s0 + SPG): shot s0 + k sits
+// k * sbytes bytes after the first (uniform offset skoff).
+__device__ inline rsrc_t grp_res(const Recd &r, int s0, int spg)
+{
+    return res((const float *)((const char *)r.base + (size_t)s0 * r.sbytes),
+               (unsigned)(spg - 1) * r.sbytes + r.bytes);
+}
+__device__ inline unsigned skoff(const Recd &r, int k) { return (unsigned)k * r.sbytes; }
+
+// Lane offsets of the loads of row r: the lane column, or kOOB where the row
+// (r, r+1, r+3) lies outside the grid or r lies past the band.
+struct RowOff {
+    unsigned o0, o1, o3, oz;
+};
+__device__ inline RowOff row_off(const Geo &g, const WaveGeo &w, int r)
+{
+    const bool live = r < w.i1;
+    RowOff o;
+    o.o0 = live ? w.vcol : kOOB;
+    o.o1 = live && r + 1 < g.Nz ? w.vcol : kOOB;
+    o.o3 = live && r + 3 < g.Nz ? w.vcol : kOOB;
+    o.oz = live ? (zrow(g, r).full ? w.vcol : w.vside) : kOOB;
+    return o;
+}
+
+// ---------------------------------------------------------------- forward
+
+template <int SPG>
+struct FRow {
+    float K, bx, bz1;                           // K, bx at r; bz at r+1
+    float p3[SPG], vz1[SPG], vx[SPG], pz[SPG];  // p at r+3, vz at r+1, vx and split at r
+};
+
+template <int SPG>
 __global__ void __launch_bounds__(NTHR)
-    k_fwd(Geo g, Pml t, Mdl m, Src src, Rec rec, TileLists tl, int S, int groups, int ntx,
-          int ntiles, FwdStep a)
+    k_fwd(Geo g, const float *__restrict__ tabs, const float *model, const SweepTables *T, int S,
+          Sweep sw, FwdStep a)
 {
-    constexpr int PH = TZ + 6;      // pressure rows i0-3 .. i0+TZ+2
-    constexpr int PW = TX + 6;      // pressure cols j0-3 .. j0+66
-    constexpr int XW = TX + 3;      // vx cols j0-2 .. j0+64
-    constexpr int ZH = TZ + 3;      // vz rows i0-2 .. i0+TZ
-    constexpr int NR = TZ / 4;      // tile rows per wave
-    constexpr int NP = (PH + 3) / 4;
-    constexpr int NZ = (ZH + 3) / 4;
+    WaveGeo w;
+    if (!wave_geo(g, sw, w))
+        return;
+    const unsigned vcol_ = w.vcol, vcolw_ = w.vcolw, vsidew_ = w.vsidew;
+    const int jc = imin(imax(w.j, 0), g.Nx - 1);
+    const float ax = w.colok ? tabs[jc] : 0.f, btx = w.colok ? tabs[g.Nx + jc] : 0.f;
+    const float ahx = w.colok ? tabs[2 * g.Nx + jc] : 0.f, bhx = w.colok ? tabs[3 * g.Nx + jc] : 0.f;
+    // z tables: alpha, beta at nodes, alpha_h, beta_h at half nodes
+    const float *__restrict__ zaz = tabs + 4 * g.Nx, *__restrict__ zbz = zaz + g.Nz;
+    const float *__restrict__ zahz = zbz + g.Nz, *__restrict__ zbhz = zahz + g.Nz;
+    const unsigned FB = 4u * (unsigned)g.N;
+    const rsrc_t rM = res(model, 3u * FB);   // K, bx, bz at 0, FB, 2 FB
+    const unsigned rowN = 4u * (unsigned)g.Nx;
+    const rsrc_t rPin = grp_res(a.pin, w.s0, SPG), rVin = grp_res(a.vin, w.s0, SPG);
+    const rsrc_t rPout = grp_res(a.pout, w.s0, SPG), rVout = grp_res(a.vout, w.s0, SPG);
 
-    __shared__ float sp[PH][PW];
-    __shared__ float svx[TZ][XW];
-    __shared__ float svz[ZH][TX];
-
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int item = xcd_item(blockIdx.x, gridDim.x);
-    const int grp = item / ntiles, tile = item - grp * ntiles;
-    const int i0 = (tile / ntx) * TZ, j0 = (tile % ntx) * TX;
-    const int s0 = (grp * S) / groups, s1 = ((grp + 1) * S) / groups;
-
-    // vx items: rows i0 + wave + 4k; main column j0 + lane (LDS col lane+2),
-    // halo columns j0-2, j0-1, j0+64 on lanes 0..2 (LDS cols 0, 1, 66).
-    const int jm = j0 + lane;
-    const int ce = lane < 2 ? lane : XW - 1;
-    const int je = j0 - 2 + ce;
-    const bool has_e = lane < 3;
-    float bxm[NR], bxe[NR], Km[NR], azr[NR], btzr[NR];
-    bool okm[NR], oke[NR];
-    // vz items: rows i0 - 2 + wave + 4k, column j0 + lane
-    float bzz[NZ], ahzz[NZ], bhzz[NZ];
-    bool okz[NZ];
-    const bool colm = jm < g.Nx;
-    const float ahxm = colm ? t.ahx[jm] : 0.f, bhxm = colm ? t.bhx[jm] : 0.f;
-    const float axm = colm ? t.ax[jm] : 0.f, btxm = colm ? t.bx[jm] : 0.f;
-    const bool cole = je >= 0 && je < g.Nx;
-    const float ahxe = cole ? t.ahx[je] : 0.f, bhxe = cole ? t.bhx[je] : 0.f;
+    float P[SPG][4];   // pressure rows i .. i+3
+    float VZ[SPG][3];  // new vz rows i-2 .. i
+    // receiver list position, end and row of the next entry (-1: none)
+    int cur[SPG], end[SPG], nxt[SPG];
+    // source: first row of its bilinear cell and this lane's injection
+    // weights dt Q w / (dx dz) on that row and the next
+    int srow[SPG];
+    float swa[SPG], swb[SPG];
 #pragma unroll
-    for (int k = 0; k < NR; ++k) {
-        int i = i0 + wave + 4 * k;
-        okm[k] = i < g.Nz && colm;
-        oke[k] = has_e && i < g.Nz && cole;
-        long long c = (long long)i * g.Nx;
-        bxm[k] = okm[k] ? m.bx[c + jm] : 0.f;
-        Km[k] = okm[k] ? m.K[c + jm] : 0.f;
-        bxe[k] = oke[k] ? m.bx[c + je] : 0.f;
-        azr[k] = i < g.Nz ? t.az[i] : 0.f;
-        btzr[k] = i < g.Nz ? t.bz[i] : 0.f;
+    for (int k = 0; k < SPG; ++k) {
+        const int s = w.s0 + k;
+        cur[k] = end[k] = 0;
+        nxt[k] = -1;
+        srow[k] = -8;
+        swa[k] = swb[k] = 0.f;
+        if (s < S) {
+            const int2 sij = T->src_ij[s];
+            const float4 sw4 = T->src_w[s];
+            const float dq = g.dt * a.Q[(long long)s * T->nt + a.n];
+            const int dj = w.j - sij.y;
+            srow[k] = uni(sij.x);
+            swa[k] = dj == 0 ? dq * sw4.x : (dj == 1 ? dq * sw4.y : 0.f);
+            swb[k] = dj == 0 ? dq * sw4.z : (dj == 1 ? dq * sw4.w : 0.f);
+            if (a.sample_n >= 0) {
+                const int li = list_index(sw, w, s);
+                cur[k] = uni(T->samp_ptr[li]);
+                end[k] = uni(T->samp_ptr[li + 1]);
+                if (cur[k] < end[k])
+                    nxt[k] = uni(T->samp[cur[k]].x);
+            }
+        }
+        const unsigned op = skoff(a.pin, k), ovz = FB + skoff(a.vin, k);
+        float pr[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            const int r = w.i0 - 3 + q;
+            pr[q] = row_ok(g, r) ? bld(rPin, vcol_, rowb(g, r) + op) : 0.f;
+        }
+        // vz at rows i0-2 .. i0 from p rows r-1 .. r+2
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int r = w.i0 - 2 + q;
+            float v = 0.f;
+            if (row_ok(g, r)) {
+                const unsigned rb = rowb(g, r);
+                const float bz = bld(rM, vcol_, rb + 2u * FB);
+                v = zahz[r] * bld(rVin, vcol_, rb + ovz) -
+                    zbhz[r] * bz * (kC1 * (pr[q + 2] - pr[q + 1]) + kC2 * (pr[q + 3] - pr[q])) * g.rdz;
+            }
+            VZ[k][q] = v;
+        }
+        bst(rVout, vcolw_, rowb(g, w.i0) + FB + skoff(a.vout, k), VZ[k][2]);
+        P[k][0] = pr[3];
+        P[k][1] = pr[4];
+        P[k][2] = pr[5];
+        P[k][3] = 0.f;
     }
-#pragma unroll
-    for (int k = 0; k < NZ; ++k) {
-        int r = wave + 4 * k;
-        int i = i0 - 2 + r;
-        okz[k] = r < ZH && i >= 0 && i < g.Nz && colm;
-        bzz[k] = okz[k] ? m.bz[(long long)i * g.Nx + jm] : 0.f;
-        ahzz[k] = okz[k] ? t.ahz[i] : 0.f;
-        bhzz[k] = okz[k] ? t.bhz[i] : 0.f;
-    }
 
-    for (int s = s0; s < s1; ++s) {
-        const float *pin = a.p_in.shot(s);
-        const float *vxin = a.vx_in.shot(s);
-        const float *vzin = a.vz_in.shot(s);
-        // stage the pressure tile with its halo; zero outside the grid
+    auto load_row = [&](int r, FRow<SPG> &b) {
+        const unsigned rb = rowb(g, r);
+        const RowOff o = row_off(g, w, r);
+        const unsigned zb = zrow(g, r).base;
+        b.K = bld(rM, o.o0, rb);
+        b.bx = bld(rM, o.o0, rb + FB);
+        b.bz1 = bld(rM, o.o1, rb + rowN + 2u * FB);
 #pragma unroll
-        for (int k = 0; k < NP; ++k) {
-            int r = wave + 4 * k;
-            if (r < PH) {
-                int i = i0 - 3 + r;
-                bool row = i >= 0 && i < g.Nz;
-                long long c = (long long)i * g.Nx;
-                sp[r][lane + 3] = (row && jm < g.Nx) ? pin[c + jm] : 0.f;
-                if (lane < 6) {
-                    int e = lane < 3 ? lane : lane + TX;
-                    int j = j0 - 3 + e;
-                    sp[r][e] = (row && j >= 0 && j < g.Nx) ? pin[c + j] : 0.f;
+        for (int k = 0; k < SPG; ++k) {
+            const unsigned kp = skoff(a.pin, k), kv = skoff(a.vin, k);
+            b.p3[k] = bld(rPin, o.o3, rb + 3u * rowN + kp);
+            b.vz1[k] = bld(rVin, o.o1, rb + rowN + FB + kv);
+            b.vx[k] = bld(rVin, o.o0, rb + kv);
+            b.pz[k] = bld(rPin, o.oz, zb + FB + kp);
+        }
+    };
+
+    auto row = [&](int i, const FRow<SPG> &b) {
+        const float K = b.K, bx = b.bx, bzn = b.bz1;
+        const unsigned rb = rowb(g, i);
+        const bool rn = row_ok(g, i + 1);
+        const float ahz1 = rn ? zahz[i + 1] : 0.f, bhz1 = rn ? zbhz[i + 1] : 0.f;
+        const float az = zaz[i], btz = zbz[i];
+        const ZRow z = zrow(g, i);
+        const unsigned zcol = z.full ? vcolw_ : vsidew_;
+        const unsigned vzw = i + 1 < w.i1 ? vcolw_ : kOOB;   // this wave owns vz row i+1
+#pragma unroll
+        for (int k = 0; k < SPG; ++k) {
+            P[k][3] = b.p3[k];
+            const float p0 = P[k][0];
+            // vz at row (i+1) + 1/2
+            const float vzn =
+                ahz1 * b.vz1[k] - bhz1 * bzn * (kC1 * (P[k][2] - P[k][1]) + kC2 * (P[k][3] - p0)) * g.rdz;
+            // vx at (i, j + 1/2)
+            const float dpx = kC1 * (from_right(p0) - p0) + kC2 * (from_right2(p0) - from_left(p0));
+            const float vxn = ahx * b.vx[k] - bhx * bx * dpx * g.rdx;
+            // pressure at n+1 (the split is zero where the layer has none,
+            // and alpha = 1, beta = dt there)
+            const float dvx = kC1 * (vxn - from_left(vxn)) + kC2 * (from_right(vxn) - from_left2(vxn));
+            const float dvz = kC1 * (VZ[k][2] - VZ[k][1]) + kC2 * (vzn - VZ[k][0]);
+            const float pz = b.pz[k];
+            float px = ax * (p0 - pz) - btx * K * dvx * g.rdx;
+            const float pzn = az * pz - btz * K * dvz * g.rdz;
+            if ((unsigned)(i - srow[k]) < 2u)
+                px += K * (i == srow[k] ? swa[k] : swb[k]);
+            // receivers whose bilinear cell starts on row i, from pin
+            if (i == nxt[k]) {
+                const int s = w.s0 + k;
+                const float q0 = from_right(p0), q1 = from_right(P[k][1]);
+                int c = cur[k];
+                int4 e = T->samp[c];
+                for (;;) {
+                    if (w.lane == e.y) {
+                        const long long rq = (long long)s * T->nrec + e.z;
+                        const float4 rw = T->rec_w[rq];
+                        a.traces[rq * T->nt + a.sample_n] =
+                            rw.x * p0 + rw.y * q0 + rw.z * P[k][1] + rw.w * q1;
+                    }
+                    if (++c >= end[k]) {
+                        e.x = -1;
+                        break;
+                    }
+                    e = T->samp[c];
+                    if (uni(e.x) != i)
+                        break;
                 }
+                cur[k] = c;
+                nxt[k] = uni(e.x);
             }
+            const unsigned kv = skoff(a.vout, k), kp = skoff(a.pout, k);
+            bst(rVout, vcolw_, rb + kv, vxn);
+            bst(rVout, vzw, rb + rowN + FB + kv, vzn);
+            bst(rPout, vcolw_, rb + kp, px + pzn);
+            bst(rPout, zcol, z.base + FB + kp, pzn);
+            VZ[k][0] = VZ[k][1];
+            VZ[k][1] = VZ[k][2];
+            VZ[k][2] = vzn;
+            P[k][0] = P[k][1];
+            P[k][1] = P[k][2];
+            P[k][2] = P[k][3];
         }
-        float vxo[NR], vxoe[NR], vzo[NZ];
-#pragma unroll
-        for (int k = 0; k < NR; ++k) {
-            long long c = (long long)(i0 + wave + 4 * k) * g.Nx;
-            vxo[k] = okm[k] ? vxin[c + jm] : 0.f;
-            vxoe[k] = oke[k] ? vxin[c + je] : 0.f;
-        }
-#pragma unroll
-        for (int k = 0; k < NZ; ++k)
-            vzo[k] = okz[k] ? vzin[(long long)(i0 - 2 + wave + 4 * k) * g.Nx + jm] : 0.f;
-        __syncthreads();
+    };
 
-        // receivers whose bilinear cell starts in this tile: sample p_in
-        if (a.sample_n >= 0) {
-            int lo = tl.samp_ptr[s * ntiles + tile], hi = tl.samp_ptr[s * ntiles + tile + 1];
-            for (int e = lo + (int)threadIdx.x; e < hi; e += NTHR) {
-                long long q = (long long)s * rec.nrec + tl.samp_rec[e];
-                long long c = rec.idx[q];
-                float4 w = rec.w[q];
-                int li = (int)(c / g.Nx) - i0 + 3, lj = (int)(c % g.Nx) - j0 + 3;
-                a.traces[q * src.nt + a.sample_n] = w.x * sp[li][lj] + w.y * sp[li][lj + 1] +
-                                                    w.z * sp[li + 1][lj] + w.w * sp[li + 1][lj + 1];
-            }
-        }
-
-        // particle velocities at n+1/2 (vx at (i, j+1/2), vz at (i+1/2, j))
-        float *vxout = a.vx_out.shot(s);
-        float *vzout = a.vz_out.shot(s);
-#pragma unroll
-        for (int k = 0; k < NR; ++k) {
-            int r = wave + 4 * k;
-            const float *row = sp[r + 3];
-            int c = lane + 2;  // LDS col of vx at column jm; pressure col c+1
-            float d = kC1 * (row[c + 2] - row[c + 1]) + kC2 * (row[c + 3] - row[c]);
-            float v = ahxm * vxo[k] - bhxm * bxm[k] * d * g.rdx;
-            v = okm[k] ? v : 0.f;
-            svx[r][c] = v;
-            if (okm[k])
-                vxout[(long long)(i0 + r) * g.Nx + jm] = v;
-            if (has_e) {
-                float de = kC1 * (row[ce + 2] - row[ce + 1]) + kC2 * (row[ce + 3] - row[ce]);
-                float ve = ahxe * vxoe[k] - bhxe * bxe[k] * de * g.rdx;
-                svx[r][ce] = oke[k] ? ve : 0.f;
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < NZ; ++k) {
-            int r = wave + 4 * k;
-            if (r < ZH) {
-                // vz row i = i0-2+r; pressure row i sits at LDS row r+1
-                float d = kC1 * (sp[r + 2][lane + 3] - sp[r + 1][lane + 3]) +
-                          kC2 * (sp[r + 3][lane + 3] - sp[r][lane + 3]);
-                float v = ahzz[k] * vzo[k] - bhzz[k] * bzz[k] * d * g.rdz;
-                v = okz[k] ? v : 0.f;
-                svz[r][lane] = v;
-                if (okz[k] && r >= 2 && r < TZ + 2)
-                    vzout[(long long)(i0 - 2 + r) * g.Nx + jm] = v;
-            }
-        }
-        __syncthreads();
-
-        // pressure at n+1 on the tile
-        float *pout = a.p_out.shot(s);
-        const float *pzin = a.pz_in.shot(s);
-        float *pzout = a.pz_out.shot(s);
-        const int2 sij = src.ij[s];
-        const float4 sw = src.w[s];
-        const float q = src.Q[(long long)s * src.nt + a.n];
-#pragma unroll
-        for (int k = 0; k < NR; ++k) {
-            if (!okm[k])
-                continue;
-            int r = wave + 4 * k;
-            int i = i0 + r;
-            int c = lane + 2;
-            float dvx = kC1 * (svx[r][c] - svx[r][c - 1]) + kC2 * (svx[r][c + 1] - svx[r][c - 2]);
-            float dvz = kC1 * (svz[r + 2][lane] - svz[r + 1][lane]) +
-                        kC2 * (svz[r + 3][lane] - svz[r][lane]);
-            float p = sp[r + 3][lane + 3];
-            bool pml = in_pml(g, i, jm);
-            long long qi = pml ? pml_index(g, i, jm) : 0;
-            float pz = pml ? pzin[qi] : 0.f;
-            float K = Km[k];
-            float px = axm * (p - pz) - btxm * K * dvx * g.rdx;
-            float pzn = azr[k] * pz - btzr[k] * K * dvz * g.rdz;
-            int di = i - sij.x, dj = jm - sij.y;
-            if ((unsigned)di < 2u && (unsigned)dj < 2u) {
-                float w = di == 0 ? (dj == 0 ? sw.x : sw.y) : (dj == 0 ? sw.z : sw.w);
-                px += g.dt * K * q * w;
-            }
-            pout[(long long)i * g.Nx + jm] = px + pzn;
-            if (pml)
-                pzout[qi] = pzn;
-        }
-        __syncthreads();
+    FRow<SPG> A, B;
+    load_row(w.i0, A);
+    for (int i = w.i0;;) {
+        load_row(i + 1, B);
+        row(i, A);
+        if (++i >= w.i1)
+            break;
+        load_row(i + 1, A);
+        row(i, B);
+        if (++i >= w.i1)
+            break;
     }
 }
 
-// Adjoint of one step for every shot of the group.  State on entry: nu =
-// adjoint after step n+1 with the receiver term R^T r^n already added to
-// the pressure components (mu_p).  Main pressure array = mu_px; aux array =
+// ---------------------------------------------------------------- adjoint
+//
+// State on entry: nu = adjoint after step n+1 with R^T r^n already added to
+// the pressure components (mu).  Main pressure field = mu_px; split field =
 // mu_pz in the absorbing layer (elsewhere mu_pz = mu_px).
 //   gK  += [mu_px (px^{n+1} - ax px^n) + mu_pz (pz^{n+1} - az pz^n)] / K
-//   lv_mid = nu_v + D+(beta K mu_p)             (T2 transposed)
+//   lv_mid = nu_v + D+(beta K mu_p)                       (T2 transposed)
 //   gbx += lvx_mid * (-bhx Dx+ p^n),  gbz likewise
 //   mu_p' = alpha mu_p + D-(beta_h b lv_mid);  lv' = alpha_h lv_mid   (T1^T)
-template <int TZ>
+// and mu_p' receives R^T r^{n-1} for the next (earlier) step.  Outside the
+// layer the split forms reduce to the unsplit ones (alpha = 1, pz = 0).
+
+template <int SPG>
+struct ARow {
+    float K3, bx, bz1, gK, gX, gZ1;   // K at r+3, bx at r, bz at r+1, partials at r (gbz r+1)
+    float mu3[SPG], mz3[SPG], pn3[SPG];           // mu_px, split mu_pz, p^n at r+3
+    float lvz1[SPG], lvx[SPG], pn1[SPG], z0[SPG], z1[SPG];  // lvz at r+1; lvx, p^{n+1}, splits at r
+};
+
+template <int SPG>
 __global__ void __launch_bounds__(NTHR)
-    k_adj(Geo g, Pml t, Mdl m, Inj inj, int nrec, int nt, TileLists tl, int S, int groups,
-          int ntx, int ntiles, AdjStep a)
+    k_adj(Geo g, const float *__restrict__ tabs, const float *model, const SweepTables *T, int S,
+          Sweep sw, AdjStep a)
 {
-    constexpr int XW = TX + 6;      // qx cols j0-3 .. j0+66 (tile rows)
-    constexpr int ZH = TZ + 6;      // qz rows i0-3 .. i0+TZ+2 (tile cols)
-    constexpr int NH = TZ + 3;      // p^n rows i0-1 .. i0+TZ+1
-    constexpr int NW = TX + 3;      // p^n cols j0-1 .. j0+65
-    constexpr int VW = TX + 3;      // wx cols j0-2 .. j0+64
-    constexpr int VH = TZ + 3;      // wz rows i0-2 .. i0+TZ
-    constexpr int NR = TZ / 4;
-    constexpr int NQ = (ZH + 3) / 4;
-    constexpr int NN = (NH + 3) / 4;
-    constexpr int NV = (VH + 3) / 4;
+    WaveGeo w;
+    if (!wave_geo(g, sw, w))
+        return;
+    const unsigned vcol_ = w.vcol, vside_ = w.vside, vcolw_ = w.vcolw, vsidew_ = w.vsidew;
+    const int jc = imin(imax(w.j, 0), g.Nx - 1);
+    const float ax = w.colok ? tabs[jc] : 0.f, btx = w.colok ? tabs[g.Nx + jc] : 0.f;
+    const float ahx = w.colok ? tabs[2 * g.Nx + jc] : 0.f, bhx = w.colok ? tabs[3 * g.Nx + jc] : 0.f;
+    // z tables: alpha, beta at nodes, alpha_h, beta_h at half nodes
+    const float *__restrict__ zaz = tabs + 4 * g.Nx, *__restrict__ zbz = zaz + g.Nz;
+    const float *__restrict__ zahz = zbz + g.Nz, *__restrict__ zbhz = zahz + g.Nz;
+    const bool colpml = w.j < g.npml || w.j >= g.Nx - g.npml;
+    const unsigned FB = 4u * (unsigned)g.N;
+    const unsigned rowN = 4u * (unsigned)g.Nx;
+    const rsrc_t rM = res(model, 3u * FB);                                  // K, bx, bz
+    const rsrc_t rG = res(a.gpart + (long long)w.grp * 3 * g.N, 3u * FB);  // gK, gbx, gbz
+    const rsrc_t rLin = grp_res(a.lin, w.s0, SPG), rLout = grp_res(a.lout, w.s0, SPG);
+    const rsrc_t rPn = grp_res(a.pn, w.s0, SPG), rPn1 = grp_res(a.pn1, w.s0, SPG);
+    // does (r, this column) carry a split?
+    auto pml_at = [&](int r) { return r < g.npml || r >= g.Nz - g.npml || colpml; };
+    auto btz_at = [&](int r) -> float { return row_ok(g, r) ? zbz[r] : 0.f; };
+    // mu_pz of shot k at row r inside the grid
+    auto muz_at = [&](int k, int r) -> float {
+        const unsigned kl = skoff(a.lin, k);
+        const float mx = bld(rLin, vcol_, rowb(g, r) + 2u * FB + kl);
+        const ZRow z = zrow(g, r);
+        const float mz = bld(rLin, z.full ? vcol_ : vside_, z.base + 3u * FB + kl);
+        return pml_at(r) ? mz : mx;
+    };
 
-    __shared__ float sqx[TZ][XW];
-    __shared__ float sqz[ZH][TX];
-    __shared__ float spn[NH][NW];
-    __shared__ float swx[TZ][VW];
-    __shared__ float swz[VH][TX];
-    __shared__ float sinj[TZ][TX];   // R^T r for the nodes of the tile
+    float KW[4];         // K rows i .. i+3
+    float MU[SPG][4];    // mu_px rows i .. i+3
+    float MZ[SPG][4];    // mu_pz rows i .. i+3
+    float PN[SPG][4];    // p^n rows i .. i+3
+    float WZ[SPG][3];    // beta_h bz lvz_mid rows i-2 .. i
+    // injection list position, end and row of the next entry (-1: none)
+    int cur[SPG], end[SPG], nxt[SPG];
 
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int item = xcd_item(blockIdx.x, gridDim.x);
-    const int grp = item / ntiles, tile = item - grp * ntiles;
-    const int i0 = (tile / ntx) * TZ, j0 = (tile % ntx) * TX;
-    const int s0 = (grp * S) / groups, s1 = ((grp + 1) * S) / groups;
-
-    const int jm = j0 + lane;
-    const bool colm = jm < g.Nx;
-    // halo columns of the qx rows: lanes 0..5 -> LDS cols 0,1,2,67,68,69
-    const bool has_q = lane < 6;
-    const int eq = lane < 3 ? lane : lane + TX;
-    const int jq = j0 - 3 + eq;
-    const bool colq = has_q && jq >= 0 && jq < g.Nx;
-    // halo columns of the vx rows: lanes 0..2 -> LDS cols 0, 1, 66
-    const bool has_v = lane < 3;
-    const int ev = lane < 2 ? lane : VW - 1;
-    const int jv = j0 - 2 + ev;
-    const bool colv = has_v && jv >= 0 && jv < g.Nx;
-
-    const float axm = colm ? t.ax[jm] : 0.f, btxm = colm ? t.bx[jm] : 0.f;
-    const float ahxm = colm ? t.ahx[jm] : 0.f, bhxm = colm ? t.bhx[jm] : 0.f;
-    const float btxq = colq ? t.bx[jq] : 0.f;
-    const float bhxv = colv ? t.bhx[jv] : 0.f;
-
-    // per-item model coefficients
-    float Km[NR], Kq[NR], bxm[NR], bxv[NR], azr[NR], btzr[NR];
-    bool okm[NR], okq[NR], okv[NR];
+    float Kr[6], btzr[6], wzr[3];
 #pragma unroll
-    for (int k = 0; k < NR; ++k) {
-        int i = i0 + wave + 4 * k;
-        bool row = i < g.Nz;
-        long long c = (long long)i * g.Nx;
-        okm[k] = row && colm;
-        okq[k] = row && colq;
-        okv[k] = row && colv;
-        Km[k] = okm[k] ? m.K[c + jm] : 0.f;
-        bxm[k] = okm[k] ? m.bx[c + jm] : 0.f;
-        Kq[k] = okq[k] ? m.K[c + jq] : 0.f;
-        bxv[k] = okv[k] ? m.bx[c + jv] : 0.f;
-        azr[k] = row ? t.az[i] : 0.f;
-        btzr[k] = row ? t.bz[i] : 0.f;
+    for (int q = 0; q < 6; ++q) {
+        const int r = w.i0 - 3 + q;
+        Kr[q] = row_ok(g, r) ? bld(rM, vcol_, rowb(g, r)) : 0.f;
+        btzr[q] = btz_at(r);
     }
-    float Kz[NQ], btzq[NQ];
-    bool okz[NQ];
 #pragma unroll
-    for (int k = 0; k < NQ; ++k) {
-        int r = wave + 4 * k;
-        int i = i0 - 3 + r;
-        okz[k] = r < ZH && i >= 0 && i < g.Nz && colm;
-        Kz[k] = okz[k] ? m.K[(long long)i * g.Nx + jm] : 0.f;
-        btzq[k] = okz[k] ? t.bz[i] : 0.f;
+    for (int q = 0; q < 3; ++q) {
+        const int r = w.i0 - 2 + q;
+        wzr[q] = row_ok(g, r) ? zbhz[r] * bld(rM, vcol_, rowb(g, r) + 2u * FB) : 0.f;
     }
-    float bzv[NV], ahzv[NV], bhzv[NV];
-    bool okw[NV];
+    KW[0] = Kr[3];
+    KW[1] = Kr[4];
+    KW[2] = Kr[5];
+    KW[3] = 0.f;
+    const float bhz0 = zbhz[w.i0], ahz0 = zahz[w.i0];
+    float accZ0 = 0.f;
 #pragma unroll
-    for (int k = 0; k < NV; ++k) {
-        int r = wave + 4 * k;
-        int i = i0 - 2 + r;
-        okw[k] = r < VH && i >= 0 && i < g.Nz && colm;
-        bzv[k] = okw[k] ? m.bz[(long long)i * g.Nx + jm] : 0.f;
-        ahzv[k] = okw[k] ? t.ahz[i] : 0.f;
-        bhzv[k] = okw[k] ? t.bhz[i] : 0.f;
-    }
-
-    float accK[NR], accX[NR], accZ[NV];
-#pragma unroll
-    for (int k = 0; k < NR; ++k)
-        accK[k] = accX[k] = 0.f;
-#pragma unroll
-    for (int k = 0; k < NV; ++k)
-        accZ[k] = 0.f;
-
-    for (int s = s0; s < s1; ++s) {
-        const float *lpx = a.lpx_in.shot(s);
-        const float *lpz = a.lpz_in.shot(s);
-        const float *pn = a.pn.shot(s);
-        // beta_x K mu_px on the tile rows (+3 columns each side)
-        float mux[NR];
-#pragma unroll
-        for (int k = 0; k < NR; ++k) {
-            int r = wave + 4 * k;
-            long long c = (long long)(i0 + r) * g.Nx;
-            mux[k] = okm[k] ? lpx[c + jm] : 0.f;
-            sinj[r][lane] = 0.f;
-            sqx[r][lane + 3] = btxm * Km[k] * mux[k];
-            if (has_q)
-                sqx[r][eq] = okq[k] ? btxq * Kq[k] * lpx[c + jq] : 0.f;
+    for (int k = 0; k < SPG; ++k) {
+        const int s = w.s0 + k;
+        cur[k] = end[k] = 0;
+        nxt[k] = -1;
+        if (s < S && a.inject_n >= 0) {
+            const int li = list_index(sw, w, s);
+            cur[k] = uni(T->inj_ptr[li]);
+            end[k] = uni(T->inj_ptr[li + 1]);
+            if (cur[k] < end[k])
+                nxt[k] = uni(T->inj[cur[k]].x);
         }
-        // beta_z K mu_pz on the tile columns (+3 rows each side)
+        const unsigned kl = skoff(a.lin, k), kn = skoff(a.pn, k);
+        float qz[6], pnr[4];
 #pragma unroll
-        for (int k = 0; k < NQ; ++k) {
-            int r = wave + 4 * k;
-            if (r < ZH) {
-                int i = i0 - 3 + r;
-                float mu = 0.f;
-                if (okz[k])
-                    mu = in_pml(g, i, jm) ? lpz[pml_index(g, i, jm)]
-                                          : lpx[(long long)i * g.Nx + jm];
-                sqz[r][lane] = btzq[k] * Kz[k] * mu;
-            }
+        for (int q = 0; q < 6; ++q) {
+            const int r = w.i0 - 3 + q;
+            qz[q] = row_ok(g, r) ? Kr[q] * btzr[q] * muz_at(k, r) : 0.f;
         }
-        // forward pressure at n with a (-1, +2) halo, for the buoyancy imaging
 #pragma unroll
-        for (int k = 0; k < NN; ++k) {
-            int r = wave + 4 * k;
-            if (r < NH) {
-                int i = i0 - 1 + r;
-                bool row = i >= 0 && i < g.Nz;
-                long long c = (long long)i * g.Nx;
-                spn[r][lane + 1] = (row && colm) ? pn[c + jm] : 0.f;
-                if (lane < 3) {
-                    int e = lane == 0 ? 0 : TX + lane;
-                    int j = j0 - 1 + e;
-                    spn[r][e] = (row && j >= 0 && j < g.Nx) ? pn[c + j] : 0.f;
+        for (int q = 0; q < 4; ++q) {
+            const int r = w.i0 - 1 + q;
+            pnr[q] = row_ok(g, r) ? bld(rPn, vcol_, rowb(g, r) + kn) : 0.f;
+        }
+        // lvz_mid at rows i0-2 .. i0 (zero outside the grid)
+        float l[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int r = w.i0 - 2 + q;
+            l[q] = row_ok(g, r) ? bld(rLin, vcol_, rowb(g, r) + FB + kl) +
+                                      (kC1 * (qz[q + 2] - qz[q + 1]) + kC2 * (qz[q + 3] - qz[q])) * g.rdz
+                                : 0.f;
+            WZ[k][q] = wzr[q] * l[q];
+        }
+        accZ0 += l[2] * (-bhz0 * (kC1 * (pnr[2] - pnr[1]) + kC2 * (pnr[3] - pnr[0])) * g.rdz);
+        bst(rLout, vcolw_, rowb(g, w.i0) + FB + skoff(a.lout, k), ahz0 * l[2]);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int r = w.i0 + q;
+            MU[k][q] = row_ok(g, r) ? bld(rLin, vcol_, rowb(g, r) + 2u * FB + kl) : 0.f;
+            MZ[k][q] = row_ok(g, r) ? muz_at(k, r) : 0.f;
+            PN[k][q] = pnr[q + 1];
+        }
+        MU[k][3] = MZ[k][3] = PN[k][3] = 0.f;
+    }
+    {
+        const unsigned o = rowb(g, w.i0) + 2u * FB;
+        bst(rG, vcolw_, o, bld(rG, vcolw_, o) + accZ0);
+    }
+
+    auto load_row = [&](int r, ARow<SPG> &b) {
+        const unsigned rb = rowb(g, r);
+        const RowOff o = row_off(g, w, r);
+        const bool live = r < w.i1;
+        const unsigned ow = live ? vcolw_ : kOOB;
+        const unsigned ow1 = r + 1 < w.i1 ? vcolw_ : kOOB;   // this wave owns gbz row r+1
+        // split lane offset of row r+3 (kOOB where it has no split)
+        const ZRow z3 = zrow(g, r + 3);
+        const unsigned oz3 = live && r + 3 < g.Nz ? (z3.full ? vcol_ : vside_) : kOOB;
+        const unsigned zb = zrow(g, r).base;
+        b.K3 = bld(rM, o.o3, rb + 3u * rowN);
+        b.bx = bld(rM, o.o0, rb + FB);
+        b.bz1 = bld(rM, o.o1, rb + rowN + 2u * FB);
+        b.gK = bld(rG, ow, rb);
+        b.gX = bld(rG, ow, rb + FB);
+        b.gZ1 = bld(rG, ow1, rb + rowN + 2u * FB);
+#pragma unroll
+        for (int k = 0; k < SPG; ++k) {
+            const unsigned kl = skoff(a.lin, k), kn = skoff(a.pn, k), kn1 = skoff(a.pn1, k);
+            b.mu3[k] = bld(rLin, o.o3, rb + 3u * rowN + 2u * FB + kl);
+            b.mz3[k] = bld(rLin, oz3, z3.base + 3u * FB + kl);
+            b.pn3[k] = bld(rPn, o.o3, rb + 3u * rowN + kn);
+            b.lvz1[k] = bld(rLin, o.o1, rb + rowN + FB + kl);
+            b.lvx[k] = bld(rLin, o.o0, rb + kl);
+            b.pn1[k] = bld(rPn1, o.o0, rb + kn1);
+            b.z0[k] = bld(rPn, o.oz, zb + FB + kn);
+            b.z1[k] = bld(rPn1, o.oz, zb + FB + kn1);
+        }
+    };
+
+    auto row = [&](int i, const ARow<SPG> &b) {
+        KW[3] = b.K3;
+        const float bx = b.bx, bzn = b.bz1;
+        const unsigned rb = rowb(g, i);
+        const bool rn = row_ok(g, i + 1);
+        const bool more = i + 1 < w.i1;   // this wave owns lvz / gbz row i+1
+        const float ahz1 = rn ? zahz[i + 1] : 0.f, bhz1 = rn ? zbhz[i + 1] : 0.f;
+        const float az = zaz[i];
+        const float bK0 = KW[0] * btz_at(i), bK1 = KW[1] * btz_at(i + 1);
+        const float bK2 = KW[2] * btz_at(i + 2), bK3 = KW[3] * btz_at(i + 3);
+        const float wzn_c = bhz1 * bzn;
+        const bool pml3 = pml_at(i + 3);
+        const ZRow z = zrow(g, i);
+        const unsigned zcol = z.full ? vcolw_ : vsidew_;
+        const unsigned vzw = more ? vcolw_ : kOOB;
+        float numK = 0.f, accX = 0.f, accZ = 0.f;
+#pragma unroll
+        for (int k = 0; k < SPG; ++k) {
+            MU[k][3] = b.mu3[k];
+            MZ[k][3] = pml3 ? b.mz3[k] : b.mu3[k];
+            PN[k][3] = b.pn3[k];
+            // lvz_mid at row (i+1): D+z of beta_z K mu_pz
+            const float q0 = bK0 * MZ[k][0], q1 = bK1 * MZ[k][1];
+            const float q2 = bK2 * MZ[k][2], q3 = bK3 * MZ[k][3];
+            const float lvzm = rn ? b.lvz1[k] + (kC1 * (q2 - q1) + kC2 * (q3 - q0)) * g.rdz : 0.f;
+            accZ += lvzm * (-bhz1 * (kC1 * (PN[k][2] - PN[k][1]) + kC2 * (PN[k][3] - PN[k][0])) * g.rdz);
+            const float wzn = wzn_c * lvzm;
+            // lvx_mid at row i: D+x of beta_x K mu_px
+            const float mux = MU[k][0];
+            const float qx = btx * KW[0] * mux;
+            const float dqx = kC1 * (from_right(qx) - qx) + kC2 * (from_right2(qx) - from_left(qx));
+            const float lvxm = w.colok ? b.lvx[k] + dqx * g.rdx : 0.f;
+            const float p0 = PN[k][0];
+            const float dpx = kC1 * (from_right(p0) - p0) + kC2 * (from_right2(p0) - from_left(p0));
+            accX += lvxm * (-bhx * dpx * g.rdx);
+            const float wx = bhx * bx * lvxm;
+            const float dwx = kC1 * (wx - from_left(wx)) + kC2 * (from_right(wx) - from_left2(wx));
+            const float dwz = kC1 * (WZ[k][2] - WZ[k][1]) + kC2 * (wzn - WZ[k][0]);
+            const float tsum = dwx * g.rdx + dwz * g.rdz;
+            // R^T r^{n-1} at the nodes of row i this wave owns
+            float inj_v = 0.f;
+            if (i == nxt[k]) {
+                const int s = w.s0 + k;
+                int c = cur[k];
+                int4 e = T->inj[c];
+                for (;;) {
+                    if (w.lane == e.y) {
+                        float acc = 0.f;
+                        const int nrec = T->nrec, nt = T->nt;
+                        for (int q = T->inj_cptr[e.z]; q < T->inj_cptr[e.z + 1]; ++q)
+                            acc += T->inj_cw[q] *
+                                   a.resid[((long long)s * nrec + T->inj_crec[q]) * nt + a.inject_n];
+                        inj_v = acc;
+                    }
+                    if (++c >= end[k]) {
+                        e.x = -1;
+                        break;
+                    }
+                    e = T->inj[c];
+                    if (uni(e.x) != i)
+                        break;
                 }
+                cur[k] = c;
+                nxt[k] = uni(e.x);
+            }
+            const float muz = MZ[k][0];
+            const float z0 = b.z0[k], z1 = b.z1[k], p1 = b.pn1[k];
+            numK += mux * ((p1 - z1) - ax * (p0 - z0)) + muz * (z1 - az * z0);
+            const unsigned ko = skoff(a.lout, k);
+            bst(rLout, vcolw_, rb + 2u * FB + ko, ax * mux + tsum + inj_v);
+            bst(rLout, zcol, z.base + 3u * FB + ko, az * muz + tsum + inj_v);
+            bst(rLout, vcolw_, rb + ko, ahx * lvxm);
+            bst(rLout, vzw, rb + rowN + FB + ko, ahz1 * lvzm);
+            WZ[k][0] = WZ[k][1];
+            WZ[k][1] = WZ[k][2];
+            WZ[k][2] = wzn;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                MU[k][q] = MU[k][q + 1];
+                MZ[k][q] = MZ[k][q + 1];
+                PN[k][q] = PN[k][q + 1];
             }
         }
-        const float *lvxi = a.lvx_in.shot(s);
-        const float *lvzi = a.lvz_in.shot(s);
-        float nvx[NR], nvxe[NR], nvz[NV];
-#pragma unroll
-        for (int k = 0; k < NR; ++k) {
-            long long c = (long long)(i0 + wave + 4 * k) * g.Nx;
-            nvx[k] = okm[k] ? lvxi[c + jm] : 0.f;
-            nvxe[k] = okv[k] ? lvxi[c + jv] : 0.f;
-        }
-#pragma unroll
-        for (int k = 0; k < NV; ++k)
-            nvz[k] = okw[k] ? lvzi[(long long)(i0 - 2 + wave + 4 * k) * g.Nx + jm] : 0.f;
-        __syncthreads();
+        // one reciprocal per row for the bulk-modulus sensitivity (1 ulp)
+        const float rK = KW[0] != 0.f ? __builtin_amdgcn_rcpf(KW[0]) : 0.f;
+        bst(rG, vcolw_, rb, b.gK + numK * rK);
+        bst(rG, vcolw_, rb + FB, b.gX + accX);
+        bst(rG, vzw, rb + rowN + 2u * FB, b.gZ1 + accZ);
+        KW[0] = KW[1];
+        KW[1] = KW[2];
+        KW[2] = KW[3];
+    };
 
-        // adjoint source of the next (earlier) step at the nodes this tile owns
-        if (a.inject_n >= 0) {
-            int lo = tl.inj_ptr[s * ntiles + tile], hi = tl.inj_ptr[s * ntiles + tile + 1];
-            for (int e = lo + (int)threadIdx.x; e < hi; e += NTHR) {
-                int k = tl.inj_node[e];
-                float acc = 0.f;
-                for (int q = inj.cptr[k]; q < inj.cptr[k + 1]; ++q)
-                    acc += inj.cw[q] * a.resid[((long long)s * nrec + inj.crec[q]) * nt + a.inject_n];
-                long long c = inj.node[k];
-                sinj[(int)(c / g.Nx) - i0][(int)(c % g.Nx) - j0] = acc;
-            }
-        }
-
-        float *lvxo = a.lvx_out.shot(s);
-        float *lvzo = a.lvz_out.shot(s);
-        // x: lambda_vx_mid, its imaging and its beta_h bx product
-#pragma unroll
-        for (int k = 0; k < NR; ++k) {
-            int r = wave + 4 * k;
-            const float *q = sqx[r];
-            int c = lane + 2;  // vx LDS col; qx col of the same node is c+1
-            float d = kC1 * (q[c + 2] - q[c + 1]) + kC2 * (q[c + 3] - q[c]);
-            float v = okm[k] ? nvx[k] + d * g.rdx : 0.f;
-            swx[r][c] = bhxm * bxm[k] * v;
-            if (okm[k]) {
-                const float *pr = spn[r + 1];
-                int e = lane + 1;  // p^n col of node jm
-                float dp = kC1 * (pr[e + 1] - pr[e]) + kC2 * (pr[e + 2] - pr[e - 1]);
-                accX[k] += v * (-bhxm * dp * g.rdx);
-                lvxo[(long long)(i0 + r) * g.Nx + jm] = ahxm * v;
-            }
-            if (has_v) {
-                float de = kC1 * (q[ev + 2] - q[ev + 1]) + kC2 * (q[ev + 3] - q[ev]);
-                float ve = okv[k] ? nvxe[k] + de * g.rdx : 0.f;
-                swx[r][ev] = bhxv * bxv[k] * ve;
-            }
-        }
-        // z: lambda_vz_mid, its imaging and its beta_h bz product
-#pragma unroll
-        for (int k = 0; k < NV; ++k) {
-            int r = wave + 4 * k;
-            if (r < VH) {
-                // vz row i = i0-2+r; qz row of node i is r+1; p^n row of node i is r-1
-                float d = kC1 * (sqz[r + 2][lane] - sqz[r + 1][lane]) +
-                          kC2 * (sqz[r + 3][lane] - sqz[r][lane]);
-                float v = okw[k] ? nvz[k] + d * g.rdz : 0.f;
-                swz[r][lane] = bhzv[k] * bzv[k] * v;
-                if (okw[k] && r >= 2 && r < TZ + 2) {
-                    int e = lane + 1;
-                    float dp = kC1 * (spn[r][e] - spn[r - 1][e]) + kC2 * (spn[r + 1][e] - spn[r - 2][e]);
-                    accZ[k] += v * (-bhzv[k] * dp * g.rdz);
-                    lvzo[(long long)(i0 - 2 + r) * g.Nx + jm] = ahzv[k] * v;
-                }
-            }
-        }
-        __syncthreads();
-
-        // pressure components on the tile and the bulk-modulus imaging
-        float *lpxo = a.lpx_out.shot(s);
-        float *lpzo = a.lpz_out.shot(s);
-        const float *pn1 = a.pn1.shot(s);
-        const float *pzn = a.pzn.shot(s);
-        const float *pzn1 = a.pzn1.shot(s);
-#pragma unroll
-        for (int k = 0; k < NR; ++k) {
-            if (!okm[k])
-                continue;
-            int r = wave + 4 * k;
-            int i = i0 + r;
-            int c = lane + 2;
-            float tsum = (kC1 * (swx[r][c] - swx[r][c - 1]) + kC2 * (swx[r][c + 1] - swx[r][c - 2])) * g.rdx +
-                         (kC1 * (swz[r + 2][lane] - swz[r + 1][lane]) +
-                          kC2 * (swz[r + 3][lane] - swz[r][lane])) * g.rdz;
-            long long cc = (long long)i * g.Nx + jm;
-            float p0 = spn[r + 1][lane + 1];
-            float p1 = pn1[cc];
-            float mx = mux[k];
-            if (in_pml(g, i, jm)) {
-                long long qi = pml_index(g, i, jm);
-                float mz = lpz[qi];
-                float z0 = pzn[qi], z1 = pzn1[qi];
-                accK[k] += (mx * ((p1 - z1) - axm * (p0 - z0)) + mz * (z1 - azr[k] * z0)) / Km[k];
-                lpxo[cc] = axm * mx + tsum + sinj[r][lane];
-                lpzo[qi] = azr[k] * mz + tsum + sinj[r][lane];
-            } else {
-                accK[k] += mx * (p1 - p0) / Km[k];
-                lpxo[cc] = mx + tsum + sinj[r][lane];
-            }
-        }
-        __syncthreads();
-    }
-
-    // one read-modify-write of this group's partial sensitivities
-    float *gK = a.gpart + (long long)grp * 3 * g.N;
-    float *gX = gK + g.N;
-    float *gZ = gX + g.N;
-#pragma unroll
-    for (int k = 0; k < NR; ++k) {
-        if (okm[k]) {
-            long long cc = (long long)(i0 + wave + 4 * k) * g.Nx + jm;
-            gK[cc] += accK[k];
-            gX[cc] += accX[k];
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < NV; ++k) {
-        int r = wave + 4 * k;
-        if (okw[k] && r >= 2 && r < TZ + 2)
-            gZ[(long long)(i0 - 2 + r) * g.Nx + jm] += accZ[k];
+    ARow<SPG> A, B;
+    load_row(w.i0, A);
+    for (int i = w.i0;;) {
+        load_row(i + 1, B);
+        row(i, A);
+        if (++i >= w.i1)
+            break;
+        load_row(i + 1, A);
+        row(i, B);
+        if (++i >= w.i1)
+            break;
     }
 }
 
-template <int TZ>
-void fwd_launch(const Geo &g, const Pml &t, const Mdl &m, const Src &src, const Rec &rec,
-                const TileLists &tl, int S, int groups, const FwdStep &a, hipStream_t st)
+inline unsigned blocks_of(const Sweep &sw)
 {
-    int ntx, ntiles = fused_tiles(g, TZ, &ntx);
-    hipLaunchKernelGGL(k_fwd<TZ>, dim3(ntiles * groups), dim3(NTHR), 0, st, g, t, m, src, rec,
-                       tl, S, groups, ntx, ntiles, a);
-}
-
-template <int TZ>
-void adj_launch(const Geo &g, const Pml &t, const Mdl &m, const Src &src, const Inj &inj,
-                int nrec, const TileLists &tl, int S, int groups, const AdjStep &a,
-                hipStream_t st)
-{
-    int ntx, ntiles = fused_tiles(g, TZ, &ntx);
-    hipLaunchKernelGGL(k_adj<TZ>, dim3(ntiles * groups), dim3(NTHR), 0, st, g, t, m, inj, nrec,
-                       src.nt, tl, S, groups, ntx, ntiles, a);
+    return (unsigned)((sw.nwaves + NTHR / WAVE - 1) / (NTHR / WAVE));
 }
 
 }  // namespace
 
-bool fused_tile_supported(int tz) { return tz == 8 || tz == 16 || tz == 32; }
+bool fused_spg_supported(int spg) { return spg == 1 || spg == 2 || spg == 4 || spg == 8; }
 
-int fused_tiles(const Geo &g, int tz, int *ntx)
+Sweep sweep_of(const Geo &g, int S, int band_rows, int spg)
 {
-    *ntx = (g.Nx + TX - 1) / TX;
-    return *ntx * ((g.Nz + tz - 1) / tz);
+    Sweep sw;
+    sw.H = band_rows;
+    sw.spg = spg;
+    sw.nstrips = (g.Nx + kStripOut - 1) / kStripOut;
+    sw.nbands = (g.Nz + band_rows - 1) / band_rows;
+    sw.ngroups = (S + spg - 1) / spg;
+    sw.nwaves = sw.nstrips * sw.nbands * sw.ngroups;
+    return sw;
 }
 
-void launch_fused_fwd(const Geo &g, const Pml &t, const Mdl &m, const Src &src, const Rec &rec,
-                      const TileLists &tl, int S, int groups, int tz, const FwdStep &a,
+void launch_fused_fwd(const Geo &g, const float *tabs, const float *model,
+                      const SweepTables *T, int S, const Sweep &sw, const FwdStep &a,
                       hipStream_t st)
 {
-    switch (tz) {
-    case 8: fwd_launch<8>(g, t, m, src, rec, tl, S, groups, a, st); break;
-    case 32: fwd_launch<32>(g, t, m, src, rec, tl, S, groups, a, st); break;
-    default: fwd_launch<16>(g, t, m, src, rec, tl, S, groups, a, st); break;
+    dim3 grid(blocks_of(sw)), blk(NTHR);
+    switch (sw.spg) {
+    case 1: hipLaunchKernelGGL(k_fwd<1>, grid, blk, 0, st, g, tabs, model, T, S, sw, a); break;
+    case 2: hipLaunchKernelGGL(k_fwd<2>, grid, blk, 0, st, g, tabs, model, T, S, sw, a); break;
+    case 8: hipLaunchKernelGGL(k_fwd<8>, grid, blk, 0, st, g, tabs, model, T, S, sw, a); break;
+    default: hipLaunchKernelGGL(k_fwd<4>, grid, blk, 0, st, g, tabs, model, T, S, sw, a); break;
     }
 }
 
-void launch_fused_adj(const Geo &g, const Pml &t, const Mdl &m, const Src &src, const Inj &inj,
-                      int nrec, const TileLists &tl, int S, int groups, int tz,
-                      const AdjStep &a, hipStream_t st)
+void launch_fused_adj(const Geo &g, const float *tabs, const float *model,
+                      const SweepTables *T, int S, const Sweep &sw, const AdjStep &a,
+                      hipStream_t st)
 {
-    switch (tz) {
-    case 8: adj_launch<8>(g, t, m, src, inj, nrec, tl, S, groups, a, st); break;
-    case 32: adj_launch<32>(g, t, m, src, inj, nrec, tl, S, groups, a, st); break;
-    default: adj_launch<16>(g, t, m, src, inj, nrec, tl, S, groups, a, st); break;
+    dim3 grid(blocks_of(sw)), blk(NTHR);
+    switch (sw.spg) {
+    case 1: hipLaunchKernelGGL(k_adj<1>, grid, blk, 0, st, g, tabs, model, T, S, sw, a); break;
+    case 2: hipLaunchKernelGGL(k_adj<2>, grid, blk, 0, st, g, tabs, model, T, S, sw, a); break;
+    case 8: hipLaunchKernelGGL(k_adj<8>, grid, blk, 0, st, g, tabs, model, T, S, sw, a); break;
+    default: hipLaunchKernelGGL(k_adj<4>, grid, blk, 0, st, g, tabs, model, T, S, sw, a); break;
     }
 }
 

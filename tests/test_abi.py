@@ -65,11 +65,13 @@ def test_bad_arguments_rejected(kw):
 
 
 def test_bad_exec_rejected():
-    rc, _ = _create(exec_=L.FwiExec(0, 0, 12, 0))
+    rc, _ = _create(exec_=L.FwiExec(0, 0, 2, 0))
     assert rc == -1
     rc, _ = _create(exec_=L.FwiExec(7, 0, 0, 0))
     assert rc == -1
-    rc, _ = _create(exec_=L.FwiExec(0, 0, 0, 5))
+    rc, _ = _create(exec_=L.FwiExec(0, 0, 0, 3))
+    assert rc == -1
+    rc, _ = _create(exec_=L.FwiExec(0, -1, 0, 0))
     assert rc == -1
 
 

@@ -99,13 +99,13 @@ def test_forward_config1(api, c1, mode):
     assert gather_err(tr, c1.d) <= TOL
 
 
-@pytest.mark.parametrize("mode,tile_z,groups", [("plain", 0, 0), ("batched", 8, 1),
-                                                ("batched", 16, 2), ("batched", 32, 6),
-                                                ("batched", 16, 4)])
-def test_forward_multi_tile_ragged(api, small, mode, tile_z, groups):
+@pytest.mark.parametrize("mode,rows,spg", [("plain", 0, 0), ("batched", 8, 1),
+                                          ("batched", 16, 2), ("batched", 37, 4),
+                                          ("batched", 173, 8), ("batched", 4, 4)])
+def test_forward_multi_tile_ragged(api, small, mode, rows, spg):
     w = small.w
-    p = api.Plan(agrid(api, w), w.src_xz, w.rec_xz, mode=mode, tile_z=tile_z,
-                 shot_groups=groups)
+    p = api.Plan(agrid(api, w), w.src_xz, w.rec_xz, mode=mode, band_rows=rows,
+                 shots_per_group=spg)
     tr = p.forward("k-rho", small.K0, small.r0, small.f).cpu().numpy()
     assert gather_err(tr, small.d) <= TOL
 
@@ -144,15 +144,16 @@ def test_adjoint_config1(api, c1, mode, param):
     assert maxrel(g2.cpu().numpy(), e2) <= TOL
 
 
-@pytest.mark.parametrize("mode,tile_z,groups,ckpt", [("plain", 0, 0, 0), ("plain", 0, 0, 23),
-                                                     ("batched", 8, 3, 0),
-                                                     ("batched", 16, 2, 17),
-                                                     ("batched", 32, 1, 300),
-                                                     ("batched", 16, 6, 1)])
-def test_adjoint_multi_tile_ragged(api, small, mode, tile_z, groups, ckpt):
+@pytest.mark.parametrize("mode,rows,spg,ckpt", [("plain", 0, 0, 0), ("plain", 0, 0, 23),
+                                               ("batched", 8, 1, 0),
+                                               ("batched", 16, 2, 17),
+                                               ("batched", 37, 4, 300),
+                                               ("batched", 173, 8, 1),
+                                               ("batched", 4, 4, 9)])
+def test_adjoint_multi_tile_ragged(api, small, mode, rows, spg, ckpt):
     w = small.w
-    p = api.Plan(agrid(api, w), w.src_xz, w.rec_xz, mode=mode, tile_z=tile_z,
-                 shot_groups=groups, ckpt_every=ckpt)
+    p = api.Plan(agrid(api, w), w.src_xz, w.rec_xz, mode=mode, band_rows=rows,
+                 shots_per_group=spg, ckpt_every=ckpt)
     gK, gr = p.adjoint("k-rho", small.K0, small.r0, small.f, small.adj)
     assert maxrel(gK.cpu().numpy(), small.gK) <= TOL
     assert maxrel(gr.cpu().numpy(), small.gr) <= TOL
@@ -162,8 +163,8 @@ def test_checkpointed_equals_full_history_bitwise(api, small):
     w = small.w
     out = []
     for k in (w.nt, 7):
-        p = api.Plan(agrid(api, w), w.src_xz, w.rec_xz, ckpt_every=k, tile_z=16,
-                     shot_groups=2)
+        p = api.Plan(agrid(api, w), w.src_xz, w.rec_xz, ckpt_every=k, band_rows=16,
+                     shots_per_group=2)
         out.append([x.cpu().numpy() for x in p.adjoint(0, small.K0, small.r0, small.f,
                                                        small.adj)])
     np.testing.assert_array_equal(out[0][0], out[1][0])

@@ -5,13 +5,15 @@ import numpy as np
 from paper_1804_01184_amd import workloads as W
 
 
-def test_candidates_cover_tiles_and_groups():
+def test_candidates_cover_rows_and_shot_groups():
     from paper_1804_01184_amd import autotune
     c = autotune.candidates(481, 481, 40)
-    assert {tz for tz, _ in c} == {8, 16, 32}
-    for tz, G in c:
-        assert 1 <= G <= 40
-    assert autotune.candidates(21, 21, 1) == [(8, 1), (16, 1), (32, 1)]
+    assert {spg for _, spg in c} == {1, 2, 4, 8}
+    for H, spg in c:
+        waves = 9 * ((481 + H - 1) // H) * ((40 + spg - 1) // spg)
+        assert 512 <= waves <= 32768
+    small = autotune.candidates(21, 21, 1)
+    assert small and all(spg in (1, 2) for _, spg in small)
 
 
 def test_workloads_seeded_and_shaped():
