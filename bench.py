@@ -11,8 +11,8 @@ Prints one JSON line.  Inputs are synthetic (workloads.py), generated and
 resident in HBM before the timed region.
 """
 import argparse
+import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -34,10 +34,21 @@ def parse():
     ap.add_argument("--workload", default="c2", choices=["c2", "c3"])
     ap.add_argument("--band-rows", type=int, default=0)
     ap.add_argument("--shots-per-group", type=int, default=0)
+    ap.add_argument("--lane-cols", type=int, default=0)
     ap.add_argument("--ckpt-every", type=int, default=0)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=0, help="time steps of the CPU sample")
+    ap.add_argument("--time-steps", type=int, default=0,
+                    help="run the workload for this many time steps instead of its own "
+                         "(short runs under hardware-counter profiling; per-launch work is "
+                         "unchanged)")
+    ap.add_argument("--no-kernel-timing", action="store_true",
+                    help="no per-launch event timing (for hardware-counter runs); the "
+                         "roofline entry is then omitted")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one 1 GiB elementwise kernel (reads 1 GiB, writes 1 GiB) and "
+                         "exit: the reference for the HBM traffic counters")
     return ap.parse_args()
 
 
@@ -49,19 +60,56 @@ def workload(name):
     return w
 
 
-def algorithmic_bytes(plan_info, S, G):
-    """Bytes one launch of each batched kernel must move at least (FP32):
-    forward step: read and write vx, vz, p for every cell and shot, the pz
-    split in the absorbing layer, the model (K, bx, bz) once per shot group;
-    adjoint step: the same for the adjoint state, plus p^n and p^{n+1} (and
-    their layer splits), plus one read-modify-write of the three gradient
-    accumulators per group."""
+def algorithmic_bytes(plan_info, S):
+    """Bytes one launch of each batched kernel must move at least (FP32),
+    with the model and the gradient touched once per launch:
+    forward step: read and write vx, vz, p for every cell and shot (24 B),
+    the pz split in the absorbing layer (8 B per layer cell), the model K,
+    bx, bz once (12 B per cell);
+    adjoint step: read and write the adjoint vx, vz, p (24 B) and its split
+    (8 B), read p^n and p^{n+1} (8 B) and their splits (8 B), the model once
+    and one read-modify-write of the three gradient arrays (12 + 24 B per
+    cell).  Re-reads the kernels make beyond this (halo rows, the model and
+    the partial gradient once per shot group) show in the measured traffic."""
     N = plan_info["Nz"] * plan_info["Nx"]
     fp = plan_info["pml_cells"] / N
-    fwd = N * S * (24 + 8 * fp) + G * N * 12
-    adj = N * S * (32 + 16 * fp) + G * N * (12 + 24)
+    fwd = N * S * (24 + 8 * fp) + N * 12
+    adj = N * S * (32 + 16 * fp) + N * (12 + 24)
     return {"fwd_step": fwd, "adj_step": adj, "per_cell_fwd": fwd / (N * S),
             "per_cell_adj": adj / (N * S), "pml_fraction": fp}
+
+
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1804_01184_amd", "csrc", "k_fused.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def measured_traffic(kernel, decomposition):
+    """HBM bytes per launch of `kernel` from the committed counter profile
+    (FETCH_SIZE and WRITE_SIZE scaled by the copy calibration), or None if
+    the profile was taken with another kernel source or decomposition."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            prof = json.load(fh)
+        with open(KERNEL_SOURCE, "rb") as fh:
+            sha = hashlib.sha256(fh.read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if prof.get("source_sha256") != sha or prof.get("decomposition") != decomposition:
+        return None
+    k = prof.get("kernels", {}).get(kernel)
+    return None if k is None else int(k["bytes_per_launch"])
+
+
+def copy_calibration():
+    import torch
+    torch.cuda.set_device(0)
+    n = 256 * 1024 * 1024
+    a = torch.empty(n, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a).fill_(0.0)
+    torch.cuda.synchronize()
+    torch.mul(a, 2.0, out=b)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration": {"bytes_read": 4 * n, "bytes_written": 4 * n}}))
 
 
 def cpu_baseline(w, steps):
@@ -87,6 +135,9 @@ def cpu_baseline(w, steps):
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported (shots would "
               "shard across GPUs with one all-reduce of the gradient; not built here)",
@@ -98,12 +149,15 @@ def main():
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
     w = workload(args.workload)
+    if args.time_steps:
+        w = w.subset(nt=args.time_steps)
     grid = api.Grid.of(w)
     f = torch.tensor(w.wavelet(), dtype=torch.float32, device=dev)
     vp0 = torch.tensor(w.vp_start, dtype=torch.float32, device=dev)
     rho0 = torch.tensor(w.rho_start, dtype=torch.float32, device=dev)
     plan = api.Plan(grid, w.src_xz, w.rec_xz, band_rows=args.band_rows,
-                    shots_per_group=args.shots_per_group, ckpt_every=args.ckpt_every)
+                    shots_per_group=args.shots_per_group, lane_cols=args.lane_cols,
+                    ckpt_every=args.ckpt_every)
     info = plan.info
     obs = plan.forward("vp-rho", w.vp_true, w.rho_true, f)
     K0, r0 = api.model_convert("vp-rho", "k-rho", vp0, rho0)
@@ -122,7 +176,7 @@ def main():
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
-    plan.timing(True)
+    plan.timing(not args.no_kernel_timing)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev[0].record(stream)
@@ -139,16 +193,22 @@ def main():
     value = cells / (ms * 1e-3) / 1e9
 
     S, G = w.nshots, info["shot_groups"]
-    ab = algorithmic_bytes(info, S, G)
-    dom = max(("fwd_step", "adj_step"), key=lambda k: per_class[k][1])
-    n_launch, dom_ms = per_class[dom]
-    avg_s = dom_ms / n_launch * 1e-3
-    achieved = ab[dom] / avg_s / 1e9
-    roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
-            "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-            "traffic": None, "avg_launch_us": round(avg_s * 1e6, 2), "launches": n_launch,
-            "bytes_per_launch": int(ab[dom]),
-            "bytes_per_cell_step": round(ab["per_cell_" + dom.split("_")[0]], 2)}
+    ab = algorithmic_bytes(info, S)
+    roof = None
+    if not args.no_kernel_timing:
+        dom = max(("fwd_step", "adj_step"), key=lambda k: per_class[k][1])
+        n_launch, dom_ms = per_class[dom]
+        avg_s = dom_ms / n_launch * 1e-3
+        achieved = ab[dom] / avg_s / 1e9
+        decomp = {"band_rows": info["band_rows"], "shots_per_group": info["shots_per_group"],
+                  "lane_cols": info["lane_cols"], "workload": w.name}
+        roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(achieved / PEAK_HBM_GBS, 4),
+                "traffic": measured_traffic(dom, decomp),
+                "avg_launch_us": round(avg_s * 1e6, 2), "launches": n_launch,
+                "bytes_per_launch": int(ab[dom]),
+                "bytes_per_cell_step": round(ab["per_cell_" + dom.split("_")[0]], 2)}
     classes = {k: {"launches": v[0], "ms": round(v[1], 3)} for k, v in per_class.items()
                if v[0]}
 
@@ -184,7 +244,8 @@ def main():
                                f"{w.nshots} shots x {w.nrec} receivers, gradient in K-rho "
                                f"chain-ruled to Vp-rho, Ip-rho, Vp-Ip",
                    "cell_steps": cells, "band_rows": info["band_rows"],
-                   "shots_per_group": info["shots_per_group"], "shot_groups": G,
+                   "shots_per_group": info["shots_per_group"], "lane_cols": info["lane_cols"],
+                   "shot_groups": G,
                    "ckpt_every": info["ckpt_every"], "segments": info["segments"]},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
                        "p99": round(float(np.percentile(lat, 99)), 3)},

@@ -109,15 +109,20 @@ typedef struct {
                              >= nt keeps the whole pressure history            */
     int32_t band_rows;    /* batched kernels: rows each wave sweeps (4..4096);
                              0: chosen from the grid and shot count          */
-    int32_t shots_per_group; /* batched kernels: shots a wave advances together,
-                             1, 2, 4 or 8; 0: default                         */
+    int32_t shots_per_group; /* batched kernels: shots a wave advances together;
+                             0: default                                      */
+    int32_t lane_cols;    /* batched kernels: adjacent grid columns each lane
+                             holds, 1, 2 or 4; 0: default.  Supported
+                             (shots_per_group, lane_cols) pairs: lane_cols 1
+                             with 1, 2, 4, 8; lane_cols 2 with 1, 2, 4;
+                             lane_cols 4 with 1, 2 (else FWI_EINVAL)         */
 } fwi_exec;
 
 typedef struct {
     int32_t Nz, Nx;           /* padded grid                                  */
     int32_t ckpt_every;       /* k actually used                              */
     int32_t segments;         /* ceil(nt / k)                                 */
-    int32_t band_rows, shots_per_group;
+    int32_t band_rows, shots_per_group, lane_cols;
     int32_t shot_groups;      /* ceil(nshots / shots_per_group)               */
     int32_t mode;
     int32_t device;           /* HIP device the plan lives on                 */

@@ -46,13 +46,15 @@ class FwiAcq(ctypes.Structure):
 
 class FwiExec(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("ckpt_every", ctypes.c_int32),
-                ("band_rows", ctypes.c_int32), ("shots_per_group", ctypes.c_int32)]
+                ("band_rows", ctypes.c_int32), ("shots_per_group", ctypes.c_int32),
+                ("lane_cols", ctypes.c_int32)]
 
 
 class FwiPlanInfo(ctypes.Structure):
     _fields_ = [("Nz", ctypes.c_int32), ("Nx", ctypes.c_int32), ("ckpt_every", ctypes.c_int32),
                 ("segments", ctypes.c_int32), ("band_rows", ctypes.c_int32),
-                ("shots_per_group", ctypes.c_int32), ("shot_groups", ctypes.c_int32),
+                ("shots_per_group", ctypes.c_int32), ("lane_cols", ctypes.c_int32),
+                ("shot_groups", ctypes.c_int32),
                 ("mode", ctypes.c_int32),
                 ("device", ctypes.c_int32), ("pml_cells", ctypes.c_int64),
                 ("cfl", ctypes.c_double)]

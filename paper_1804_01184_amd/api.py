@@ -64,12 +64,13 @@ class Plan:
     """A propagation problem: grid, sources, receivers and execution mode.
 
     mode: "batched" (all shots per fused launch) or "plain" (one shot per
-    launch, separate velocity/pressure launches).  band_rows and
-    shots_per_group set the batched decomposition (0: defaults).
+    launch, separate velocity/pressure launches).  band_rows,
+    shots_per_group and lane_cols set the batched decomposition (0:
+    defaults).
     """
 
     def __init__(self, grid: Grid, src_xz, rec_xz, wavelet_per_shot=False, mode="batched",
-                 ckpt_every=0, band_rows=0, shots_per_group=0, device=None):
+                 ckpt_every=0, band_rows=0, shots_per_group=0, lane_cols=0, device=None):
         self.grid = grid
         self.device = (torch.device("cuda", torch.cuda.current_device()) if device is None
                        else torch.device(device))
@@ -86,7 +87,7 @@ class Plan:
         a = L.FwiAcq(self.nshots, self.nrec, int(self.wavelet_per_shot),
                      src.ctypes.data_as(dp), rec.ctypes.data_as(dp))
         m = {"batched": L.FWI_EXEC_BATCHED, "plain": L.FWI_EXEC_PLAIN}[mode]
-        ex = L.FwiExec(m, int(ckpt_every), int(band_rows), int(shots_per_group))
+        ex = L.FwiExec(m, int(ckpt_every), int(band_rows), int(shots_per_group), int(lane_cols))
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             L.check(L.lib().fwi_plan_create(ctypes.byref(g), ctypes.byref(a), ctypes.byref(ex),

@@ -66,10 +66,7 @@ struct fwi_plan {
     float *inj_cw = nullptr;
     int inj_nodes = 0;
     std::vector<int> shot_node_ptr;  // [S+1] node range of each shot
-    // per-(shot, band, strip) lists of the batched kernels
-    int *wl_samp_ptr = nullptr, *wl_inj_ptr = nullptr;
-    int4 *wl_samp = nullptr, *wl_inj = nullptr;
-    SweepTables *sweep_tabs = nullptr;   // device copy of the table pointers
+    SweepTables *sweep_tabs = nullptr;   // device copy of the source tables
     std::vector<int2> h_src_ij;
     std::vector<float4> h_src_w;
     // per-launch event timing (instrumentation)
@@ -100,25 +97,34 @@ hipEvent_t take_event(fwi_plan *p)
 }
 
 // Brackets the launches issued in its scope with events when timing is on.
+// With by_launch, the events are not recorded here: the caller hands them
+// (b, e) to a launch that stamps them with its dispatch's start and end.
 struct Timed {
     fwi_plan *p;
     hipStream_t st;
     int cls;
+    bool by_launch;
     hipEvent_t b = nullptr, e = nullptr;
-    Timed(fwi_plan *p_, hipStream_t st_, int cls_) : p(p_), st(st_), cls(cls_)
+    Timed(fwi_plan *p_, hipStream_t st_, int cls_, bool by_launch_ = false)
+        : p(p_), st(st_), cls(cls_), by_launch(by_launch_)
     {
         if (!p->timing)
             return;
         b = take_event(p);
         e = take_event(p);
-        if (b && e)
+        if (!b || !e) {
+            b = e = nullptr;
+            return;
+        }
+        if (!by_launch)
             (void)hipEventRecord(b, st);
     }
     ~Timed()
     {
         if (!b || !e)
             return;
-        (void)hipEventRecord(e, st);
+        if (!by_launch)
+            (void)hipEventRecord(e, st);
         p->marks.push_back({cls, b, e});
     }
 };
@@ -154,9 +160,11 @@ Layout layout(const fwi_plan *p, int op)
 {
     Layout L{};
     size_t off = 0;
+    // every array is followed by at least 64 spare bytes (the batched
+    // kernels may read a few bytes past a field and discard them)
     auto take = [&](size_t floats) {
         size_t o = off;
-        off = align_up(off + floats * sizeof(float), kAlign);
+        off = align_up(off + floats * sizeof(float) + 64, kAlign);
         return o;
     };
     const Geo &g = p->geo;
@@ -306,10 +314,8 @@ Recd recd(const Fld &f, long long floats)
     return Recd{f.p, (unsigned)(f.ss * sizeof(float)), (unsigned)(floats * sizeof(float))};
 }
 
-// One forward step n -> n+1 for shots [s0, s0+nb) from `in` to `out`.  The
-// batched kernel also writes trace sample n-1 (from `in`) when traces != 0.
-void step_fwd(const Ctx &c, int s0, int nb, const State &in, const State &out, int n,
-              float *traces = nullptr)
+// One forward step n -> n+1 for shots [s0, s0+nb) from `in` to `out`.
+void step_fwd(const Ctx &c, int s0, int nb, const State &in, const State &out, int n)
 {
     const fwi_plan *p = c.pl;
     const Geo &g = p->geo;
@@ -331,11 +337,9 @@ void step_fwd(const Ctx &c, int s0, int nb, const State &in, const State &out, i
         a.vout = recd(out.vx, 2 * g.N);
         a.pout = recd(out.p, g.N + g.Npml);
         a.Q = src.Q;
-        a.traces = traces;
         a.n = n;
-        a.sample_n = (traces && n > 0) ? n - 1 : -1;
-        Timed tm(c.pl, c.st, FWI_KC_FWD_STEP);
-        launch_fused_fwd(g, p->pml, c.m.K, p->sweep_tabs, p->S, p->sweep, a, c.st);
+        Timed tm(c.pl, c.st, FWI_KC_FWD_STEP, true);
+        launch_fused_fwd(g, p->pml, c.m.K, p->sweep_tabs, p->S, p->sweep, a, c.st, tm.b, tm.e);
     }
 }
 
@@ -347,9 +351,7 @@ void step_adj(const Ctx &c, int s0, int nb, const State &in, const State &out, F
 {
     const fwi_plan *p = c.pl;
     const Geo &g = p->geo;
-    // the batched kernel of step n+1 already added R^T r^n to its output,
-    // except for the first adjoint step
-    if (p->mode == FWI_EXEC_PLAIN || n == p->grid.nt - 1) {
+    {
         Timed tm(c.pl, c.st, FWI_KC_INJECT);
         launch_inject(g, inj_of(c, s0, real_shots(p, s0, nb)), resid, p->nrec, p->grid.nt, n,
                       in.p, s0, c.st);
@@ -374,11 +376,9 @@ void step_adj(const Ctx &c, int s0, int nb, const State &in, const State &out, F
         a.pn = recd(pn, g.N + g.Npml);
         a.pn1 = recd(pn1, g.N + g.Npml);
         a.gpart = gpart;
-        a.resid = resid;
         a.n = n;
-        a.inject_n = n > 0 ? n - 1 : -1;
-        Timed tm(c.pl, c.st, FWI_KC_ADJ_STEP);
-        launch_fused_adj(g, p->pml, c.m.K, p->sweep_tabs, p->S, p->sweep, a, c.st);
+        Timed tm(c.pl, c.st, FWI_KC_ADJ_STEP, true);
+        launch_fused_adj(g, p->pml, c.m.K, p->sweep_tabs, p->S, p->sweep, a, c.st, tm.b, tm.e);
     }
 }
 
@@ -420,9 +420,8 @@ void sweep_forward(const Ctx &c, int s0, int nb, bool keep, float *traces)
             out = state_at(c.f(c.L.ckpt) + (size_t)(n1 / k - 1) * nb * p->SS, p);
             next_cw = -1;
         }
-        bool batched = p->mode != FWI_EXEC_PLAIN;
-        step_fwd(c, s0, nb, cur, out, n, batched ? traces : nullptr);
-        if (traces && (!batched || n == nt - 1)) {
+        step_fwd(c, s0, nb, cur, out, n);
+        if (traces) {
             Timed tm(c.pl, c.st, FWI_KC_SAMPLE);
             launch_sample(p->geo, out.p, out.pz, rec, real_shots(p, s0, nb), traces, nt, n, c.st);
         }
@@ -667,16 +666,21 @@ fwi_status fwi_plan_create(const fwi_grid *grid, const fwi_acq *acq, const fwi_e
         return fail(FWI_EUNSTABLE, "vmax dt sqrt(1/dx^2+1/dz^2)(9/8+1/24) = %.4f > 1", sn);
     if (acq->nshots < 1 || acq->nrec < 1 || !acq->src_xz || !acq->rec_xz)
         return fail(FWI_EINVAL, "need at least one shot and one receiver with positions");
-    fwi_exec ex{FWI_EXEC_BATCHED, 0, 0, 0};
+    fwi_exec ex{FWI_EXEC_BATCHED, 0, 0, 0, 0};
     if (exec)
         ex = *exec;
     if (ex.mode != FWI_EXEC_BATCHED && ex.mode != FWI_EXEC_PLAIN)
         return fail(FWI_EINVAL, "unknown exec mode %d", ex.mode);
     if (ex.band_rows != 0 && (ex.band_rows < 4 || ex.band_rows > 4096))
         return fail(FWI_EINVAL, "band_rows %d out of range (4..4096)", ex.band_rows);
-    if (ex.shots_per_group != 0 && !fused_spg_supported(ex.shots_per_group))
-        return fail(FWI_EINVAL, "shots_per_group %d not supported (1, 2, 4 or 8)",
-                    ex.shots_per_group);
+    if (ex.shots_per_group < 0 || ex.lane_cols < 0 ||
+        (ex.shots_per_group != 0 && ex.lane_cols != 0 &&
+         !fused_supported(ex.shots_per_group, ex.lane_cols)) ||
+        (ex.shots_per_group != 0 && ex.lane_cols == 0 &&
+         !fused_supported(ex.shots_per_group, 1)) ||
+        (ex.lane_cols != 0 && ex.shots_per_group == 0 && !fused_supported(1, ex.lane_cols)))
+        return fail(FWI_EINVAL, "shots_per_group %d with lane_cols %d not supported",
+                    ex.shots_per_group, ex.lane_cols);
     if (ex.ckpt_every < 0)
         return fail(FWI_EINVAL, "ckpt_every out of range");
 
@@ -709,19 +713,25 @@ fwi_status fwi_plan_create(const fwi_grid *grid, const fwi_acq *acq, const fwi_e
     p->k = std::max(1, std::min(k, G.nt));
     p->nseg = (G.nt + p->k - 1) / p->k;
     {
-        // shots advanced together by a wave; band height so that the launch
-        // has about 2048 waves (8 per CU)
-        int spg = ex.shots_per_group;
-        if (spg == 0)
+        // defaults (from decomposition sweeps on MI355X): up to four shots per
+        // wave, one column per lane, bands short enough for about 4096
+        // waves, 8 to 64 rows
+        int spg = ex.shots_per_group, cols = ex.lane_cols;
+        if (spg == 0) {
             spg = p->S >= 4 ? 4 : (p->S >= 2 ? 2 : 1);
+            if (cols != 0 && !fused_supported(spg, cols))
+                spg = 1;
+        }
+        if (cols == 0)
+            cols = 1;
         int H = ex.band_rows;
         if (H == 0) {
-            Sweep one = sweep_of(g, p->S, (int)Nz, spg);
+            Sweep one = sweep_of(g, p->S, (int)Nz, spg, cols);
             long long per_band = (long long)one.nstrips * one.ngroups;
-            long long bands = std::max<long long>(1, (2048 + per_band - 1) / per_band);
-            H = (int)std::min<long long>(256, std::max<long long>(8, (Nz + bands - 1) / bands));
+            long long bands = std::max<long long>(1, (4096 + per_band - 1) / per_band);
+            H = (int)std::min<long long>(64, std::max<long long>(8, (Nz + bands - 1) / bands));
         }
-        p->sweep = sweep_of(g, p->S, H, spg);
+        p->sweep = sweep_of(g, p->S, H, spg, cols);
         p->Spad = p->mode == FWI_EXEC_PLAIN ? p->S : p->sweep.ngroups * spg;
         // the batched kernels address a shot group's records, the model and
         // a partial gradient with 32-bit byte offsets below 2^31
@@ -811,40 +821,6 @@ fwi_status fwi_plan_create(const fwi_grid *grid, const fwi_acq *acq, const fwi_e
     inj_cptr.push_back((int)inj_crec.size());
     p->inj_nodes = (int)inj_node.size();
 
-    // per-(shot, band, strip) lists for the batched kernels, sorted by row
-    const Sweep &sw = p->sweep;
-    const int nlist = S * sw.nbands * sw.nstrips;
-    std::vector<int> samp_ptr((size_t)nlist + 1, 0), inj_ptr2((size_t)nlist + 1, 0);
-    std::vector<int4> samp_e, inj_e;
-    {
-        std::vector<std::vector<int4>> bucket(nlist);
-        auto place = [&](int s, long long c, int idx) {
-            int i = (int)(c / g.Nx), j = (int)(c % g.Nx);
-            int strip = j / kStripOut, band = i / sw.H;
-            int lane = j - strip * kStripOut + 3;
-            bucket[((size_t)s * sw.nbands + band) * sw.nstrips + strip].push_back(
-                make_int4(i, lane, idx, 0));
-        };
-        auto flatten = [&](std::vector<int> &ptr, std::vector<int4> &out) {
-            for (int l = 0; l < nlist; ++l) {
-                auto &b = bucket[l];
-                std::stable_sort(b.begin(), b.end(), [](const int4 &x, const int4 &y) {
-                    return x.x != y.x ? x.x < y.x : x.y < y.y;
-                });
-                out.insert(out.end(), b.begin(), b.end());
-                ptr[l + 1] = (int)out.size();
-                b.clear();
-            }
-        };
-        for (int s = 0; s < S; ++s)
-            for (int r = 0; r < nr; ++r)
-                place(s, rec_idx[(size_t)s * nr + r], r);
-        flatten(samp_ptr, samp_e);
-        for (int s = 0; s < S; ++s)
-            for (int k = p->shot_node_ptr[s]; k < p->shot_node_ptr[s + 1]; ++k)
-                place(s, inj_node[k], k);
-        flatten(inj_ptr2, inj_e);
-    }
     if (hipGetDevice(&p->device) != hipSuccess) {
         delete p;
         return fail(FWI_EDEVICE, "no HIP device");
@@ -864,8 +840,6 @@ fwi_status fwi_plan_create(const fwi_grid *grid, const fwi_acq *acq, const fwi_e
     size_t o_ip = take(sizeof(int) * inj_cptr.size());
     size_t o_ir = take(sizeof(int) * inj_crec.size());
     size_t o_iw = take(sizeof(float) * inj_cw.size());
-    size_t o_wsp = take(sizeof(int) * samp_ptr.size()), o_ws = take(sizeof(int4) * samp_e.size());
-    size_t o_wip = take(sizeof(int) * inj_ptr2.size()), o_wi = take(sizeof(int4) * inj_e.size());
     size_t o_st = take(sizeof(SweepTables));
     if (hipMalloc(&p->dev, off) != hipSuccess) {
         (void)hipGetLastError();
@@ -883,23 +857,10 @@ fwi_status fwi_plan_create(const fwi_grid *grid, const fwi_acq *acq, const fwi_e
     p->inj_cptr = (int *)(d + o_ip);
     p->inj_crec = (int *)(d + o_ir);
     p->inj_cw = (float *)(d + o_iw);
-    p->wl_samp_ptr = (int *)(d + o_wsp);
-    p->wl_samp = (int4 *)(d + o_ws);
-    p->wl_inj_ptr = (int *)(d + o_wip);
-    p->wl_inj = (int4 *)(d + o_wi);
     p->sweep_tabs = (SweepTables *)(d + o_st);
     SweepTables st_host;
     st_host.src_ij = p->src_ij;
     st_host.src_w = p->src_w;
-    st_host.rec_w = p->rec_w;
-    st_host.samp_ptr = p->wl_samp_ptr;
-    st_host.samp = p->wl_samp;
-    st_host.inj_ptr = p->wl_inj_ptr;
-    st_host.inj = p->wl_inj;
-    st_host.inj_cptr = p->inj_cptr;
-    st_host.inj_crec = p->inj_crec;
-    st_host.inj_cw = p->inj_cw;
-    st_host.nrec = p->nrec;
     st_host.nt = G.nt;
     bool ok = true;
     auto up = [&](void *dst, const void *src, size_t bytes) {
@@ -915,10 +876,6 @@ fwi_status fwi_plan_create(const fwi_grid *grid, const fwi_acq *acq, const fwi_e
     up(p->inj_cptr, inj_cptr.data(), sizeof(int) * inj_cptr.size());
     up(p->inj_crec, inj_crec.data(), sizeof(int) * inj_crec.size());
     up(p->inj_cw, inj_cw.data(), sizeof(float) * inj_cw.size());
-    up(p->wl_samp_ptr, samp_ptr.data(), sizeof(int) * samp_ptr.size());
-    up(p->wl_samp, samp_e.data(), sizeof(int4) * samp_e.size());
-    up(p->wl_inj_ptr, inj_ptr2.data(), sizeof(int) * inj_ptr2.size());
-    up(p->wl_inj, inj_e.data(), sizeof(int4) * inj_e.size());
     up(p->sweep_tabs, &st_host, sizeof(SweepTables));
     launch_pml_tables(g, G.vmax, G.npml > 0 ? G.pml_r : 0.5, G.dx, G.dz, G.dt, p->pml, nullptr);
     if (!ok || hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
@@ -952,6 +909,7 @@ fwi_status fwi_plan_get_info(const fwi_plan *p, fwi_plan_info *info)
     info->segments = p->nseg;
     info->band_rows = p->sweep.H;
     info->shots_per_group = p->mode == FWI_EXEC_PLAIN ? 1 : p->sweep.spg;
+    info->lane_cols = p->mode == FWI_EXEC_PLAIN ? 1 : p->sweep.cols;
     info->shot_groups = groups_of(p);
     info->mode = p->mode;
     info->device = p->device;

@@ -138,34 +138,26 @@ void launch_plain_adj_b(const Geo &g, const Pml &t, const Mdl &m, const float *l
 
 // ----------------------------------------------------------------- fused
 // Decomposition of the batched kernels: each wave64 owns a strip of
-// kStripOut output columns (plus a 3-column halo each side) and a band of H
-// rows, for a group of spg shots.  Wave w -> (group, band, strip), strip
-// fastest.
-constexpr int kStripOut = 58;
+// strip_cols(cols) output columns (plus halo_cols(cols) halo columns on each
+// side; a lane holds `cols` adjacent columns) and a band of H rows, for a
+// group of spg shots.  Wave w -> (band, group, strip), strip fastest.
 struct Sweep {
     int nstrips, nbands, ngroups, nwaves;
-    int H;     // band rows
-    int spg;   // shots per group
+    int H;      // band rows
+    int spg;    // shots per group
+    int cols;   // columns per lane
 };
+bool fused_supported(int spg, int cols);
+int strip_cols(int cols);
+int halo_cols(int cols);
+Sweep sweep_of(const Geo &g, int S, int band_rows, int spg, int cols);
 
-// Geometry tables of a plan for the batched kernels, kept in device memory
-// so that the kernels take one pointer to them.  samp / inj are per-(shot,
-// band, strip) work lists, CSR over (shot * nbands + band) * nstrips +
-// strip, entries (row, lane, index, 0) sorted by row: receivers whose
-// bilinear cell starts at (row, lane) (index = receiver), and
-// receiver-touched nodes (index = entry of inj_cptr).
+// Source tables of a plan for the batched kernels, kept in device memory
+// so that the kernels take one pointer to them.
 struct SweepTables {
-    const int2 *src_ij;
-    const float4 *src_w;
-    const float4 *rec_w;      // [S][nrec]
-    const int *samp_ptr;
-    const int4 *samp;
-    const int *inj_ptr;
-    const int4 *inj;
-    const int *inj_cptr;
-    const int *inj_crec;
-    const float *inj_cw;
-    int nrec, nt;
+    const int2 *src_ij;     // [S]
+    const float4 *src_w;    // [S]
+    int nt;
 };
 
 // The records of a batch of shots: shot s starts at base + s * sbytes bytes
@@ -183,27 +175,22 @@ struct Recd {
 struct FwdStep {
     Recd vin, pin, vout, pout;
     const float *Q;     // [S][nt] time integral of the wavelet at n+1/2
-    float *traces;      // [S][nrec][nt]
     int n;              // time step being taken (n -> n+1)
-    int sample_n;       // >= 0: write trace sample sample_n from pin
 };
 struct AdjStep {
     Recd lin, lout, pn, pn1;
-    float *gpart;           // [groups][3][N]: gK, gbx, gbz
-    const float *resid;     // [S][nrec][nt]
+    float *gpart;       // [groups][3][N]: gK, gbx, gbz
     int n;
-    int inject_n;           // >= 0: add R^T r^{inject_n} to the output pressure
 };
 
-bool fused_spg_supported(int spg);
-Sweep sweep_of(const Geo &g, int S, int band_rows, int spg);
 // tabs: the 8 damping tables (x: alpha, beta, alpha_h, beta_h; then z) in
-// one block; model: K, bx, bz as one block of 3N floats.
+// one block; model: K, bx, bz as one block of 3N floats.  e0 / e1 (may be
+// null) receive the start and end times of the kernel's dispatch.
 void launch_fused_fwd(const Geo &g, const float *tabs, const float *model,
                       const SweepTables *tab_dev, int S, const Sweep &sw, const FwdStep &a,
-                      hipStream_t st);
+                      hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 void launch_fused_adj(const Geo &g, const float *tabs, const float *model,
                       const SweepTables *tab_dev, int S, const Sweep &sw, const AdjStep &a,
-                      hipStream_t st);
+                      hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 
 }  // namespace fwi

@@ -1,16 +1,20 @@
 // Batched path: one launch per time step covers every shot of the model.
 //
-// Each wave64 owns a strip of 64 consecutive columns (58 output columns and
-// a 3-column halo on each side) and a band of rows, and marches down the
-// band one row at a time.  The vertical parts of the stencils live in
-// per-lane register windows (the rows above and below the current one), the
-// horizontal parts are exchanged between lanes with DPP wave shifts, so the
-// kernels use no LDS and no barriers: waves are independent and occupancy is
-// limited only by registers.  Velocity and pressure half-steps are fused:
-// the new velocities of a row are formed and consumed by the new pressure of
-// the same row in registers, so every wavefield value is read once and
-// written once per step (ping-pong buffers, since neighbouring strips and
-// bands still read the old level).
+// Each wave64 owns a strip of consecutive columns and a band of rows, and
+// marches down the band one row at a time.  A lane holds C adjacent columns
+// (C = 1, 2 or 4), read and written with one 4C-byte buffer access, so the
+// per-row scalar work and the memory instructions are shared by C cells.
+// The strip is 64 C columns wide, of which ceil(3 / C) lanes on each side
+// are halo (the stencil reaches 3 columns through the two half steps).  The
+// vertical parts of the stencils live in per-lane register windows (the
+// rows above and below the current one); the horizontal parts take the
+// neighbouring lane's edge columns with DPP wave shifts, so the kernels use
+// no LDS and no barriers: waves are independent and occupancy is limited
+// only by registers.  Velocity and pressure half-steps are fused: the new
+// velocities of a row are formed and consumed by the new pressure of the
+// same row in registers, so every wavefield value is read once and written
+// once per step (ping-pong buffers, since neighbouring strips and bands
+// still read the old level).
 //
 // A wave advances SPG shots of the same model together, row by row: the
 // model coefficients of a row are read once for all of them, and in the
@@ -22,17 +26,24 @@
 // The loads of row i+1 are issued before the arithmetic and the stores of
 // row i into one of two alternating register sets, so their latency overlaps
 // a row of work and no register copies (which would wait for them) are
-// needed.  Loads are unconditional: rows outside the grid or past the band
-// are read through an out-of-range lane offset, which returns zero without
-// touching memory, so the memory counters see the same sequence on every
-// row.
+// needed.  The adjoint reads the values it needs only at the end of a row
+// (the stored forward pressure of step n+1, the splits, the partial
+// gradient) into a single set, issued at the start of the row before the
+// next row's loads.  Loads are unconditional: rows outside the grid or past
+// the band are read through an out-of-range lane offset, which returns zero
+// without touching memory, so the memory counters see the same sequence on
+// every row.
 //
-// Receiver sampling (forward) and the adjoint-source injection (adjoint,
-// for the next, earlier step) are done by the wave owning the node, from
-// per-(shot, strip, band) lists sorted by row.  Workgroups are numbered so
-// that each XCD receives a contiguous range of waves (neighbouring strips
-// and bands share its L2).
+// Receiver sampling and the adjoint-source injection are separate small
+// launches, one thread per receiver or node (done inside the sweep, they
+// made the waves holding receivers walk their lists serially, a few memory
+// round trips per node, and those waves set the length of the launch).
+// Workgroups are numbered so that each XCD receives a contiguous range of
+// waves (neighbouring strips, the shot groups of a band and neighbouring
+// bands share its L2).
 #include "fwi2d_internal.h"
+
+#include <hip/hip_ext.h>
 
 namespace fwi {
 
@@ -42,21 +53,32 @@ constexpr int WAVE = 64;
 constexpr int HALO = 3;
 constexpr int NTHR = 256;  // 4 independent waves per workgroup
 
+template <int C>
+struct Lanes {
+    static constexpr int HL = (HALO + C - 1) / C;   // halo lanes on each side
+    static constexpr int W = (WAVE - 2 * HL) * C;   // output columns per strip
+};
+
 // Buffer accesses: a uniform resource per record group, a uniform byte
 // offset for the row (scalar offset) and a per-lane byte offset for the
 // column.  A lane offset of kOOB lies past every resource, so its loads
 // return 0 (ghost cells outside the grid, cells without an absorbing-layer
 // split, rows past the band) and its stores are dropped (halo lanes).  The
-// host keeps every resource and every row offset below 2^31 bytes.
+// host keeps every resource and every row offset below 2^31 bytes, and
+// every resource is followed by at least kSlack allocated bytes (the lane
+// holding the last grid column may read past it; those values are masked).
 using rsrc_t = __amdgpu_buffer_rsrc_t;
 constexpr unsigned kOOB = 0x80000000u;
 constexpr int kRsrcWord3 = 0x00020000;
+constexpr unsigned kSlack = 16;
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ inline rsrc_t res(const float *p, unsigned bytes)
 {
-    return __builtin_amdgcn_make_buffer_rsrc((void *)p, (short)0, (int)bytes, kRsrcWord3);
+    return __builtin_amdgcn_make_buffer_rsrc((void *)p, (short)0, (int)(bytes + kSlack), kRsrcWord3);
 }
-// (the b32 builtins move raw 32-bit words: bit casts, not conversions)
+// (the buffer builtins move raw 32-bit words: bit casts, not conversions)
 __device__ inline float bld(rsrc_t r, unsigned voff, unsigned soff)
 {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
@@ -64,6 +86,52 @@ __device__ inline float bld(rsrc_t r, unsigned voff, unsigned soff)
 __device__ inline void bst(rsrc_t r, unsigned voff, unsigned soff, float v)
 {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)voff, (int)soff, 0);
+}
+// Vector components are copied to scalars before the bit cast: a bit cast
+// of a component expression (x.y) is not lowered to that component.
+template <int C>
+__device__ inline void vld(rsrc_t r, unsigned voff, unsigned soff, float (&o)[C])
+{
+    if constexpr (C == 1) {
+        o[0] = bld(r, voff, soff);
+    } else if constexpr (C == 2) {
+        const u32x2 x = __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const unsigned e = x[c];
+            o[c] = __builtin_bit_cast(float, e);
+        }
+    } else {
+        const u32x4 x = __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const unsigned e = x[c];
+            o[c] = __builtin_bit_cast(float, e);
+        }
+    }
+}
+template <int C>
+__device__ inline void vst(rsrc_t r, unsigned voff, unsigned soff, const float (&v)[C])
+{
+    if constexpr (C == 1) {
+        bst(r, voff, soff, v[0]);
+    } else if constexpr (C == 2) {
+        u32x2 x;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const float e = v[c];
+            x[c] = __builtin_bit_cast(unsigned, e);
+        }
+        __builtin_amdgcn_raw_buffer_store_b64(x, r, (int)voff, (int)soff, 0);
+    } else {
+        u32x4 x;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const float e = v[c];
+            x[c] = __builtin_bit_cast(unsigned, e);
+        }
+        __builtin_amdgcn_raw_buffer_store_b128(x, r, (int)voff, (int)soff, 0);
+    }
 }
 
 // by-value min / max (reference-returning overloads applied to kernel
@@ -93,54 +161,118 @@ __device__ inline float wave_shift(float v)
 }
 __device__ inline float from_right(float v) { return wave_shift<kDppWaveShl1>(v); }
 __device__ inline float from_left(float v) { return wave_shift<kDppWaveShr1>(v); }
-__device__ inline float from_right2(float v) { return from_right(from_right(v)); }
-__device__ inline float from_left2(float v) { return from_left(from_left(v)); }
 
+// Fourth-order staggered differences of a row held C columns per lane
+// (without the 1/h factor).  Forward: at j + 1/2 from the nodes j-1 .. j+2;
+// backward: at node j from the half nodes j-3/2 .. j+1/2 (stored at j-2 .. j+1).
+template <int C>
+__device__ inline void dfwd(const float (&v)[C], float (&d)[C])
+{
+    const float r0 = from_right(v[0]);                          // column C
+    const float r1 = C >= 2 ? from_right(v[C >= 2 ? 1 : 0]) : from_right(r0);  // column C+1
+    const float l1 = from_left(v[C - 1]);                       // column -1
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const float p1 = c + 1 < C ? v[c + 1 < C ? c + 1 : 0] : r0;
+        const float p2 = c + 2 < C ? v[c + 2 < C ? c + 2 : 0] : (c + 2 == C ? r0 : r1);
+        const float m1 = c >= 1 ? v[c >= 1 ? c - 1 : 0] : l1;
+        d[c] = kC1 * (p1 - v[c]) + kC2 * (p2 - m1);
+    }
+}
+template <int C>
+__device__ inline void dbwd(const float (&v)[C], float (&d)[C])
+{
+    const float l1 = from_left(v[C - 1]);                                      // column -1
+    const float l2 = C >= 2 ? from_left(v[C >= 2 ? C - 2 : 0]) : from_left(l1);  // column -2
+    const float r0 = from_right(v[0]);                                         // column C
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const float m1 = c >= 1 ? v[c >= 1 ? c - 1 : 0] : l1;
+        const float m2 = c >= 2 ? v[c >= 2 ? c - 2 : 0] : (c == 1 ? l1 : l2);
+        const float p1 = c + 1 < C ? v[c + 1 < C ? c + 1 : 0] : r0;
+        d[c] = kC1 * (v[c] - m1) + kC2 * (p1 - m2);
+    }
+}
+
+template <int C>
 struct WaveGeo {
-    int lane, j;
-    bool colok;       // column inside the grid
-    unsigned vcol;    // lane column byte offset, kOOB outside the grid
-    unsigned vcolw;   // same for stores: kOOB unless an output lane
-    unsigned vside;   // column part of the split index on middle rows
-    unsigned vsidew;  // same for stores
-    int i0, i1;       // owned rows [i0, i1)
-    int s0;           // shots [s0, s0 + SPG)
+    int lane, j0;         // lane and its first column
+    bool colok[C];        // column inside the grid
+    unsigned vcol;        // lane byte offset for loads, kOOB if its first column is outside
+    unsigned vcolw;       // for whole-lane stores: kOOB unless an output lane fully inside
+    unsigned vtail[C];    // element stores of the output lane holding the last column
+    unsigned zf[C], zs[C];    // split offsets on full rows / middle rows (loads)
+    unsigned zfw[C], zsw[C];  // the same for stores
+    bool colpml[C];       // column inside the absorbing layer
+    int i0, i1;           // owned rows [i0, i1)
+    int s0;               // shots [s0, s0 + SPG)
     int strip, band, grp;
 };
 
-__device__ inline bool wave_geo(const Geo &g, const Sweep &sw, WaveGeo &w)
+template <int C>
+__device__ inline bool wave_geo(const Geo &g, const Sweep &sw, WaveGeo<C> &w)
 {
+    constexpr int HL = Lanes<C>::HL, W = Lanes<C>::W;
     w.lane = threadIdx.x & (WAVE - 1);
     // wave index, made provably uniform so that everything derived from it
     // (rows, shots, buffer resources) lives in scalar registers
     int wid = uni(xcd_item(blockIdx.x, gridDim.x) * (NTHR / WAVE) + (int)(threadIdx.x / WAVE));
     if (wid >= sw.nwaves)
         return false;
+    // strip fastest, then shot group, then band: the groups of a band run
+    // together, so the model rows they all read are shared in L2
     w.strip = wid % sw.nstrips;
     int rest = wid / sw.nstrips;
-    w.band = rest % sw.nbands;
-    w.grp = rest / sw.nbands;
-    w.j = w.strip * kStripOut - HALO + w.lane;
-    w.colok = w.j >= 0 && w.j < g.Nx;
-    const bool outl = w.colok && w.lane >= HALO && w.lane < WAVE - HALO;
-    w.vcol = w.colok ? 4u * (unsigned)w.j : kOOB;
-    w.vcolw = outl ? w.vcol : kOOB;
-    unsigned side = kOOB;
-    if (w.colok && w.j < g.npml)
-        side = 4u * (unsigned)w.j;
-    else if (w.colok && w.j >= g.Nx - g.npml)
-        side = 4u * (unsigned)(w.j - (g.Nx - 2 * g.npml));
-    w.vside = side;
-    w.vsidew = outl ? side : kOOB;
+    w.grp = rest % sw.ngroups;
+    w.band = rest / sw.ngroups;
+    w.j0 = w.strip * W + (w.lane - HL) * C;
+    const bool outl = w.lane >= HL && w.lane < WAVE - HL;
+    const bool in0 = w.j0 >= 0 && w.j0 < g.Nx;
+    const bool whole = in0 && w.j0 + C - 1 < g.Nx;
+    w.vcol = in0 ? 4u * (unsigned)w.j0 : kOOB;
+    w.vcolw = outl && whole ? w.vcol : kOOB;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const int j = w.j0 + c;
+        w.colok[c] = j >= 0 && j < g.Nx;
+        w.colpml[c] = j < g.npml || j >= g.Nx - g.npml;
+        w.vtail[c] = outl && in0 && !whole && w.colok[c] ? 4u * (unsigned)j : kOOB;
+        unsigned side = kOOB;
+        if (w.colok[c] && j < g.npml)
+            side = 4u * (unsigned)j;
+        else if (w.colok[c] && j >= g.Nx - g.npml)
+            side = 4u * (unsigned)(j - (g.Nx - 2 * g.npml));
+        w.zf[c] = w.colok[c] ? 4u * (unsigned)j : kOOB;
+        w.zs[c] = side;
+        w.zfw[c] = outl ? w.zf[c] : kOOB;
+        w.zsw[c] = outl ? side : kOOB;
+    }
     w.i0 = w.band * sw.H;
     w.i1 = imin(w.i0 + sw.H, g.Nz);
     w.s0 = w.grp * sw.spg;
     return true;
 }
 
-__device__ inline int list_index(const Sweep &sw, const WaveGeo &w, int s)
+// Whole-lane store plus the element stores of the lane holding the last
+// grid column (on = false drops both).
+template <int C>
+__device__ inline void vst_row(rsrc_t r, const WaveGeo<C> &w, bool on, unsigned soff,
+                               const float (&v)[C])
 {
-    return (s * sw.nbands + w.band) * sw.nstrips + w.strip;
+    vst<C>(r, on ? w.vcolw : kOOB, soff, v);
+#pragma unroll
+    for (int c = 0; c + 1 < C; ++c)
+        bst(r, on ? w.vtail[c] : kOOB, soff, v[c]);
+}
+
+// Zero the elements past the last grid column (they were read from the
+// next row or past the field and feed horizontal differences).
+template <int C>
+__device__ inline void mask_cols(const WaveGeo<C> &w, float (&v)[C])
+{
+#pragma unroll
+    for (int c = 1; c < C; ++c)
+        v[c] = w.colok[c] ? v[c] : 0.f;
 }
 
 __device__ inline bool row_ok(const Geo &g, int i) { return (unsigned)i < (unsigned)g.Nz; }
@@ -165,6 +297,29 @@ __device__ inline ZRow zrow(const Geo &g, int i)
                     : 4u * (unsigned)(2 * g.npml * g.Nx + (i - g.npml) * 2 * g.npml);
     return z;
 }
+// Select between two lane values.  The empty asm makes both operands
+// values first, so the choice is not turned into a choice between two
+// addresses of the wave geometry (which would keep it in scratch memory).
+__device__ inline unsigned pick(bool c, unsigned a, unsigned b)
+{
+    asm("" : "+v"(a), "+v"(b));
+    return c ? a : b;
+}
+// Split element offsets of row i for loads (live = false: none) and stores.
+template <int C>
+__device__ inline void zoffs(const WaveGeo<C> &w, const ZRow &z, bool live, unsigned (&o)[C])
+{
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+        o[c] = live ? pick(z.full, w.zf[c], w.zs[c]) : kOOB;
+}
+template <int C>
+__device__ inline void zoffs_w(const WaveGeo<C> &w, const ZRow &z, unsigned (&o)[C])
+{
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+        o[c] = pick(z.full, w.zfw[c], w.zsw[c]);
+}
 
 // One resource for the records of shots [s0, s0 + SPG): shot s0 + k sits
 // k * sbytes bytes after the first (uniform offset skoff).
@@ -175,42 +330,61 @@ __device__ inline rsrc_t grp_res(const Recd &r, int s0, int spg)
 }
 __device__ inline unsigned skoff(const Recd &r, int k) { return (unsigned)k * r.sbytes; }
 
-// Lane offsets of the loads of row r: the lane column, or kOOB where the row
+// Lane offsets of the loads of row r: the lane offset, or kOOB where the row
 // (r, r+1, r+3) lies outside the grid or r lies past the band.
 struct RowOff {
-    unsigned o0, o1, o3, oz;
+    unsigned o0, o1, o3;
 };
-__device__ inline RowOff row_off(const Geo &g, const WaveGeo &w, int r)
+template <int C>
+__device__ inline RowOff row_off(const Geo &g, const WaveGeo<C> &w, int r)
 {
     const bool live = r < w.i1;
     RowOff o;
     o.o0 = live ? w.vcol : kOOB;
     o.o1 = live && r + 1 < g.Nz ? w.vcol : kOOB;
     o.o3 = live && r + 3 < g.Nz ? w.vcol : kOOB;
-    o.oz = live ? (zrow(g, r).full ? w.vcol : w.vside) : kOOB;
     return o;
+}
+
+// x tables of the lane's columns (alpha, beta at nodes, alpha_h, beta_h at
+// half nodes); zero outside the grid.
+template <int C>
+struct XTab {
+    float ax[C], btx[C], ahx[C], bhx[C];
+};
+template <int C>
+__device__ inline void xtab(const Geo &g, const float *__restrict__ tabs, const WaveGeo<C> &w,
+                            XTab<C> &t)
+{
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const int jc = imin(imax(w.j0 + c, 0), g.Nx - 1);
+        const bool ok = w.colok[c];
+        t.ax[c] = ok ? tabs[jc] : 0.f;
+        t.btx[c] = ok ? tabs[g.Nx + jc] : 0.f;
+        t.ahx[c] = ok ? tabs[2 * g.Nx + jc] : 0.f;
+        t.bhx[c] = ok ? tabs[3 * g.Nx + jc] : 0.f;
+    }
 }
 
 // ---------------------------------------------------------------- forward
 
-template <int SPG>
+template <int SPG, int C>
 struct FRow {
-    float K, bx, bz1;                           // K, bx at r; bz at r+1
-    float p3[SPG], vz1[SPG], vx[SPG], pz[SPG];  // p at r+3, vz at r+1, vx and split at r
+    float K[C], bx[C], bz1[C];                              // K, bx at r; bz at r+1
+    float p3[SPG][C], vz1[SPG][C], vx[SPG][C], pz[SPG][C];  // p at r+3, vz at r+1, vx, split at r
 };
 
-template <int SPG>
+template <int SPG, int C>
 __global__ void __launch_bounds__(NTHR)
     k_fwd(Geo g, const float *__restrict__ tabs, const float *model, const SweepTables *T, int S,
           Sweep sw, FwdStep a)
 {
-    WaveGeo w;
-    if (!wave_geo(g, sw, w))
+    WaveGeo<C> w;
+    if (!wave_geo<C>(g, sw, w))
         return;
-    const unsigned vcol_ = w.vcol, vcolw_ = w.vcolw, vsidew_ = w.vsidew;
-    const int jc = imin(imax(w.j, 0), g.Nx - 1);
-    const float ax = w.colok ? tabs[jc] : 0.f, btx = w.colok ? tabs[g.Nx + jc] : 0.f;
-    const float ahx = w.colok ? tabs[2 * g.Nx + jc] : 0.f, bhx = w.colok ? tabs[3 * g.Nx + jc] : 0.f;
+    XTab<C> xt;
+    xtab<C>(g, tabs, w, xt);
     // z tables: alpha, beta at nodes, alpha_h, beta_h at half nodes
     const float *__restrict__ zaz = tabs + 4 * g.Nx, *__restrict__ zbz = zaz + g.Nz;
     const float *__restrict__ zahz = zbz + g.Nz, *__restrict__ zbhz = zahz + g.Nz;
@@ -220,148 +394,150 @@ __global__ void __launch_bounds__(NTHR)
     const rsrc_t rPin = grp_res(a.pin, w.s0, SPG), rVin = grp_res(a.vin, w.s0, SPG);
     const rsrc_t rPout = grp_res(a.pout, w.s0, SPG), rVout = grp_res(a.vout, w.s0, SPG);
 
-    float P[SPG][4];   // pressure rows i .. i+3
-    float VZ[SPG][3];  // new vz rows i-2 .. i
-    // receiver list position, end and row of the next entry (-1: none)
-    int cur[SPG], end[SPG], nxt[SPG];
+    float P[SPG][4][C];   // pressure rows i .. i+3
+    float VZ[SPG][3][C];  // new vz rows i-2 .. i
     // source: first row of its bilinear cell and this lane's injection
     // weights dt Q w / (dx dz) on that row and the next
     int srow[SPG];
-    float swa[SPG], swb[SPG];
+    float swa[SPG][C], swb[SPG][C];
 #pragma unroll
     for (int k = 0; k < SPG; ++k) {
         const int s = w.s0 + k;
-        cur[k] = end[k] = 0;
-        nxt[k] = -1;
         srow[k] = -8;
-        swa[k] = swb[k] = 0.f;
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            swa[k][c] = swb[k][c] = 0.f;
         if (s < S) {
             const int2 sij = T->src_ij[s];
             const float4 sw4 = T->src_w[s];
             const float dq = g.dt * a.Q[(long long)s * T->nt + a.n];
-            const int dj = w.j - sij.y;
             srow[k] = uni(sij.x);
-            swa[k] = dj == 0 ? dq * sw4.x : (dj == 1 ? dq * sw4.y : 0.f);
-            swb[k] = dj == 0 ? dq * sw4.z : (dj == 1 ? dq * sw4.w : 0.f);
-            if (a.sample_n >= 0) {
-                const int li = list_index(sw, w, s);
-                cur[k] = uni(T->samp_ptr[li]);
-                end[k] = uni(T->samp_ptr[li + 1]);
-                if (cur[k] < end[k])
-                    nxt[k] = uni(T->samp[cur[k]].x);
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const int dj = w.j0 + c - sij.y;
+                swa[k][c] = dj == 0 ? dq * sw4.x : (dj == 1 ? dq * sw4.y : 0.f);
+                swb[k][c] = dj == 0 ? dq * sw4.z : (dj == 1 ? dq * sw4.w : 0.f);
             }
         }
         const unsigned op = skoff(a.pin, k), ovz = FB + skoff(a.vin, k);
-        float pr[6];
+        float pr[6][C];
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
             const int r = w.i0 - 3 + q;
-            pr[q] = row_ok(g, r) ? bld(rPin, vcol_, rowb(g, r) + op) : 0.f;
+            vld<C>(rPin, row_ok(g, r) ? w.vcol : kOOB, row_ok(g, r) ? rowb(g, r) + op : 0u, pr[q]);
+            mask_cols<C>(w, pr[q]);
         }
         // vz at rows i0-2 .. i0 from p rows r-1 .. r+2
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
             const int r = w.i0 - 2 + q;
-            float v = 0.f;
-            if (row_ok(g, r)) {
-                const unsigned rb = rowb(g, r);
-                const float bz = bld(rM, vcol_, rb + 2u * FB);
-                v = zahz[r] * bld(rVin, vcol_, rb + ovz) -
-                    zbhz[r] * bz * (kC1 * (pr[q + 2] - pr[q + 1]) + kC2 * (pr[q + 3] - pr[q])) * g.rdz;
-            }
-            VZ[k][q] = v;
+            const bool ok = row_ok(g, r);
+            const unsigned rb = ok ? rowb(g, r) : 0u, vo = ok ? w.vcol : kOOB;
+            float bz[C], vz[C];
+            vld<C>(rM, vo, rb + 2u * FB, bz);
+            vld<C>(rVin, vo, rb + ovz, vz);
+            const float ahz = ok ? zahz[r] : 0.f, bhz = ok ? zbhz[r] : 0.f;
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                VZ[k][q][c] = ahz * vz[c] -
+                              bhz * bz[c] *
+                                  (kC1 * (pr[q + 2][c] - pr[q + 1][c]) + kC2 * (pr[q + 3][c] - pr[q][c])) *
+                                  g.rdz;
         }
-        bst(rVout, vcolw_, rowb(g, w.i0) + FB + skoff(a.vout, k), VZ[k][2]);
-        P[k][0] = pr[3];
-        P[k][1] = pr[4];
-        P[k][2] = pr[5];
-        P[k][3] = 0.f;
+        vst_row<C>(rVout, w, true, rowb(g, w.i0) + FB + skoff(a.vout, k), VZ[k][2]);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            P[k][0][c] = pr[3][c];
+            P[k][1][c] = pr[4][c];
+            P[k][2][c] = pr[5][c];
+            P[k][3][c] = 0.f;
+        }
     }
 
-    auto load_row = [&](int r, FRow<SPG> &b) {
+    auto load_row = [&](int r, FRow<SPG, C> &b) {
         const unsigned rb = rowb(g, r);
-        const RowOff o = row_off(g, w, r);
-        const unsigned zb = zrow(g, r).base;
-        b.K = bld(rM, o.o0, rb);
-        b.bx = bld(rM, o.o0, rb + FB);
-        b.bz1 = bld(rM, o.o1, rb + rowN + 2u * FB);
+        const RowOff o = row_off<C>(g, w, r);
+        const ZRow z = zrow(g, r);
+        unsigned oz[C];
+        zoffs<C>(w, z, r < w.i1, oz);
+        vld<C>(rM, o.o0, rb, b.K);
+        vld<C>(rM, o.o0, rb + FB, b.bx);
+        vld<C>(rM, o.o1, rb + rowN + 2u * FB, b.bz1);
 #pragma unroll
         for (int k = 0; k < SPG; ++k) {
             const unsigned kp = skoff(a.pin, k), kv = skoff(a.vin, k);
-            b.p3[k] = bld(rPin, o.o3, rb + 3u * rowN + kp);
-            b.vz1[k] = bld(rVin, o.o1, rb + rowN + FB + kv);
-            b.vx[k] = bld(rVin, o.o0, rb + kv);
-            b.pz[k] = bld(rPin, o.oz, zb + FB + kp);
+            vld<C>(rPin, o.o3, rb + 3u * rowN + kp, b.p3[k]);
+            vld<C>(rVin, o.o1, rb + rowN + FB + kv, b.vz1[k]);
+            vld<C>(rVin, o.o0, rb + kv, b.vx[k]);
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                b.pz[k][c] = bld(rPin, oz[c], z.base + FB + kp);
         }
     };
 
-    auto row = [&](int i, const FRow<SPG> &b) {
-        const float K = b.K, bx = b.bx, bzn = b.bz1;
+    auto row = [&](int i, FRow<SPG, C> &b) {
         const unsigned rb = rowb(g, i);
         const bool rn = row_ok(g, i + 1);
         const float ahz1 = rn ? zahz[i + 1] : 0.f, bhz1 = rn ? zbhz[i + 1] : 0.f;
         const float az = zaz[i], btz = zbz[i];
         const ZRow z = zrow(g, i);
-        const unsigned zcol = z.full ? vcolw_ : vsidew_;
-        const unsigned vzw = i + 1 < w.i1 ? vcolw_ : kOOB;   // this wave owns vz row i+1
+        unsigned zw[C];
+        zoffs_w<C>(w, z, zw);
+        const bool more = i + 1 < w.i1;   // this wave owns vz row i+1
 #pragma unroll
         for (int k = 0; k < SPG; ++k) {
-            P[k][3] = b.p3[k];
-            const float p0 = P[k][0];
-            // vz at row (i+1) + 1/2
-            const float vzn =
-                ahz1 * b.vz1[k] - bhz1 * bzn * (kC1 * (P[k][2] - P[k][1]) + kC2 * (P[k][3] - p0)) * g.rdz;
+            mask_cols<C>(w, b.p3[k]);
+            float vzn[C], vxn[C], dp[C], pn[C], pzn[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                P[k][3][c] = b.p3[k][c];
+                // vz at row (i+1) + 1/2
+                vzn[c] = ahz1 * b.vz1[k][c] -
+                         bhz1 * b.bz1[c] *
+                             (kC1 * (P[k][2][c] - P[k][1][c]) + kC2 * (P[k][3][c] - P[k][0][c])) * g.rdz;
+            }
             // vx at (i, j + 1/2)
-            const float dpx = kC1 * (from_right(p0) - p0) + kC2 * (from_right2(p0) - from_left(p0));
-            const float vxn = ahx * b.vx[k] - bhx * bx * dpx * g.rdx;
+            dfwd<C>(P[k][0], dp);
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                vxn[c] = xt.ahx[c] * b.vx[k][c] - xt.bhx[c] * b.bx[c] * dp[c] * g.rdx;
             // pressure at n+1 (the split is zero where the layer has none,
             // and alpha = 1, beta = dt there)
-            const float dvx = kC1 * (vxn - from_left(vxn)) + kC2 * (from_right(vxn) - from_left2(vxn));
-            const float dvz = kC1 * (VZ[k][2] - VZ[k][1]) + kC2 * (vzn - VZ[k][0]);
-            const float pz = b.pz[k];
-            float px = ax * (p0 - pz) - btx * K * dvx * g.rdx;
-            const float pzn = az * pz - btz * K * dvz * g.rdz;
-            if ((unsigned)(i - srow[k]) < 2u)
-                px += K * (i == srow[k] ? swa[k] : swb[k]);
-            // receivers whose bilinear cell starts on row i, from pin
-            if (i == nxt[k]) {
-                const int s = w.s0 + k;
-                const float q0 = from_right(p0), q1 = from_right(P[k][1]);
-                int c = cur[k];
-                int4 e = T->samp[c];
-                for (;;) {
-                    if (w.lane == e.y) {
-                        const long long rq = (long long)s * T->nrec + e.z;
-                        const float4 rw = T->rec_w[rq];
-                        a.traces[rq * T->nt + a.sample_n] =
-                            rw.x * p0 + rw.y * q0 + rw.z * P[k][1] + rw.w * q1;
-                    }
-                    if (++c >= end[k]) {
-                        e.x = -1;
-                        break;
-                    }
-                    e = T->samp[c];
-                    if (uni(e.x) != i)
-                        break;
-                }
-                cur[k] = c;
-                nxt[k] = uni(e.x);
+            float dvx[C];
+            dbwd<C>(vxn, dvx);
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const float dvz = kC1 * (VZ[k][2][c] - VZ[k][1][c]) + kC2 * (vzn[c] - VZ[k][0][c]);
+                const float pz = b.pz[k][c];
+                const float px = xt.ax[c] * (P[k][0][c] - pz) - xt.btx[c] * b.K[c] * dvx[c] * g.rdx;
+                pzn[c] = az * pz - btz * b.K[c] * dvz * g.rdz;
+                pn[c] = px + pzn[c];
+            }
+            if ((unsigned)(i - srow[k]) < 2u) {
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+                    pn[c] += b.K[c] * (i == srow[k] ? swa[k][c] : swb[k][c]);
             }
             const unsigned kv = skoff(a.vout, k), kp = skoff(a.pout, k);
-            bst(rVout, vcolw_, rb + kv, vxn);
-            bst(rVout, vzw, rb + rowN + FB + kv, vzn);
-            bst(rPout, vcolw_, rb + kp, px + pzn);
-            bst(rPout, zcol, z.base + FB + kp, pzn);
-            VZ[k][0] = VZ[k][1];
-            VZ[k][1] = VZ[k][2];
-            VZ[k][2] = vzn;
-            P[k][0] = P[k][1];
-            P[k][1] = P[k][2];
-            P[k][2] = P[k][3];
+            vst_row<C>(rVout, w, true, rb + kv, vxn);
+            vst_row<C>(rVout, w, more, rb + rowN + FB + kv, vzn);
+            vst_row<C>(rPout, w, true, rb + kp, pn);
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                bst(rPout, zw[c], z.base + FB + kp, pzn[c]);
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                VZ[k][0][c] = VZ[k][1][c];
+                VZ[k][1][c] = VZ[k][2][c];
+                VZ[k][2][c] = vzn[c];
+                P[k][0][c] = P[k][1][c];
+                P[k][1][c] = P[k][2][c];
+                P[k][2][c] = P[k][3][c];
+            }
         }
     };
 
-    FRow<SPG> A, B;
+    FRow<SPG, C> A, B;
     load_row(w.i0, A);
     for (int i = w.i0;;) {
         load_row(i + 1, B);
@@ -384,258 +560,344 @@ __global__ void __launch_bounds__(NTHR)
 //   lv_mid = nu_v + D+(beta K mu_p)                       (T2 transposed)
 //   gbx += lvx_mid * (-bhx Dx+ p^n),  gbz likewise
 //   mu_p' = alpha mu_p + D-(beta_h b lv_mid);  lv' = alpha_h lv_mid   (T1^T)
-// and mu_p' receives R^T r^{n-1} for the next (earlier) step.  Outside the
-// layer the split forms reduce to the unsplit ones (alpha = 1, pz = 0).
+// (mu_p' receives R^T r^{n-1} from the injection launch before the next,
+// earlier step).  Outside the layer the split forms reduce to the unsplit
+// ones (alpha = 1, pz = 0).
 
-template <int SPG>
-struct ARow {
-    float K3, bx, bz1, gK, gX, gZ1;   // K at r+3, bx at r, bz at r+1, partials at r (gbz r+1)
-    float mu3[SPG], mz3[SPG], pn3[SPG];           // mu_px, split mu_pz, p^n at r+3
-    float lvz1[SPG], lvx[SPG], pn1[SPG], z0[SPG], z1[SPG];  // lvz at r+1; lvx, p^{n+1}, splits at r
+template <int SPG, int C>
+struct ARow {   // loads needed early in the row (double buffered)
+    float K3[C], bx[C], bz1[C];                 // K at r+3, bx at r, bz at r+1
+    float mu3[SPG][C], mz3[SPG][C], pn3[SPG][C];  // mu_px, split mu_pz, p^n at r+3
+    float lvz1[SPG][C], lvx[SPG][C];            // lvz at r+1, lvx at r
+};
+template <int SPG, int C>
+struct ALate {  // loads needed at the end of the row (single set)
+    float gK[C], gX[C], gZ1[C];                 // partials at r (gbz at r+1)
+    float pn1[SPG][C], z0[SPG][C], z1[SPG][C];  // p^{n+1}, splits of p^n and p^{n+1} at r
 };
 
-template <int SPG>
+template <int SPG, int C>
 __global__ void __launch_bounds__(NTHR)
     k_adj(Geo g, const float *__restrict__ tabs, const float *model, const SweepTables *T, int S,
           Sweep sw, AdjStep a)
 {
-    WaveGeo w;
-    if (!wave_geo(g, sw, w))
+    WaveGeo<C> w;
+    if (!wave_geo<C>(g, sw, w))
         return;
-    const unsigned vcol_ = w.vcol, vside_ = w.vside, vcolw_ = w.vcolw, vsidew_ = w.vsidew;
-    const int jc = imin(imax(w.j, 0), g.Nx - 1);
-    const float ax = w.colok ? tabs[jc] : 0.f, btx = w.colok ? tabs[g.Nx + jc] : 0.f;
-    const float ahx = w.colok ? tabs[2 * g.Nx + jc] : 0.f, bhx = w.colok ? tabs[3 * g.Nx + jc] : 0.f;
+    XTab<C> xt;
+    xtab<C>(g, tabs, w, xt);
     // z tables: alpha, beta at nodes, alpha_h, beta_h at half nodes
     const float *__restrict__ zaz = tabs + 4 * g.Nx, *__restrict__ zbz = zaz + g.Nz;
     const float *__restrict__ zahz = zbz + g.Nz, *__restrict__ zbhz = zahz + g.Nz;
-    const bool colpml = w.j < g.npml || w.j >= g.Nx - g.npml;
     const unsigned FB = 4u * (unsigned)g.N;
     const unsigned rowN = 4u * (unsigned)g.Nx;
     const rsrc_t rM = res(model, 3u * FB);                                  // K, bx, bz
     const rsrc_t rG = res(a.gpart + (long long)w.grp * 3 * g.N, 3u * FB);  // gK, gbx, gbz
     const rsrc_t rLin = grp_res(a.lin, w.s0, SPG), rLout = grp_res(a.lout, w.s0, SPG);
     const rsrc_t rPn = grp_res(a.pn, w.s0, SPG), rPn1 = grp_res(a.pn1, w.s0, SPG);
-    // does (r, this column) carry a split?
-    auto pml_at = [&](int r) { return r < g.npml || r >= g.Nz - g.npml || colpml; };
+    auto rowpml = [&](int r) { return r < g.npml || r >= g.Nz - g.npml; };
     auto btz_at = [&](int r) -> float { return row_ok(g, r) ? zbz[r] : 0.f; };
-    // mu_pz of shot k at row r inside the grid
-    auto muz_at = [&](int k, int r) -> float {
+    // mu_pz of shot k at row r (zero outside the grid)
+    auto muz_at = [&](int k, int r, float (&o)[C]) {
+        const bool ok = row_ok(g, r);
         const unsigned kl = skoff(a.lin, k);
-        const float mx = bld(rLin, vcol_, rowb(g, r) + 2u * FB + kl);
-        const ZRow z = zrow(g, r);
-        const float mz = bld(rLin, z.full ? vcol_ : vside_, z.base + 3u * FB + kl);
-        return pml_at(r) ? mz : mx;
+        float mx[C];
+        vld<C>(rLin, ok ? w.vcol : kOOB, ok ? rowb(g, r) + 2u * FB + kl : 0u, mx);
+        const ZRow z = zrow(g, ok ? r : 0);
+        unsigned oz[C];
+        zoffs<C>(w, z, ok, oz);
+        const bool rp = rowpml(r);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const float mz = bld(rLin, oz[c], z.base + 3u * FB + kl);
+            o[c] = rp || w.colpml[c] ? mz : mx[c];
+        }
     };
 
-    float KW[4];         // K rows i .. i+3
-    float MU[SPG][4];    // mu_px rows i .. i+3
-    float MZ[SPG][4];    // mu_pz rows i .. i+3
-    float PN[SPG][4];    // p^n rows i .. i+3
-    float WZ[SPG][3];    // beta_h bz lvz_mid rows i-2 .. i
-    // injection list position, end and row of the next entry (-1: none)
-    int cur[SPG], end[SPG], nxt[SPG];
+    float KW[4][C];         // K rows i .. i+3
+    float MU[SPG][4][C];    // mu_px rows i .. i+3
+    float MZ[SPG][4][C];    // mu_pz rows i .. i+3
+    float PN[SPG][4][C];    // p^n rows i .. i+3
+    float WZ[SPG][3][C];    // beta_h bz lvz_mid rows i-2 .. i
 
-    float Kr[6], btzr[6], wzr[3];
+    float Kr[6][C], btzr[6], wzr[3][C];
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
         const int r = w.i0 - 3 + q;
-        Kr[q] = row_ok(g, r) ? bld(rM, vcol_, rowb(g, r)) : 0.f;
+        const bool ok = row_ok(g, r);
+        vld<C>(rM, ok ? w.vcol : kOOB, ok ? rowb(g, r) : 0u, Kr[q]);
         btzr[q] = btz_at(r);
     }
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
         const int r = w.i0 - 2 + q;
-        wzr[q] = row_ok(g, r) ? zbhz[r] * bld(rM, vcol_, rowb(g, r) + 2u * FB) : 0.f;
+        const bool ok = row_ok(g, r);
+        float bz[C];
+        vld<C>(rM, ok ? w.vcol : kOOB, ok ? rowb(g, r) + 2u * FB : 0u, bz);
+        const float bhz = ok ? zbhz[r] : 0.f;
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            wzr[q][c] = bhz * bz[c];
     }
-    KW[0] = Kr[3];
-    KW[1] = Kr[4];
-    KW[2] = Kr[5];
-    KW[3] = 0.f;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        KW[0][c] = Kr[3][c];
+        KW[1][c] = Kr[4][c];
+        KW[2][c] = Kr[5][c];
+        KW[3][c] = 0.f;
+    }
     const float bhz0 = zbhz[w.i0], ahz0 = zahz[w.i0];
-    float accZ0 = 0.f;
+    float accZ0[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+        accZ0[c] = 0.f;
 #pragma unroll
     for (int k = 0; k < SPG; ++k) {
-        const int s = w.s0 + k;
-        cur[k] = end[k] = 0;
-        nxt[k] = -1;
-        if (s < S && a.inject_n >= 0) {
-            const int li = list_index(sw, w, s);
-            cur[k] = uni(T->inj_ptr[li]);
-            end[k] = uni(T->inj_ptr[li + 1]);
-            if (cur[k] < end[k])
-                nxt[k] = uni(T->inj[cur[k]].x);
-        }
         const unsigned kl = skoff(a.lin, k), kn = skoff(a.pn, k);
-        float qz[6], pnr[4];
+        float qz[6][C], pnr[4][C];
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
             const int r = w.i0 - 3 + q;
-            qz[q] = row_ok(g, r) ? Kr[q] * btzr[q] * muz_at(k, r) : 0.f;
+            float mz[C];
+            muz_at(k, r, mz);
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                qz[q][c] = Kr[q][c] * btzr[q] * mz[c];
+            if (q >= 3) {
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+                    MZ[k][q - 3][c] = mz[c];
+            }
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int r = w.i0 - 1 + q;
-            pnr[q] = row_ok(g, r) ? bld(rPn, vcol_, rowb(g, r) + kn) : 0.f;
+            const bool ok = row_ok(g, r);
+            vld<C>(rPn, ok ? w.vcol : kOOB, ok ? rowb(g, r) + kn : 0u, pnr[q]);
+            mask_cols<C>(w, pnr[q]);
         }
         // lvz_mid at rows i0-2 .. i0 (zero outside the grid)
-        float l[3];
+        float l[3][C];
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
             const int r = w.i0 - 2 + q;
-            l[q] = row_ok(g, r) ? bld(rLin, vcol_, rowb(g, r) + FB + kl) +
-                                      (kC1 * (qz[q + 2] - qz[q + 1]) + kC2 * (qz[q + 3] - qz[q])) * g.rdz
-                                : 0.f;
-            WZ[k][q] = wzr[q] * l[q];
+            const bool ok = row_ok(g, r);
+            float lz[C];
+            vld<C>(rLin, ok ? w.vcol : kOOB, ok ? rowb(g, r) + FB + kl : 0u, lz);
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                l[q][c] = ok ? lz[c] + (kC1 * (qz[q + 2][c] - qz[q + 1][c]) +
+                                        kC2 * (qz[q + 3][c] - qz[q][c])) * g.rdz
+                             : 0.f;
+                WZ[k][q][c] = wzr[q][c] * l[q][c];
+            }
         }
-        accZ0 += l[2] * (-bhz0 * (kC1 * (pnr[2] - pnr[1]) + kC2 * (pnr[3] - pnr[0])) * g.rdz);
-        bst(rLout, vcolw_, rowb(g, w.i0) + FB + skoff(a.lout, k), ahz0 * l[2]);
+        float lo[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            accZ0[c] += l[2][c] * (-bhz0 * (kC1 * (pnr[2][c] - pnr[1][c]) + kC2 * (pnr[3][c] - pnr[0][c])) * g.rdz);
+            lo[c] = ahz0 * l[2][c];
+        }
+        vst_row<C>(rLout, w, true, rowb(g, w.i0) + FB + skoff(a.lout, k), lo);
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
             const int r = w.i0 + q;
-            MU[k][q] = row_ok(g, r) ? bld(rLin, vcol_, rowb(g, r) + 2u * FB + kl) : 0.f;
-            MZ[k][q] = row_ok(g, r) ? muz_at(k, r) : 0.f;
-            PN[k][q] = pnr[q + 1];
+            const bool ok = row_ok(g, r);
+            vld<C>(rLin, ok ? w.vcol : kOOB, ok ? rowb(g, r) + 2u * FB + kl : 0u, MU[k][q]);
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                PN[k][q][c] = pnr[q + 1][c];
         }
-        MU[k][3] = MZ[k][3] = PN[k][3] = 0.f;
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            MU[k][3][c] = MZ[k][3][c] = PN[k][3][c] = 0.f;
     }
     {
         const unsigned o = rowb(g, w.i0) + 2u * FB;
-        bst(rG, vcolw_, o, bld(rG, vcolw_, o) + accZ0);
+        float gz[C];
+        vld<C>(rG, w.vcolw, o, gz);
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            if (c + 1 < C) {
+                const float t = bld(rG, w.vtail[c], o);
+                gz[c] = w.vtail[c] != kOOB ? t : gz[c];
+            }
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            gz[c] += accZ0[c];
+        vst_row<C>(rG, w, true, o, gz);
     }
 
-    auto load_row = [&](int r, ARow<SPG> &b) {
+    auto load_row = [&](int r, ARow<SPG, C> &b) {
         const unsigned rb = rowb(g, r);
-        const RowOff o = row_off(g, w, r);
+        const RowOff o = row_off<C>(g, w, r);
         const bool live = r < w.i1;
-        const unsigned ow = live ? vcolw_ : kOOB;
-        const unsigned ow1 = r + 1 < w.i1 ? vcolw_ : kOOB;   // this wave owns gbz row r+1
-        // split lane offset of row r+3 (kOOB where it has no split)
+        // split element offsets of row r+3 (kOOB where it has no split)
         const ZRow z3 = zrow(g, r + 3);
-        const unsigned oz3 = live && r + 3 < g.Nz ? (z3.full ? vcol_ : vside_) : kOOB;
-        const unsigned zb = zrow(g, r).base;
-        b.K3 = bld(rM, o.o3, rb + 3u * rowN);
-        b.bx = bld(rM, o.o0, rb + FB);
-        b.bz1 = bld(rM, o.o1, rb + rowN + 2u * FB);
-        b.gK = bld(rG, ow, rb);
-        b.gX = bld(rG, ow, rb + FB);
-        b.gZ1 = bld(rG, ow1, rb + rowN + 2u * FB);
+        unsigned oz3[C];
+        zoffs<C>(w, z3, live && r + 3 < g.Nz, oz3);
+        vld<C>(rM, o.o3, rb + 3u * rowN, b.K3);
+        vld<C>(rM, o.o0, rb + FB, b.bx);
+        vld<C>(rM, o.o1, rb + rowN + 2u * FB, b.bz1);
 #pragma unroll
         for (int k = 0; k < SPG; ++k) {
-            const unsigned kl = skoff(a.lin, k), kn = skoff(a.pn, k), kn1 = skoff(a.pn1, k);
-            b.mu3[k] = bld(rLin, o.o3, rb + 3u * rowN + 2u * FB + kl);
-            b.mz3[k] = bld(rLin, oz3, z3.base + 3u * FB + kl);
-            b.pn3[k] = bld(rPn, o.o3, rb + 3u * rowN + kn);
-            b.lvz1[k] = bld(rLin, o.o1, rb + rowN + FB + kl);
-            b.lvx[k] = bld(rLin, o.o0, rb + kl);
-            b.pn1[k] = bld(rPn1, o.o0, rb + kn1);
-            b.z0[k] = bld(rPn, o.oz, zb + FB + kn);
-            b.z1[k] = bld(rPn1, o.oz, zb + FB + kn1);
+            const unsigned kl = skoff(a.lin, k), kn = skoff(a.pn, k);
+            vld<C>(rLin, o.o3, rb + 3u * rowN + 2u * FB + kl, b.mu3[k]);
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                b.mz3[k][c] = bld(rLin, oz3[c], z3.base + 3u * FB + kl);
+            vld<C>(rPn, o.o3, rb + 3u * rowN + kn, b.pn3[k]);
+            vld<C>(rLin, o.o1, rb + rowN + FB + kl, b.lvz1[k]);
+            vld<C>(rLin, o.o0, rb + kl, b.lvx[k]);
+        }
+    };
+    // end-of-row values of row i (issued before the next row's loads)
+    auto load_late = [&](int i, ALate<SPG, C> &t) {
+        const unsigned rb = rowb(g, i);
+        const bool more = i + 1 < w.i1;
+        const ZRow z = zrow(g, i);
+        unsigned oz[C];
+        zoffs<C>(w, z, true, oz);
+        // partial gradient: this wave's output columns only (the lane
+        // holding the last column reads its elements one by one)
+        vld<C>(rG, w.vcolw, rb, t.gK);
+        vld<C>(rG, w.vcolw, rb + FB, t.gX);
+        vld<C>(rG, more ? w.vcolw : kOOB, rb + rowN + 2u * FB, t.gZ1);
+#pragma unroll
+        for (int c = 0; c + 1 < C; ++c) {
+            const float a0 = bld(rG, w.vtail[c], rb), a1 = bld(rG, w.vtail[c], rb + FB);
+            const float a2 = bld(rG, more ? w.vtail[c] : kOOB, rb + rowN + 2u * FB);
+            const bool tl = w.vtail[c] != kOOB;
+            t.gK[c] = tl ? a0 : t.gK[c];
+            t.gX[c] = tl ? a1 : t.gX[c];
+            t.gZ1[c] = tl ? a2 : t.gZ1[c];
+        }
+#pragma unroll
+        for (int k = 0; k < SPG; ++k) {
+            const unsigned kn = skoff(a.pn, k), kn1 = skoff(a.pn1, k);
+            vld<C>(rPn1, w.vcol, rb + kn1, t.pn1[k]);
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                t.z0[k][c] = bld(rPn, oz[c], z.base + FB + kn);
+                t.z1[k][c] = bld(rPn1, oz[c], z.base + FB + kn1);
+            }
         }
     };
 
-    auto row = [&](int i, const ARow<SPG> &b) {
-        KW[3] = b.K3;
-        const float bx = b.bx, bzn = b.bz1;
+    auto row = [&](int i, ARow<SPG, C> &b, const ALate<SPG, C> &t) {
         const unsigned rb = rowb(g, i);
         const bool rn = row_ok(g, i + 1);
         const bool more = i + 1 < w.i1;   // this wave owns lvz / gbz row i+1
         const float ahz1 = rn ? zahz[i + 1] : 0.f, bhz1 = rn ? zbhz[i + 1] : 0.f;
         const float az = zaz[i];
-        const float bK0 = KW[0] * btz_at(i), bK1 = KW[1] * btz_at(i + 1);
-        const float bK2 = KW[2] * btz_at(i + 2), bK3 = KW[3] * btz_at(i + 3);
-        const float wzn_c = bhz1 * bzn;
-        const bool pml3 = pml_at(i + 3);
+        const float bt0 = btz_at(i), bt1 = btz_at(i + 1), bt2 = btz_at(i + 2), bt3 = btz_at(i + 3);
+        const bool rp3 = rowpml(i + 3);
         const ZRow z = zrow(g, i);
-        const unsigned zcol = z.full ? vcolw_ : vsidew_;
-        const unsigned vzw = more ? vcolw_ : kOOB;
-        float numK = 0.f, accX = 0.f, accZ = 0.f;
+        unsigned zw[C];
+        zoffs_w<C>(w, z, zw);
+        float numK[C], accX[C], accZ[C], bK[4][C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            KW[3][c] = b.K3[c];
+            numK[c] = accX[c] = accZ[c] = 0.f;
+            bK[0][c] = KW[0][c] * bt0;
+            bK[1][c] = KW[1][c] * bt1;
+            bK[2][c] = KW[2][c] * bt2;
+            bK[3][c] = KW[3][c] * bt3;
+        }
 #pragma unroll
         for (int k = 0; k < SPG; ++k) {
-            MU[k][3] = b.mu3[k];
-            MZ[k][3] = pml3 ? b.mz3[k] : b.mu3[k];
-            PN[k][3] = b.pn3[k];
-            // lvz_mid at row (i+1): D+z of beta_z K mu_pz
-            const float q0 = bK0 * MZ[k][0], q1 = bK1 * MZ[k][1];
-            const float q2 = bK2 * MZ[k][2], q3 = bK3 * MZ[k][3];
-            const float lvzm = rn ? b.lvz1[k] + (kC1 * (q2 - q1) + kC2 * (q3 - q0)) * g.rdz : 0.f;
-            accZ += lvzm * (-bhz1 * (kC1 * (PN[k][2] - PN[k][1]) + kC2 * (PN[k][3] - PN[k][0])) * g.rdz);
-            const float wzn = wzn_c * lvzm;
-            // lvx_mid at row i: D+x of beta_x K mu_px
-            const float mux = MU[k][0];
-            const float qx = btx * KW[0] * mux;
-            const float dqx = kC1 * (from_right(qx) - qx) + kC2 * (from_right2(qx) - from_left(qx));
-            const float lvxm = w.colok ? b.lvx[k] + dqx * g.rdx : 0.f;
-            const float p0 = PN[k][0];
-            const float dpx = kC1 * (from_right(p0) - p0) + kC2 * (from_right2(p0) - from_left(p0));
-            accX += lvxm * (-bhx * dpx * g.rdx);
-            const float wx = bhx * bx * lvxm;
-            const float dwx = kC1 * (wx - from_left(wx)) + kC2 * (from_right(wx) - from_left2(wx));
-            const float dwz = kC1 * (WZ[k][2] - WZ[k][1]) + kC2 * (wzn - WZ[k][0]);
-            const float tsum = dwx * g.rdx + dwz * g.rdz;
-            // R^T r^{n-1} at the nodes of row i this wave owns
-            float inj_v = 0.f;
-            if (i == nxt[k]) {
-                const int s = w.s0 + k;
-                int c = cur[k];
-                int4 e = T->inj[c];
-                for (;;) {
-                    if (w.lane == e.y) {
-                        float acc = 0.f;
-                        const int nrec = T->nrec, nt = T->nt;
-                        for (int q = T->inj_cptr[e.z]; q < T->inj_cptr[e.z + 1]; ++q)
-                            acc += T->inj_cw[q] *
-                                   a.resid[((long long)s * nrec + T->inj_crec[q]) * nt + a.inject_n];
-                        inj_v = acc;
-                    }
-                    if (++c >= end[k]) {
-                        e.x = -1;
-                        break;
-                    }
-                    e = T->inj[c];
-                    if (uni(e.x) != i)
-                        break;
-                }
-                cur[k] = c;
-                nxt[k] = uni(e.x);
-            }
-            const float muz = MZ[k][0];
-            const float z0 = b.z0[k], z1 = b.z1[k], p1 = b.pn1[k];
-            numK += mux * ((p1 - z1) - ax * (p0 - z0)) + muz * (z1 - az * z0);
-            const unsigned ko = skoff(a.lout, k);
-            bst(rLout, vcolw_, rb + 2u * FB + ko, ax * mux + tsum + inj_v);
-            bst(rLout, zcol, z.base + 3u * FB + ko, az * muz + tsum + inj_v);
-            bst(rLout, vcolw_, rb + ko, ahx * lvxm);
-            bst(rLout, vzw, rb + rowN + FB + ko, ahz1 * lvzm);
-            WZ[k][0] = WZ[k][1];
-            WZ[k][1] = WZ[k][2];
-            WZ[k][2] = wzn;
+            mask_cols<C>(w, b.pn3[k]);
+            float lvzm[C], wzn[C], qx[C], dqx[C], dpx[C], lvxm[C], wx[C], dwx[C], tsum[C];
 #pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                MU[k][q] = MU[k][q + 1];
-                MZ[k][q] = MZ[k][q + 1];
-                PN[k][q] = PN[k][q + 1];
+            for (int c = 0; c < C; ++c) {
+                MU[k][3][c] = b.mu3[k][c];
+                MZ[k][3][c] = rp3 || w.colpml[c] ? b.mz3[k][c] : b.mu3[k][c];
+                PN[k][3][c] = b.pn3[k][c];
+                // lvz_mid at row (i+1): D+z of beta_z K mu_pz
+                const float q0 = bK[0][c] * MZ[k][0][c], q1 = bK[1][c] * MZ[k][1][c];
+                const float q2 = bK[2][c] * MZ[k][2][c], q3 = bK[3][c] * MZ[k][3][c];
+                lvzm[c] = rn ? b.lvz1[k][c] + (kC1 * (q2 - q1) + kC2 * (q3 - q0)) * g.rdz : 0.f;
+                accZ[c] += lvzm[c] * (-bhz1 * (kC1 * (PN[k][2][c] - PN[k][1][c]) +
+                                               kC2 * (PN[k][3][c] - PN[k][0][c])) * g.rdz);
+                wzn[c] = bhz1 * b.bz1[c] * lvzm[c];
+                // lvx_mid at row i: D+x of beta_x K mu_px
+                qx[c] = xt.btx[c] * KW[0][c] * MU[k][0][c];
+            }
+            dfwd<C>(qx, dqx);
+            dfwd<C>(PN[k][0], dpx);
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                lvxm[c] = w.colok[c] ? b.lvx[k][c] + dqx[c] * g.rdx : 0.f;
+                accX[c] += lvxm[c] * (-xt.bhx[c] * dpx[c] * g.rdx);
+                wx[c] = xt.bhx[c] * b.bx[c] * lvxm[c];
+            }
+            dbwd<C>(wx, dwx);
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const float dwz = kC1 * (WZ[k][2][c] - WZ[k][1][c]) + kC2 * (wzn[c] - WZ[k][0][c]);
+                tsum[c] = dwx[c] * g.rdx + dwz * g.rdz;
+            }
+            float opx[C], opz[C], ovx[C], ovz[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const float mux = MU[k][0][c], muz = MZ[k][0][c], p0 = PN[k][0][c];
+                const float z0 = t.z0[k][c], z1 = t.z1[k][c], p1 = t.pn1[k][c];
+                numK[c] += mux * ((p1 - z1) - xt.ax[c] * (p0 - z0)) + muz * (z1 - az * z0);
+                opx[c] = xt.ax[c] * mux + tsum[c];
+                opz[c] = az * muz + tsum[c];
+                ovx[c] = xt.ahx[c] * lvxm[c];
+                ovz[c] = ahz1 * lvzm[c];
+            }
+            const unsigned ko = skoff(a.lout, k);
+            vst_row<C>(rLout, w, true, rb + 2u * FB + ko, opx);
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                bst(rLout, zw[c], z.base + 3u * FB + ko, opz[c]);
+            vst_row<C>(rLout, w, true, rb + ko, ovx);
+            vst_row<C>(rLout, w, more, rb + rowN + FB + ko, ovz);
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                WZ[k][0][c] = WZ[k][1][c];
+                WZ[k][1][c] = WZ[k][2][c];
+                WZ[k][2][c] = wzn[c];
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    MU[k][q][c] = MU[k][q + 1][c];
+                    MZ[k][q][c] = MZ[k][q + 1][c];
+                    PN[k][q][c] = PN[k][q + 1][c];
+                }
             }
         }
         // one reciprocal per row for the bulk-modulus sensitivity (1 ulp)
-        const float rK = KW[0] != 0.f ? __builtin_amdgcn_rcpf(KW[0]) : 0.f;
-        bst(rG, vcolw_, rb, b.gK + numK * rK);
-        bst(rG, vcolw_, rb + FB, b.gX + accX);
-        bst(rG, vzw, rb + rowN + 2u * FB, b.gZ1 + accZ);
-        KW[0] = KW[1];
-        KW[1] = KW[2];
-        KW[2] = KW[3];
+        float gk[C], gx[C], gz[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const float rK = KW[0][c] != 0.f ? __builtin_amdgcn_rcpf(KW[0][c]) : 0.f;
+            gk[c] = t.gK[c] + numK[c] * rK;
+            gx[c] = t.gX[c] + accX[c];
+            gz[c] = t.gZ1[c] + accZ[c];
+            KW[0][c] = KW[1][c];
+            KW[1][c] = KW[2][c];
+            KW[2][c] = KW[3][c];
+        }
+        vst_row<C>(rG, w, true, rb, gk);
+        vst_row<C>(rG, w, true, rb + FB, gx);
+        vst_row<C>(rG, w, more, rb + rowN + 2u * FB, gz);
     };
 
-    ARow<SPG> A, B;
+    ARow<SPG, C> A, B;
+    ALate<SPG, C> L;
     load_row(w.i0, A);
     for (int i = w.i0;;) {
+        load_late(i, L);
         load_row(i + 1, B);
-        row(i, A);
+        row(i, A, L);
         if (++i >= w.i1)
             break;
+        load_late(i, L);
         load_row(i + 1, A);
-        row(i, B);
+        row(i, B, L);
         if (++i >= w.i1)
             break;
     }
@@ -646,46 +908,94 @@ inline unsigned blocks_of(const Sweep &sw)
     return (unsigned)((sw.nwaves + NTHR / WAVE - 1) / (NTHR / WAVE));
 }
 
+// The start / stop events (may be null) take the dispatch's own start and
+// end times.
+template <int SPG, int C>
+void launch_f(const Geo &g, const float *tabs, const float *model, const SweepTables *T, int S,
+              const Sweep &sw, const FwdStep &a, hipStream_t st, hipEvent_t e0, hipEvent_t e1)
+{
+    hipExtLaunchKernelGGL((k_fwd<SPG, C>), dim3(blocks_of(sw)), dim3(NTHR), 0, st, e0, e1, 0, g,
+                          tabs, model, T, S, sw, a);
+}
+template <int SPG, int C>
+void launch_a(const Geo &g, const float *tabs, const float *model, const SweepTables *T, int S,
+              const Sweep &sw, const AdjStep &a, hipStream_t st, hipEvent_t e0, hipEvent_t e1)
+{
+    hipExtLaunchKernelGGL((k_adj<SPG, C>), dim3(blocks_of(sw)), dim3(NTHR), 0, st, e0, e1, 0, g,
+                          tabs, model, T, S, sw, a);
+}
+
 }  // namespace
 
-bool fused_spg_supported(int spg) { return spg == 1 || spg == 2 || spg == 4 || spg == 8; }
+// Instantiated (shots per group, columns per lane) pairs.
+bool fused_supported(int spg, int cols)
+{
+    switch (cols) {
+    case 1: return spg == 1 || spg == 2 || spg == 4 || spg == 8;
+    case 2: return spg == 1 || spg == 2 || spg == 4;
+    case 4: return spg == 1 || spg == 2;
+    }
+    return false;
+}
 
-Sweep sweep_of(const Geo &g, int S, int band_rows, int spg)
+int strip_cols(int cols)
+{
+    switch (cols) {
+    case 2: return Lanes<2>::W;
+    case 4: return Lanes<4>::W;
+    default: return Lanes<1>::W;
+    }
+}
+
+int halo_cols(int cols)
+{
+    switch (cols) {
+    case 2: return Lanes<2>::HL * 2;
+    case 4: return Lanes<4>::HL * 4;
+    default: return Lanes<1>::HL;
+    }
+}
+
+Sweep sweep_of(const Geo &g, int S, int band_rows, int spg, int cols)
 {
     Sweep sw;
     sw.H = band_rows;
     sw.spg = spg;
-    sw.nstrips = (g.Nx + kStripOut - 1) / kStripOut;
+    sw.cols = cols;
+    const int W = strip_cols(cols);
+    sw.nstrips = (g.Nx + W - 1) / W;
     sw.nbands = (g.Nz + band_rows - 1) / band_rows;
     sw.ngroups = (S + spg - 1) / spg;
     sw.nwaves = sw.nstrips * sw.nbands * sw.ngroups;
     return sw;
 }
 
+#define FWI_DISPATCH(fn, ...)                                                   \
+    switch (sw.cols * 16 + sw.spg) {                                            \
+    case 16 + 1: fn<1, 1>(__VA_ARGS__); break;                                  \
+    case 16 + 2: fn<2, 1>(__VA_ARGS__); break;                                  \
+    case 16 + 4: fn<4, 1>(__VA_ARGS__); break;                                  \
+    case 16 + 8: fn<8, 1>(__VA_ARGS__); break;                                  \
+    case 32 + 1: fn<1, 2>(__VA_ARGS__); break;                                  \
+    case 32 + 2: fn<2, 2>(__VA_ARGS__); break;                                  \
+    case 32 + 4: fn<4, 2>(__VA_ARGS__); break;                                  \
+    case 64 + 1: fn<1, 4>(__VA_ARGS__); break;                                  \
+    case 64 + 2: fn<2, 4>(__VA_ARGS__); break;                                  \
+    default: break;                                                             \
+    }
+
 void launch_fused_fwd(const Geo &g, const float *tabs, const float *model,
                       const SweepTables *T, int S, const Sweep &sw, const FwdStep &a,
-                      hipStream_t st)
+                      hipStream_t st, hipEvent_t e0, hipEvent_t e1)
 {
-    dim3 grid(blocks_of(sw)), blk(NTHR);
-    switch (sw.spg) {
-    case 1: hipLaunchKernelGGL(k_fwd<1>, grid, blk, 0, st, g, tabs, model, T, S, sw, a); break;
-    case 2: hipLaunchKernelGGL(k_fwd<2>, grid, blk, 0, st, g, tabs, model, T, S, sw, a); break;
-    case 8: hipLaunchKernelGGL(k_fwd<8>, grid, blk, 0, st, g, tabs, model, T, S, sw, a); break;
-    default: hipLaunchKernelGGL(k_fwd<4>, grid, blk, 0, st, g, tabs, model, T, S, sw, a); break;
-    }
+    FWI_DISPATCH(launch_f, g, tabs, model, T, S, sw, a, st, e0, e1)
 }
 
 void launch_fused_adj(const Geo &g, const float *tabs, const float *model,
                       const SweepTables *T, int S, const Sweep &sw, const AdjStep &a,
-                      hipStream_t st)
+                      hipStream_t st, hipEvent_t e0, hipEvent_t e1)
 {
-    dim3 grid(blocks_of(sw)), blk(NTHR);
-    switch (sw.spg) {
-    case 1: hipLaunchKernelGGL(k_adj<1>, grid, blk, 0, st, g, tabs, model, T, S, sw, a); break;
-    case 2: hipLaunchKernelGGL(k_adj<2>, grid, blk, 0, st, g, tabs, model, T, S, sw, a); break;
-    case 8: hipLaunchKernelGGL(k_adj<8>, grid, blk, 0, st, g, tabs, model, T, S, sw, a); break;
-    default: hipLaunchKernelGGL(k_adj<4>, grid, blk, 0, st, g, tabs, model, T, S, sw, a); break;
-    }
+    FWI_DISPATCH(launch_a, g, tabs, model, T, S, sw, a, st, e0, e1)
 }
 
 }  // namespace fwi

@@ -16,11 +16,11 @@ def test_tune_and_cache(tmp_path, monkeypatch):
     monkeypatch.setenv("FWI2D_TUNE_CACHE", str(tmp_path / "tune.json"))
     w = W.gauss_problem(181, 6, 40, 200, npml=16, seed=4)
     g = api.Grid.of(w)
-    H, spg = autotune.tune(g, w.src_xz, w.rec_xz)
+    best = autotune.tune(g, w.src_xz, w.rec_xz)
     Nz, Nx = g.padded
-    assert (H, spg) in autotune.candidates(Nz, Nx, w.nshots)
+    assert best in autotune.candidates(Nz, Nx, w.nshots)
     assert (tmp_path / "tune.json").exists()
-    assert autotune.tune(g, w.src_xz, w.rec_xz) == (H, spg)
+    assert autotune.tune(g, w.src_xz, w.rec_xz) == best
     f = w.wavelet()
     plan_d = api.Plan(g, w.src_xz, w.rec_xz)
     plan_t = autotune.tuned_plan(g, w.src_xz, w.rec_xz)

@@ -99,13 +99,20 @@ def test_forward_config1(api, c1, mode):
     assert gather_err(tr, c1.d) <= TOL
 
 
-@pytest.mark.parametrize("mode,rows,spg", [("plain", 0, 0), ("batched", 8, 1),
-                                          ("batched", 16, 2), ("batched", 37, 4),
-                                          ("batched", 173, 8), ("batched", 4, 4)])
-def test_forward_multi_tile_ragged(api, small, mode, rows, spg):
+# (band rows, shots per group, columns per lane): several bands and strips,
+# a ragged last band, a partial last shot group, the lane holding the last
+# grid column split across the grid edge (173 padded columns)
+FWD_CASES = [("plain", 0, 0, 0), ("batched", 8, 1, 1), ("batched", 16, 2, 1),
+             ("batched", 37, 4, 1), ("batched", 173, 8, 1), ("batched", 4, 4, 1),
+             ("batched", 8, 1, 2), ("batched", 13, 2, 2), ("batched", 37, 4, 2),
+             ("batched", 8, 1, 4), ("batched", 29, 2, 4)]
+
+
+@pytest.mark.parametrize("mode,rows,spg,cols", FWD_CASES)
+def test_forward_multi_tile_ragged(api, small, mode, rows, spg, cols):
     w = small.w
     p = api.Plan(agrid(api, w), w.src_xz, w.rec_xz, mode=mode, band_rows=rows,
-                 shots_per_group=spg)
+                 shots_per_group=spg, lane_cols=cols)
     tr = p.forward("k-rho", small.K0, small.r0, small.f).cpu().numpy()
     assert gather_err(tr, small.d) <= TOL
 
@@ -144,16 +151,17 @@ def test_adjoint_config1(api, c1, mode, param):
     assert maxrel(g2.cpu().numpy(), e2) <= TOL
 
 
-@pytest.mark.parametrize("mode,rows,spg,ckpt", [("plain", 0, 0, 0), ("plain", 0, 0, 23),
-                                               ("batched", 8, 1, 0),
-                                               ("batched", 16, 2, 17),
-                                               ("batched", 37, 4, 300),
-                                               ("batched", 173, 8, 1),
-                                               ("batched", 4, 4, 9)])
-def test_adjoint_multi_tile_ragged(api, small, mode, rows, spg, ckpt):
+ADJ_CASES = [("plain", 0, 0, 0, 0), ("plain", 0, 0, 0, 23), ("batched", 8, 1, 1, 0),
+             ("batched", 16, 2, 1, 17), ("batched", 37, 4, 1, 300), ("batched", 173, 8, 1, 1),
+             ("batched", 4, 4, 1, 9), ("batched", 8, 1, 2, 0), ("batched", 13, 2, 2, 17),
+             ("batched", 37, 4, 2, 9), ("batched", 8, 1, 4, 0), ("batched", 29, 2, 4, 23)]
+
+
+@pytest.mark.parametrize("mode,rows,spg,cols,ckpt", ADJ_CASES)
+def test_adjoint_multi_tile_ragged(api, small, mode, rows, spg, cols, ckpt):
     w = small.w
     p = api.Plan(agrid(api, w), w.src_xz, w.rec_xz, mode=mode, band_rows=rows,
-                 shots_per_group=spg, ckpt_every=ckpt)
+                 shots_per_group=spg, lane_cols=cols, ckpt_every=ckpt)
     gK, gr = p.adjoint("k-rho", small.K0, small.r0, small.f, small.adj)
     assert maxrel(gK.cpu().numpy(), small.gK) <= TOL
     assert maxrel(gr.cpu().numpy(), small.gr) <= TOL
@@ -232,10 +240,10 @@ def test_conversions_chain_rule_contrast(api):
 
 
 def test_single_shot_single_receiver_and_tiny_grid(api):
-    """Degenerate sizes: one shot, one receiver, a grid smaller than a tile,
-    no absorbing layer, one time step and a few."""
-    for npml, nt in ((0, 1), (0, 9), (3, 40)):
-        n = 9
+    """Degenerate sizes: one shot, one receiver, a grid smaller than a strip,
+    no absorbing layer, one time step and a few, odd and even widths, every
+    lane width."""
+    for n, npml, nt in ((9, 0, 1), (9, 0, 9), (9, 3, 40), (10, 3, 40), (10, 0, 7)):
         g = O.Grid(n, n, 5.0, 5.0, npml, nt, 1e-3, 2000.0)
         src = np.array([[17.0, 21.0]])
         rec = np.array([[[23.0, 12.5]]])
@@ -246,8 +254,9 @@ def test_single_shot_single_receiver_and_tiny_grid(api):
         ref = O.forward_krho(g, src, rec, K, r, f)
         adj = rng.standard_normal(ref.shape)
         eK, er = O.adjoint_krho(g, src, rec, K, r, f, adj)
-        for mode in ("plain", "batched"):
-            p = api.Plan(api.Grid(n, n, 5.0, 5.0, npml, nt, 1e-3, 2000.0), src, rec, mode=mode)
+        for mode, cols in (("plain", 0), ("batched", 1), ("batched", 2), ("batched", 4)):
+            p = api.Plan(api.Grid(n, n, 5.0, 5.0, npml, nt, 1e-3, 2000.0), src, rec, mode=mode,
+                         lane_cols=cols)
             tr = p.forward(0, K, r, f).cpu().numpy()
             assert maxrel(tr, ref) <= TOL
             gK, gr = p.adjoint(0, K, r, f, adj.astype(np.float32))

@@ -5,15 +5,17 @@ import numpy as np
 from paper_1804_01184_amd import workloads as W
 
 
-def test_candidates_cover_rows_and_shot_groups():
+def test_candidates_cover_rows_shot_groups_and_lane_widths():
     from paper_1804_01184_amd import autotune
+    assert [autotune.strip_cols(c) for c in (1, 2, 4)] == [58, 120, 248]
     c = autotune.candidates(481, 481, 40)
-    assert {spg for _, spg in c} == {1, 2, 4, 8}
-    for H, spg in c:
-        waves = 9 * ((481 + H - 1) // H) * ((40 + spg - 1) // spg)
-        assert 512 <= waves <= 32768
+    assert {(spg, cols) for _, spg, cols in c} == set(autotune.PAIRS)
+    for H, spg, cols in c:
+        strips = -(-481 // autotune.strip_cols(cols))
+        waves = strips * ((481 + H - 1) // H) * ((40 + spg - 1) // spg)
+        assert 512 <= waves <= 65536
     small = autotune.candidates(21, 21, 1)
-    assert small and all(spg in (1, 2) for _, spg in small)
+    assert small and all(spg in (1, 2) for _, spg, _ in small)
 
 
 def test_workloads_seeded_and_shaped():
