@@ -105,8 +105,11 @@ typedef struct {
 
 typedef struct {
     int32_t mode;         /* fwi_exec_mode                                    */
-    int32_t ckpt_every;   /* forward states kept every k steps; 0: ceil(sqrt(nt));
-                             >= nt keeps the whole pressure history            */
+    int32_t ckpt_every;   /* forward states kept every k steps; 0: the whole
+                             pressure history when it fits (plain: one
+                             shot's history <= 64 GiB; batched: all shots'
+                             history <= half the device memory), else
+                             ceil(sqrt(nt)); >= nt keeps the whole history   */
     int32_t band_rows;    /* batched kernels: rows each wave sweeps (4..4096);
                              0: chosen from the grid and shot count          */
     int32_t shots_per_group; /* batched kernels: shots a wave advances together;
@@ -116,6 +119,12 @@ typedef struct {
                              (shots_per_group, lane_cols) pairs: lane_cols 1
                              with 1, 2, 4, 8; lane_cols 2 with 1, 2, 4;
                              lane_cols 4 with 1, 2 (else FWI_EINVAL)         */
+    int32_t two_step;     /* batched forward sweeps advance two time steps per
+                             launch (the intermediate velocities stay on
+                             chip): 0 default (on), 1 off, 2 on              */
+    int32_t two_step_band_rows;       /* decomposition of the two-step     */
+    int32_t two_step_shots_per_group; /* kernel, 0: defaults; supported    */
+    int32_t two_step_lane_cols;       /* (shots, cols): (1|2, 1|2), (1, 4) */
 } fwi_exec;
 
 typedef struct {
@@ -124,6 +133,8 @@ typedef struct {
     int32_t segments;         /* ceil(nt / k)                                 */
     int32_t band_rows, shots_per_group, lane_cols;
     int32_t shot_groups;      /* ceil(nshots / shots_per_group)               */
+    int32_t two_step;         /* 1: forward sweeps use the two-step kernel    */
+    int32_t two_step_band_rows, two_step_shots_per_group, two_step_lane_cols;
     int32_t mode;
     int32_t device;           /* HIP device the plan lives on                 */
     int64_t pml_cells;        /* cells of the absorbing layer                 */
@@ -221,7 +232,8 @@ typedef enum {
     FWI_KC_SAMPLE = 6,     /* receiver sampling                                */
     FWI_KC_INJECT = 7,     /* adjoint-source injection                         */
     FWI_KC_OTHER = 8,      /* preparation, copies, misfit, finalization        */
-    FWI_KC_COUNT = 9
+    FWI_KC_FWD_PAIR = 9,   /* batched two-step forward (all shots, 2 steps)    */
+    FWI_KC_COUNT = 10
 } fwi_kernel_class;
 
 typedef struct {

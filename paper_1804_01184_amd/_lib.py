@@ -28,7 +28,7 @@ SYMBOLS = ["fwi_plan_create", "fwi_plan_destroy", "fwi_plan_get_info", "fwi_work
            "fwi_sync", "fwi_status_str", "fwi_last_error"]
 
 KERNEL_CLASSES = ["fwd_step", "adj_step", "plain_vel", "plain_pres", "plain_adj_a",
-                  "plain_adj_b", "sample", "inject", "other"]
+                  "plain_adj_b", "sample", "inject", "other", "fwd_pair"]
 
 
 class FwiGrid(ctypes.Structure):
@@ -47,21 +47,27 @@ class FwiAcq(ctypes.Structure):
 class FwiExec(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("ckpt_every", ctypes.c_int32),
                 ("band_rows", ctypes.c_int32), ("shots_per_group", ctypes.c_int32),
-                ("lane_cols", ctypes.c_int32)]
+                ("lane_cols", ctypes.c_int32), ("two_step", ctypes.c_int32),
+                ("two_step_band_rows", ctypes.c_int32),
+                ("two_step_shots_per_group", ctypes.c_int32),
+                ("two_step_lane_cols", ctypes.c_int32)]
 
 
 class FwiPlanInfo(ctypes.Structure):
     _fields_ = [("Nz", ctypes.c_int32), ("Nx", ctypes.c_int32), ("ckpt_every", ctypes.c_int32),
                 ("segments", ctypes.c_int32), ("band_rows", ctypes.c_int32),
                 ("shots_per_group", ctypes.c_int32), ("lane_cols", ctypes.c_int32),
-                ("shot_groups", ctypes.c_int32),
+                ("shot_groups", ctypes.c_int32), ("two_step", ctypes.c_int32),
+                ("two_step_band_rows", ctypes.c_int32),
+                ("two_step_shots_per_group", ctypes.c_int32),
+                ("two_step_lane_cols", ctypes.c_int32),
                 ("mode", ctypes.c_int32),
                 ("device", ctypes.c_int32), ("pml_cells", ctypes.c_int64),
                 ("cfl", ctypes.c_double)]
 
 
 class FwiTiming(ctypes.Structure):
-    _fields_ = [("launches", ctypes.c_int64 * 9), ("ms", ctypes.c_double * 9)]
+    _fields_ = [("launches", ctypes.c_int64 * 10), ("ms", ctypes.c_double * 10)]
 
 
 class FwiError(RuntimeError):

@@ -2,7 +2,8 @@
 
 ``python -m paper_1804_01184_amd.build`` from the repository root.  Every
 translation unit is compiled for gfx950 only; packed FP32 instructions are
-disabled (-packed-fp32-ops).  Objects go to ``_build/`` beside the package.
+disabled (-packed-fp32-ops); multiply-adds are contracted within expressions
+only (-ffp-contract=on).  Objects go to ``_build/`` beside the package.
 """
 import os
 import subprocess
@@ -16,7 +17,10 @@ LIB = os.path.join(PKG, "libfwi2d.so")
 SOURCES = ["fwi2d_api.hip", "k_common.hip", "k_plain.hip", "k_fused.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
+# -ffp-contract=on: multiply-adds are fused only within one source
+# expression, so the one-step and two-step forward kernels, which share the
+# update expressions, round every step the same way.
+FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-ffp-contract=on",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include")]
 

@@ -51,6 +51,8 @@ struct fwi_plan {
     int Spad;   // shots of a batched launch: S padded to whole shot groups
     int mode, k, nseg;
     Sweep sweep;   // batched decomposition (band rows, shots per group)
+    bool two_step = false;   // forward sweeps use the two-step kernel
+    Sweep sweep2;            // its decomposition
     int device;
     Geo geo;
     long long SS, ST;  // per-shot floats of a state record / a store record
@@ -150,6 +152,7 @@ struct Layout {
     size_t Kphys, rhophys, Kpad, bx, bz, Q;
     size_t work[2], lam[2];
     size_t ckpt, store, gpart, fold, traces, resid, partials;
+    size_t mid;   // p^{n+1} of a two-step launch outside the stored history
     size_t total;
 };
 
@@ -185,6 +188,8 @@ Layout layout(const fwi_plan *p, int op)
     L.Q = take((size_t)p->S * p->grid.nt);
     L.work[0] = take((size_t)B * p->SS);
     L.work[1] = take((size_t)B * p->SS);
+    if (p->two_step)
+        L.mid = take((size_t)B * p->ST);
     if (op == FWI_OP_GRADIENT) {
         L.lam[0] = take((size_t)B * p->SS);
         L.lam[1] = take((size_t)B * p->SS);
@@ -343,6 +348,26 @@ void step_fwd(const Ctx &c, int s0, int nb, const State &in, const State &out, i
     }
 }
 
+// Two forward steps n -> n+2 for shots [s0, s0+nb) (batched only): `mid`
+// (a pressure record: p, then its split N floats later) receives p^{n+1},
+// `out` the state at n+2; out's velocities must not be in's.
+void step_fwd2(const Ctx &c, int s0, int nb, const State &in, Fld mid, const State &out, int n)
+{
+    const fwi_plan *p = c.pl;
+    const Geo &g = p->geo;
+    (void)nb;
+    FwdStep2 a;
+    a.vin = recd(in.vx, 2 * g.N);
+    a.pin = recd(in.p, g.N + g.Npml);
+    a.vout = recd(out.vx, 2 * g.N);
+    a.pout = recd(out.p, g.N + g.Npml);
+    a.pmid = recd(mid, g.N + g.Npml);
+    a.Q = src_of(c, s0).Q;
+    a.n = n;
+    Timed tm(c.pl, c.st, FWI_KC_FWD_PAIR, true);
+    launch_fused_fwd2(g, p->pml, c.m.K, p->sweep_tabs, p->S, p->sweep2, a, c.st, tm.b, tm.e);
+}
+
 // One adjoint step n for shots [s0, s0+nb): injects R^T r^n into `in`, then
 // writes the adjoint state of step n into `out` and accumulates the
 // sensitivities into gpart.
@@ -395,6 +420,7 @@ void zero_state(const Ctx &c, float *base, int nb)
 void sweep_forward(const Ctx &c, int s0, int nb, bool keep, float *traces)
 {
     const fwi_plan *p = c.pl;
+    const Geo &g = p->geo;
     const int nt = p->grid.nt, k = p->k;
     const int nlast = (p->nseg - 1) * k;
     State w[2] = {state_at(c.f(c.L.work[0]), p), state_at(c.f(c.L.work[1]), p)};
@@ -402,31 +428,70 @@ void sweep_forward(const Ctx &c, int s0, int nb, bool keep, float *traces)
     State cur = w[0];
     int cw = 0;  // work buffer holding cur's velocities (-1: a checkpoint slot)
     Rec rec = rec_of(c, s0);
-    for (int n = 0; n < nt; ++n) {
-        int n1 = n + 1;
-        int nw = cw == 0 ? 1 : 0;
+    float *slot0 = c.f(c.L.store);
+    auto slot_p = [&](int level) {   // store slot of a level >= nlast
+        float *b = slot0 + (size_t)(level - nlast) * nb * p->ST;
+        return std::make_pair(Fld{b, p->ST}, Fld{b + g.N, p->ST});
+    };
+    // levels kept as full states (checkpoints, and the level the stored
+    // history starts from)
+    auto full_state = [&](int level) { return keep && level % k == 0 && level <= nlast; };
+    // target of level n+1 for a step from a state whose velocities are in
+    // work buffer cw
+    auto target = [&](int n, int cw_in, int &cw_out) {
+        const int nw = cw_in == 0 ? 1 : 0;
         State out = w[nw];
-        int next_cw = nw;
+        cw_out = nw;
         if (keep && n >= nlast) {
-            float *slot0 = c.f(c.L.store);
-            if (n == nlast) {
-                Fld sp0 = {slot0, p->ST}, spz0 = {slot0 + p->geo.N, p->ST};
-                copy_p(c, sp0, spz0, cur.p, cur.pz, nb);
-            }
-            float *slot = slot0 + (size_t)(n1 - nlast) * nb * p->ST;
-            out.p = {slot, p->ST};
-            out.pz = {slot + p->geo.N, p->ST};
-        } else if (keep && n1 % k == 0) {
-            out = state_at(c.f(c.L.ckpt) + (size_t)(n1 / k - 1) * nb * p->SS, p);
-            next_cw = -1;
+            auto sl = slot_p(n + 1);
+            out.p = sl.first;
+            out.pz = sl.second;
+        } else if (full_state(n + 1)) {
+            out = state_at(c.f(c.L.ckpt) + (size_t)((n + 1) / k - 1) * nb * p->SS, p);
+            cw_out = -1;
         }
-        step_fwd(c, s0, nb, cur, out, n);
-        if (traces) {
-            Timed tm(c.pl, c.st, FWI_KC_SAMPLE);
-            launch_sample(p->geo, out.p, out.pz, rec, real_shots(p, s0, nb), traces, nt, n, c.st);
+        return out;
+    };
+    auto sample = [&](const State &st, int n) {
+        if (!traces)
+            return;
+        Timed tm(c.pl, c.st, FWI_KC_SAMPLE);
+        launch_sample(g, st.p, st.pz, rec, real_shots(p, s0, nb), traces, nt, n, c.st);
+    };
+    for (int n = 0; n < nt;) {
+        if (keep && n == nlast) {
+            auto sl = slot_p(nlast);
+            copy_p(c, sl.first, sl.second, cur.p, cur.pz, nb);
         }
-        cur = out;
-        cw = next_cw;
+        if (p->two_step && n + 1 < nt && !full_state(n + 1)) {
+            // two steps: level n+1 only as pressure (history slot or scratch)
+            std::pair<Fld, Fld> mid;
+            if (keep && n + 1 > nlast)
+                mid = slot_p(n + 1);
+            else
+                mid = {Fld{c.f(c.L.mid), p->ST}, Fld{c.f(c.L.mid) + g.N, p->ST}};
+            int cw2;
+            State out = target(n + 1, cw, cw2);
+            if (cw2 == cw)   // velocities of n+2 must not overwrite those of n
+                cw2 = -1;
+            step_fwd2(c, s0, nb, cur, mid.first, out, n);
+            State ms = cur;
+            ms.p = mid.first;
+            ms.pz = mid.second;
+            sample(ms, n);
+            sample(out, n + 1);
+            cur = out;
+            cw = cw2;
+            n += 2;
+        } else {
+            int cw1;
+            State out = target(n, cw, cw1);
+            step_fwd(c, s0, nb, cur, out, n);
+            sample(out, n);
+            cur = out;
+            cw = cw1;
+            n += 1;
+        }
     }
 }
 
@@ -461,13 +526,22 @@ void sweep_backward(const Ctx &c, int s0, int nb, const float *resid, float *gpa
             }
             auto s0p = slot(0);
             copy_p(c, s0p.first, s0p.second, cur.p, cur.pz, nb);
-            for (int n = n0; n < n1; ++n) {
+            for (int n = n0; n < n1;) {
                 int nw = cw == 0 ? 1 : 0;
                 State out = w[nw];
-                auto sl = slot(n + 1 - n0);
-                out.p = sl.first;
-                out.pz = sl.second;
-                step_fwd(c, s0, nb, cur, out, n);
+                if (p->two_step && n + 1 < n1) {
+                    auto sm = slot(n + 1 - n0), sl = slot(n + 2 - n0);
+                    out.p = sl.first;
+                    out.pz = sl.second;
+                    step_fwd2(c, s0, nb, cur, sm.first, out, n);
+                    n += 2;
+                } else {
+                    auto sl = slot(n + 1 - n0);
+                    out.p = sl.first;
+                    out.pz = sl.second;
+                    step_fwd(c, s0, nb, cur, out, n);
+                    n += 1;
+                }
                 cur = out;
                 cw = nw;
             }
@@ -666,7 +740,7 @@ fwi_status fwi_plan_create(const fwi_grid *grid, const fwi_acq *acq, const fwi_e
         return fail(FWI_EUNSTABLE, "vmax dt sqrt(1/dx^2+1/dz^2)(9/8+1/24) = %.4f > 1", sn);
     if (acq->nshots < 1 || acq->nrec < 1 || !acq->src_xz || !acq->rec_xz)
         return fail(FWI_EINVAL, "need at least one shot and one receiver with positions");
-    fwi_exec ex{FWI_EXEC_BATCHED, 0, 0, 0, 0};
+    fwi_exec ex{FWI_EXEC_BATCHED, 0, 0, 0, 0, 0, 0, 0, 0};
     if (exec)
         ex = *exec;
     if (ex.mode != FWI_EXEC_BATCHED && ex.mode != FWI_EXEC_PLAIN)
@@ -683,6 +757,17 @@ fwi_status fwi_plan_create(const fwi_grid *grid, const fwi_acq *acq, const fwi_e
                     ex.shots_per_group, ex.lane_cols);
     if (ex.ckpt_every < 0)
         return fail(FWI_EINVAL, "ckpt_every out of range");
+    if (ex.two_step < 0 || ex.two_step > 2)
+        return fail(FWI_EINVAL, "two_step %d out of range (0, 1, 2)", ex.two_step);
+    if (ex.two_step_band_rows != 0 && (ex.two_step_band_rows < 4 || ex.two_step_band_rows > 4096))
+        return fail(FWI_EINVAL, "two_step_band_rows %d out of range (4..4096)",
+                    ex.two_step_band_rows);
+    {
+        const int s2 = ex.two_step_shots_per_group, c2 = ex.two_step_lane_cols;
+        if (s2 < 0 || c2 < 0 || !fused2_supported(s2 ? s2 : 1, c2 ? c2 : 1))
+            return fail(FWI_EINVAL, "two-step kernel: shots_per_group %d with lane_cols %d not "
+                        "supported", s2, c2);
+    }
 
     fwi_plan *p = new fwi_plan();
     p->grid = G;
@@ -703,15 +788,6 @@ fwi_status fwi_plan_create(const fwi_grid *grid, const fwi_acq *acq, const fwi_e
     g.Npml = 2LL * G.npml * Nx + (Nz - 2LL * G.npml) * 2 * G.npml;
     p->SS = align64(3 * g.N + g.Npml);
     p->ST = align64(g.N + g.Npml);
-    int k = ex.ckpt_every > 0 ? ex.ckpt_every : (int)std::ceil(std::sqrt((double)G.nt));
-    if (p->mode == FWI_EXEC_PLAIN && ex.ckpt_every == 0) {
-        // plain: keep the whole history of one shot when it takes <= 64 GiB
-        double bytes = (double)(G.nt + 1) * p->ST * sizeof(float);
-        if (bytes <= 64.0 * (1ull << 30))
-            k = G.nt;
-    }
-    p->k = std::max(1, std::min(k, G.nt));
-    p->nseg = (G.nt + p->k - 1) / p->k;
     {
         // defaults (from decomposition sweeps on MI355X): up to four shots per
         // wave, one column per lane, bands short enough for about 4096
@@ -736,12 +812,49 @@ fwi_status fwi_plan_create(const fwi_grid *grid, const fwi_acq *acq, const fwi_e
         // the batched kernels address a shot group's records, the model and
         // a partial gradient with 32-bit byte offsets below 2^31
         const long long lim = (1LL << 31) - 64LL * Nx;
+        // two-step forward kernel over the same padded shots: defaults one
+        // shot and one column per lane, bands giving about 4096 waves, 16 to
+        // 96 rows (its halo is 6 rows)
+        const int spg2 = ex.two_step_shots_per_group ? ex.two_step_shots_per_group : 1;
+        const int cols2 = ex.two_step_lane_cols ? ex.two_step_lane_cols : 1;
+        int H2 = ex.two_step_band_rows;
+        if (H2 == 0) {
+            Sweep one = sweep_of(g, p->Spad, (int)Nz, spg2, cols2, 2);
+            long long per_band = (long long)one.nstrips * one.ngroups;
+            long long bands = std::max<long long>(1, (4096 + per_band - 1) / per_band);
+            H2 = (int)std::min<long long>(96, std::max<long long>(16, (Nz + bands - 1) / bands));
+        }
+        p->sweep2 = sweep_of(g, p->Spad, H2, spg2, cols2, 2);
+        p->two_step = p->mode != FWI_EXEC_PLAIN && ex.two_step != 1 && p->Spad % spg2 == 0 &&
+                      (long long)spg2 * p->SS * 4 < lim;
         if (p->mode != FWI_EXEC_PLAIN &&
             ((long long)spg * p->SS * 4 >= lim || 3 * g.N * 4 >= lim)) {
             delete p;
             return fail(FWI_EINVAL, "grid of %lld cells too large for %d shots per group "
                         "(records of a group must stay below 2 GiB)", (long long)g.N, spg);
         }
+    }
+    {
+        // checkpoint interval: with ckpt_every = 0 the whole pressure history
+        // is kept when it fits (plain: one shot's history <= 64 GiB;
+        // batched: all shots' history <= half the device memory), so the
+        // backward sweep needs no recompute; else every ceil(sqrt(nt)) steps
+        int k = ex.ckpt_every > 0 ? ex.ckpt_every : (int)std::ceil(std::sqrt((double)G.nt));
+        if (ex.ckpt_every == 0) {
+            const int B = p->mode == FWI_EXEC_PLAIN ? 1 : p->Spad;
+            const double bytes = (double)(G.nt + 1) * B * p->ST * sizeof(float);
+            double budget = 64.0 * (1ull << 30);
+            if (p->mode != FWI_EXEC_PLAIN) {
+                size_t free_b = 0, total_b = 0;
+                budget = hipMemGetInfo(&free_b, &total_b) == hipSuccess ? 0.5 * (double)total_b
+                                                                         : 0.0;
+                (void)hipGetLastError();
+            }
+            if (bytes <= budget)
+                k = G.nt;
+        }
+        p->k = std::max(1, std::min(k, G.nt));
+        p->nseg = (G.nt + p->k - 1) / p->k;
     }
 
     // geometry: bilinear cell and weights of every source and receiver
@@ -910,6 +1023,10 @@ fwi_status fwi_plan_get_info(const fwi_plan *p, fwi_plan_info *info)
     info->band_rows = p->sweep.H;
     info->shots_per_group = p->mode == FWI_EXEC_PLAIN ? 1 : p->sweep.spg;
     info->lane_cols = p->mode == FWI_EXEC_PLAIN ? 1 : p->sweep.cols;
+    info->two_step = p->two_step ? 1 : 0;
+    info->two_step_band_rows = p->sweep2.H;
+    info->two_step_shots_per_group = p->sweep2.spg;
+    info->two_step_lane_cols = p->sweep2.cols;
     info->shot_groups = groups_of(p);
     info->mode = p->mode;
     info->device = p->device;

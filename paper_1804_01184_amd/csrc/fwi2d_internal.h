@@ -138,9 +138,10 @@ void launch_plain_adj_b(const Geo &g, const Pml &t, const Mdl &m, const float *l
 
 // ----------------------------------------------------------------- fused
 // Decomposition of the batched kernels: each wave64 owns a strip of
-// strip_cols(cols) output columns (plus halo_cols(cols) halo columns on each
-// side; a lane holds `cols` adjacent columns) and a band of H rows, for a
-// group of spg shots.  Wave w -> (band, group, strip), strip fastest.
+// strip_cols(cols, steps) output columns (plus a halo of 3 columns per time
+// step on each side, rounded up to whole lanes; a lane holds `cols`
+// adjacent columns) and a band of H rows, for a group of spg shots.  Wave
+// w -> (band, group, strip), strip fastest.
 struct Sweep {
     int nstrips, nbands, ngroups, nwaves;
     int H;      // band rows
@@ -148,9 +149,11 @@ struct Sweep {
     int cols;   // columns per lane
 };
 bool fused_supported(int spg, int cols);
-int strip_cols(int cols);
-int halo_cols(int cols);
-Sweep sweep_of(const Geo &g, int S, int band_rows, int spg, int cols);
+bool fused2_supported(int spg, int cols);
+// Output columns of one strip of the one-step (steps = 1) or two-step
+// (steps = 2) forward kernels; the two-step kernels need twice the halo.
+int strip_cols(int cols, int steps = 1);
+Sweep sweep_of(const Geo &g, int S, int band_rows, int spg, int cols, int steps = 1);
 
 // Source tables of a plan for the batched kernels, kept in device memory
 // so that the kernels take one pointer to them.
@@ -177,6 +180,12 @@ struct FwdStep {
     const float *Q;     // [S][nt] time integral of the wavelet at n+1/2
     int n;              // time step being taken (n -> n+1)
 };
+// Two forward steps n -> n+2: pmid receives p^{n+1} and its split.
+struct FwdStep2 {
+    Recd vin, pin, vout, pout, pmid;
+    const float *Q;
+    int n;
+};
 struct AdjStep {
     Recd lin, lout, pn, pn1;
     float *gpart;       // [groups][3][N]: gK, gbx, gbz
@@ -192,5 +201,9 @@ void launch_fused_fwd(const Geo &g, const float *tabs, const float *model,
 void launch_fused_adj(const Geo &g, const float *tabs, const float *model,
                       const SweepTables *tab_dev, int S, const Sweep &sw, const AdjStep &a,
                       hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+// sw: a decomposition made with steps = 2.
+void launch_fused_fwd2(const Geo &g, const float *tabs, const float *model,
+                       const SweepTables *tab_dev, int S, const Sweep &sw, const FwdStep2 &a,
+                       hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 
 }  // namespace fwi

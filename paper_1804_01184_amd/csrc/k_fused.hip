@@ -44,6 +44,7 @@
 #include "fwi2d_internal.h"
 
 #include <hip/hip_ext.h>
+#include <type_traits>
 
 namespace fwi {
 
@@ -53,9 +54,11 @@ constexpr int WAVE = 64;
 constexpr int HALO = 3;
 constexpr int NTHR = 256;  // 4 independent waves per workgroup
 
-template <int C>
+// Strip geometry for C columns per lane and a stencil reach of R columns
+// (3 for one time step, 6 for two).
+template <int C, int R = HALO>
 struct Lanes {
-    static constexpr int HL = (HALO + C - 1) / C;   // halo lanes on each side
+    static constexpr int HL = (R + C - 1) / C;      // halo lanes on each side
     static constexpr int W = (WAVE - 2 * HL) * C;   // output columns per strip
 };
 
@@ -209,10 +212,10 @@ struct WaveGeo {
     int strip, band, grp;
 };
 
-template <int C>
+template <int C, int R = HALO>
 __device__ inline bool wave_geo(const Geo &g, const Sweep &sw, WaveGeo<C> &w)
 {
-    constexpr int HL = Lanes<C>::HL, W = Lanes<C>::W;
+    constexpr int HL = Lanes<C, R>::HL, W = Lanes<C, R>::W;
     w.lane = threadIdx.x & (WAVE - 1);
     // wave index, made provably uniform so that everything derived from it
     // (rows, shots, buffer resources) lives in scalar registers
@@ -551,6 +554,305 @@ __global__ void __launch_bounds__(NTHR)
     }
 }
 
+// ------------------------------------------------------- forward, two steps
+//
+// Steps n -> n+1 -> n+2 in one pass: the wave computes step n+1 on rows
+// [i0-3, i1+3) of its band (the second step needs p^{n+1} three rows and
+// three columns beyond its own rows and columns, so strips carry a 6-column
+// halo and step-one rows run three ahead), keeps step n+1's velocities,
+// split and model in three-row delay lines and its pressure in a window,
+// and computes step n+2 three rows behind.  Only p^{n+1} (and its split) of
+// the intermediate level is written, to the `mid` record (the pressure
+// history the adjoint reads); the intermediate velocities never leave
+// registers, so two steps cost one read and one write of the state.
+
+template <int SPG, int C>
+__global__ void __launch_bounds__(NTHR)
+    k_fwd2(Geo g, const float *__restrict__ tabs, const float *model, const SweepTables *T, int S,
+           Sweep sw, FwdStep2 a)
+{
+    WaveGeo<C> w;
+    if (!wave_geo<C, 2 * HALO>(g, sw, w))
+        return;
+    XTab<C> xt;
+    xtab<C>(g, tabs, w, xt);
+    const float *__restrict__ zaz = tabs + 4 * g.Nx, *__restrict__ zbz = zaz + g.Nz;
+    const float *__restrict__ zahz = zbz + g.Nz, *__restrict__ zbhz = zahz + g.Nz;
+    const unsigned FB = 4u * (unsigned)g.N;
+    const rsrc_t rM = res(model, 3u * FB);
+    const unsigned rowN = 4u * (unsigned)g.Nx;
+    const rsrc_t rPin = grp_res(a.pin, w.s0, SPG), rVin = grp_res(a.vin, w.s0, SPG);
+    const rsrc_t rPmid = grp_res(a.pmid, w.s0, SPG);
+    const rsrc_t rPout = grp_res(a.pout, w.s0, SPG), rVout = grp_res(a.vout, w.s0, SPG);
+    // z tables with zero outside the grid (step-one rows run past it)
+    auto zt = [&](const float *t, int r) -> float { return row_ok(g, r) ? t[r] : 0.f; };
+    // row byte offset of row r plus `extra`, or 0 when row r is outside the
+    // grid (its lane offset is then kOOB)
+    auto rofs = [&](int r, unsigned extra) -> unsigned {
+        return row_ok(g, r) ? rowb(g, r) + extra : 0u;
+    };
+    const int t0 = w.i0 - 3;
+
+    float P1[SPG][4][C];    // p^n rows t .. t+3
+    float VZ1[SPG][3][C];   // vz^{n+1/2} rows t-2 .. t
+    float P2[SPG][3][C];    // p^{n+1} rows t-3 .. t-1
+    float VZ2[SPG][3][C];   // vz^{n+3/2} rows r-2 .. r (r = t-3)
+    float DVZ[SPG][3][C];   // vz^{n+1/2} rows t-2 .. t (made at t-3 .. t-1)
+    float DVX[SPG][3][C];   // vx^{n+1/2} rows t-3 .. t-1
+    float DPZ[SPG][3][C];   // pz^{n+1} rows t-3 .. t-1
+    float DK[3][C], DBX[3][C], DBZ[3][C];   // K, bx rows t-3 .. t-1; bz rows t-2 .. t
+    int srow[SPG];
+    float swa[2][SPG][C], swb[2][SPG][C];   // source weights of steps n and n+1
+#pragma unroll
+    for (int k = 0; k < SPG; ++k) {
+        const int s = w.s0 + k;
+        srow[k] = -8;
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            swa[0][k][c] = swb[0][k][c] = swa[1][k][c] = swb[1][k][c] = 0.f;
+        if (s < S) {
+            const int2 sij = T->src_ij[s];
+            const float4 sw4 = T->src_w[s];
+            srow[k] = uni(sij.x);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const float dq = g.dt * a.Q[(long long)s * T->nt + a.n + h];
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    const int dj = w.j0 + c - sij.y;
+                    swa[h][k][c] = dj == 0 ? dq * sw4.x : (dj == 1 ? dq * sw4.y : 0.f);
+                    swb[h][k][c] = dj == 0 ? dq * sw4.z : (dj == 1 ? dq * sw4.w : 0.f);
+                }
+            }
+        }
+        const unsigned op = skoff(a.pin, k), ovz = FB + skoff(a.vin, k);
+        float pr[6][C];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            const int r = t0 - 3 + q;
+            vld<C>(rPin, row_ok(g, r) ? w.vcol : kOOB, rofs(r, op), pr[q]);
+            mask_cols<C>(w, pr[q]);
+        }
+        // vz^{n+1/2} at rows t0-2 .. t0
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int r = t0 - 2 + q;
+            const bool ok = row_ok(g, r);
+            const unsigned vo = ok ? w.vcol : kOOB;
+            float bz[C], vz[C];
+            vld<C>(rM, vo, rofs(r, 2u * FB), bz);
+            vld<C>(rVin, vo, rofs(r, ovz), vz);
+            const float ahz = zt(zahz, r), bhz = zt(zbhz, r);
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                VZ1[k][q][c] = ahz * vz[c] -
+                               bhz * bz[c] *
+                                   (kC1 * (pr[q + 2][c] - pr[q + 1][c]) + kC2 * (pr[q + 3][c] - pr[q][c])) *
+                                   g.rdz;
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            P1[k][0][c] = pr[3][c];
+            P1[k][1][c] = pr[4][c];
+            P1[k][2][c] = pr[5][c];
+            P1[k][3][c] = 0.f;
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+                P2[k][q][c] = VZ2[k][q][c] = DVZ[k][q][c] = DVX[k][q][c] = DPZ[k][q][c] = 0.f;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            DK[q][c] = DBX[q][c] = DBZ[q][c] = 0.f;
+
+    // step-one loads of row t (p at t+3, vz at t+1, vx and split at t,
+    // K and bx at t, bz at t+1); rows outside the grid read zero
+    auto load_row = [&](int t, FRow<SPG, C> &b) {
+        const bool live = t < w.i1 + 3;
+        const bool ok0 = live && row_ok(g, t), ok1 = live && row_ok(g, t + 1);
+        const bool ok3 = live && row_ok(g, t + 3);
+        const unsigned o0 = ok0 ? w.vcol : kOOB, o1 = ok1 ? w.vcol : kOOB;
+        const unsigned o3 = ok3 ? w.vcol : kOOB;
+        const ZRow z = zrow(g, ok0 ? t : 0);
+        unsigned oz[C];
+        zoffs<C>(w, z, ok0, oz);
+        vld<C>(rM, o0, rofs(t, 0u), b.K);
+        vld<C>(rM, o0, rofs(t, FB), b.bx);
+        vld<C>(rM, o1, rofs(t + 1, 2u * FB), b.bz1);
+#pragma unroll
+        for (int k = 0; k < SPG; ++k) {
+            const unsigned kp = skoff(a.pin, k), kv = skoff(a.vin, k);
+            vld<C>(rPin, o3, rofs(t + 3, kp), b.p3[k]);
+            vld<C>(rVin, o1, rofs(t + 1, FB + kv), b.vz1[k]);
+            vld<C>(rVin, o0, rofs(t, kv), b.vx[k]);
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                b.pz[k][c] = bld(rPin, oz[c], z.base + FB + kp);
+        }
+    };
+
+    auto row = [&](int t, FRow<SPG, C> &b) {
+        const bool okt = row_ok(g, t);
+        const bool rp1 = t < g.npml || t >= g.Nz - g.npml;   // row t in the layer
+        const float ahz1 = zt(zahz, t + 1), bhz1 = zt(zbhz, t + 1);
+        const float az1 = zt(zaz, t), btz1 = zt(zbz, t);
+        const ZRow z1 = zrow(g, okt ? t : 0);
+        unsigned zw1[C];
+        zoffs_w<C>(w, z1, zw1);
+        const bool mid_on = t >= w.i0 && t < w.i1;   // this wave owns p^{n+1} row t
+        const int r = t - 3;                          // step-two row
+        const bool two = t >= w.i0;                   // step two runs (r >= i0 - 3)
+        const bool full = r >= w.i0;                  // step two on an owned row
+        const bool rn = row_ok(g, r + 1);
+        const float ahz2 = zt(zahz, r + 1), bhz2 = zt(zbhz, r + 1);
+        const float az2 = zt(zaz, r), btz2 = zt(zbz, r);
+        const ZRow z2 = zrow(g, full ? r : 0);
+        unsigned zw2[C];
+        zoffs_w<C>(w, z2, zw2);
+        const unsigned rb1 = okt ? rowb(g, t) : 0u, rb2 = full ? rowb(g, r) : 0u;
+        const unsigned rbz = (r + 1 >= w.i0 && r + 1 < w.i1) ? rowb(g, r + 1) : 0u;
+        const bool vz_on = r + 1 >= w.i0 && r + 1 < w.i1;   // owns vz row r+1
+#pragma unroll
+        for (int k = 0; k < SPG; ++k) {
+            mask_cols<C>(w, b.p3[k]);
+            // ---- step one at row t
+            float vzn[C], vxn[C], dp[C], pn[C], pzn[C], dvx[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                P1[k][3][c] = b.p3[k][c];
+                vzn[c] = ahz1 * b.vz1[k][c] -
+                         bhz1 * b.bz1[c] *
+                             (kC1 * (P1[k][2][c] - P1[k][1][c]) + kC2 * (P1[k][3][c] - P1[k][0][c])) * g.rdz;
+            }
+            dfwd<C>(P1[k][0], dp);
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                vxn[c] = xt.ahx[c] * b.vx[k][c] - xt.bhx[c] * b.bx[c] * dp[c] * g.rdx;
+            dbwd<C>(vxn, dvx);
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const float dvz = kC1 * (VZ1[k][2][c] - VZ1[k][1][c]) + kC2 * (vzn[c] - VZ1[k][0][c]);
+                const float pz = b.pz[k][c];
+                const float px = xt.ax[c] * (P1[k][0][c] - pz) - xt.btx[c] * b.K[c] * dvx[c] * g.rdx;
+                pzn[c] = az1 * pz - btz1 * b.K[c] * dvz * g.rdz;
+                pn[c] = px + pzn[c];
+            }
+            if ((unsigned)(t - srow[k]) < 2u) {
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+                    pn[c] += b.K[c] * (t == srow[k] ? swa[0][k][c] : swb[0][k][c]);
+            }
+            // p^{n+1} past the last grid column must read zero in step two's
+            // horizontal differences
+            mask_cols<C>(w, pn);
+            const unsigned km = skoff(a.pmid, k);
+            vst_row<C>(rPmid, w, mid_on, rb1 + km, pn);
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                bst(rPmid, mid_on ? zw1[c] : kOOB, z1.base + FB + km, pzn[c]);
+            // ---- step two at row r = t-3 (p^{n+1} rows r .. r+3 = P2, pn)
+            if (two) {
+                float vz2[C];
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+                    vz2[c] = rn ? ahz2 * DVZ[k][0][c] -
+                                      bhz2 * DBZ[0][c] *
+                                          (kC1 * (P2[k][2][c] - P2[k][1][c]) + kC2 * (pn[c] - P2[k][0][c])) *
+                                          g.rdz
+                                : 0.f;
+                const unsigned kv = skoff(a.vout, k), kp = skoff(a.pout, k);
+                if (full) {
+                    float dp2[C], vx2[C], dvx2[C], p2[C], pz2[C];
+                    dfwd<C>(P2[k][0], dp2);
+#pragma unroll
+                    for (int c = 0; c < C; ++c)
+                        vx2[c] = xt.ahx[c] * DVX[k][0][c] - xt.bhx[c] * DBX[0][c] * dp2[c] * g.rdx;
+                    dbwd<C>(vx2, dvx2);
+#pragma unroll
+                    for (int c = 0; c < C; ++c) {
+                        const float dvz = kC1 * (VZ2[k][2][c] - VZ2[k][1][c]) + kC2 * (vz2[c] - VZ2[k][0][c]);
+                        const float pz = DPZ[k][0][c];
+                        const float px =
+                            xt.ax[c] * (P2[k][0][c] - pz) - xt.btx[c] * DK[0][c] * dvx2[c] * g.rdx;
+                        pz2[c] = az2 * pz - btz2 * DK[0][c] * dvz * g.rdz;
+                        p2[c] = px + pz2[c];
+                    }
+                    if ((unsigned)(r - srow[k]) < 2u) {
+#pragma unroll
+                        for (int c = 0; c < C; ++c)
+                            p2[c] += DK[0][c] * (r == srow[k] ? swa[1][k][c] : swb[1][k][c]);
+                    }
+                    vst_row<C>(rVout, w, true, rb2 + kv, vx2);
+                    vst_row<C>(rPout, w, true, rb2 + kp, p2);
+#pragma unroll
+                    for (int c = 0; c < C; ++c)
+                        bst(rPout, zw2[c], z2.base + FB + kp, pz2[c]);
+                }
+                vst_row<C>(rVout, w, vz_on, rbz + FB + kv, vz2);
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    VZ2[k][0][c] = VZ2[k][1][c];
+                    VZ2[k][1][c] = VZ2[k][2][c];
+                    VZ2[k][2][c] = vz2[c];
+                }
+            }
+            // ---- shift the windows and delay lines
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                P2[k][0][c] = P2[k][1][c];
+                P2[k][1][c] = P2[k][2][c];
+                P2[k][2][c] = pn[c];
+                DVZ[k][0][c] = DVZ[k][1][c];
+                DVZ[k][1][c] = DVZ[k][2][c];
+                DVZ[k][2][c] = vzn[c];
+                DVX[k][0][c] = DVX[k][1][c];
+                DVX[k][1][c] = DVX[k][2][c];
+                DVX[k][2][c] = vxn[c];
+                DPZ[k][0][c] = DPZ[k][1][c];
+                DPZ[k][1][c] = DPZ[k][2][c];
+                // the split is kept only where the layer has one (elsewhere
+                // the one-step path reads it as zero); carrying the computed
+                // value would round the interior differently
+                DPZ[k][2][c] = rp1 || w.colpml[c] ? pzn[c] : 0.f;
+                VZ1[k][0][c] = VZ1[k][1][c];
+                VZ1[k][1][c] = VZ1[k][2][c];
+                VZ1[k][2][c] = vzn[c];
+                P1[k][0][c] = P1[k][1][c];
+                P1[k][1][c] = P1[k][2][c];
+                P1[k][2][c] = P1[k][3][c];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            DK[0][c] = DK[1][c];
+            DK[1][c] = DK[2][c];
+            DK[2][c] = b.K[c];
+            DBX[0][c] = DBX[1][c];
+            DBX[1][c] = DBX[2][c];
+            DBX[2][c] = b.bx[c];
+            DBZ[0][c] = DBZ[1][c];
+            DBZ[1][c] = DBZ[2][c];
+            DBZ[2][c] = b.bz1[c];
+        }
+    };
+
+    FRow<SPG, C> A, B;
+    const int tend = w.i1 + 3;   // step-one rows [t0, tend)
+    load_row(t0, A);
+    for (int t = t0;;) {
+        load_row(t + 1, B);
+        row(t, A);
+        if (++t >= tend)
+            break;
+        load_row(t + 1, A);
+        row(t, B);
+        if (++t >= tend)
+            break;
+    }
+}
+
 // ---------------------------------------------------------------- adjoint
 //
 // State on entry: nu = adjoint after step n+1 with R^T r^n already added to
@@ -614,11 +916,15 @@ __global__ void __launch_bounds__(NTHR)
         }
     };
 
+    // Row windows are rings of 4 slots: at phase R = (i - i0) mod 4 the row
+    // of logical index q sits in slot (q + R) & 3, so moving down a row
+    // re-labels the slots instead of copying them (the row loop is unrolled
+    // four times, one phase each).
     float KW[4][C];         // K rows i .. i+3
     float MU[SPG][4][C];    // mu_px rows i .. i+3
     float MZ[SPG][4][C];    // mu_pz rows i .. i+3
     float PN[SPG][4][C];    // p^n rows i .. i+3
-    float WZ[SPG][3][C];    // beta_h bz lvz_mid rows i-2 .. i
+    float WZ[SPG][4][C];    // beta_h bz lvz_mid rows i-2 .. i+1
 
     float Kr[6][C], btzr[6], wzr[3][C];
 #pragma unroll
@@ -678,6 +984,9 @@ __global__ void __launch_bounds__(NTHR)
         }
         // lvz_mid at rows i0-2 .. i0 (zero outside the grid)
         float l[3][C];
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            WZ[k][3][c] = 0.f;
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
             const int r = w.i0 - 2 + q;
@@ -784,7 +1093,9 @@ __global__ void __launch_bounds__(NTHR)
         }
     };
 
-    auto row = [&](int i, ARow<SPG, C> &b, const ALate<SPG, C> &t) {
+    auto row = [&](auto phase, int i, ARow<SPG, C> &b, const ALate<SPG, C> &t) {
+        constexpr int R = decltype(phase)::value;
+        constexpr int S0 = R & 3, S1 = (1 + R) & 3, S2 = (2 + R) & 3, S3 = (3 + R) & 3;
         const unsigned rb = rowb(g, i);
         const bool rn = row_ok(g, i + 1);
         const bool more = i + 1 < w.i1;   // this wave owns lvz / gbz row i+1
@@ -798,34 +1109,34 @@ __global__ void __launch_bounds__(NTHR)
         float numK[C], accX[C], accZ[C], bK[4][C];
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            KW[3][c] = b.K3[c];
+            KW[S3][c] = b.K3[c];
             numK[c] = accX[c] = accZ[c] = 0.f;
-            bK[0][c] = KW[0][c] * bt0;
-            bK[1][c] = KW[1][c] * bt1;
-            bK[2][c] = KW[2][c] * bt2;
-            bK[3][c] = KW[3][c] * bt3;
+            bK[0][c] = KW[S0][c] * bt0;
+            bK[1][c] = KW[S1][c] * bt1;
+            bK[2][c] = KW[S2][c] * bt2;
+            bK[3][c] = KW[S3][c] * bt3;
         }
 #pragma unroll
         for (int k = 0; k < SPG; ++k) {
             mask_cols<C>(w, b.pn3[k]);
-            float lvzm[C], wzn[C], qx[C], dqx[C], dpx[C], lvxm[C], wx[C], dwx[C], tsum[C];
+            float lvzm[C], qx[C], dqx[C], dpx[C], lvxm[C], wx[C], dwx[C], tsum[C];
 #pragma unroll
             for (int c = 0; c < C; ++c) {
-                MU[k][3][c] = b.mu3[k][c];
-                MZ[k][3][c] = rp3 || w.colpml[c] ? b.mz3[k][c] : b.mu3[k][c];
-                PN[k][3][c] = b.pn3[k][c];
+                MU[k][S3][c] = b.mu3[k][c];
+                MZ[k][S3][c] = rp3 || w.colpml[c] ? b.mz3[k][c] : b.mu3[k][c];
+                PN[k][S3][c] = b.pn3[k][c];
                 // lvz_mid at row (i+1): D+z of beta_z K mu_pz
-                const float q0 = bK[0][c] * MZ[k][0][c], q1 = bK[1][c] * MZ[k][1][c];
-                const float q2 = bK[2][c] * MZ[k][2][c], q3 = bK[3][c] * MZ[k][3][c];
+                const float q0 = bK[0][c] * MZ[k][S0][c], q1 = bK[1][c] * MZ[k][S1][c];
+                const float q2 = bK[2][c] * MZ[k][S2][c], q3 = bK[3][c] * MZ[k][S3][c];
                 lvzm[c] = rn ? b.lvz1[k][c] + (kC1 * (q2 - q1) + kC2 * (q3 - q0)) * g.rdz : 0.f;
-                accZ[c] += lvzm[c] * (-bhz1 * (kC1 * (PN[k][2][c] - PN[k][1][c]) +
-                                               kC2 * (PN[k][3][c] - PN[k][0][c])) * g.rdz);
-                wzn[c] = bhz1 * b.bz1[c] * lvzm[c];
+                accZ[c] += lvzm[c] * (-bhz1 * (kC1 * (PN[k][S2][c] - PN[k][S1][c]) +
+                                               kC2 * (PN[k][S3][c] - PN[k][S0][c])) * g.rdz);
+                WZ[k][S3][c] = bhz1 * b.bz1[c] * lvzm[c];
                 // lvx_mid at row i: D+x of beta_x K mu_px
-                qx[c] = xt.btx[c] * KW[0][c] * MU[k][0][c];
+                qx[c] = xt.btx[c] * KW[S0][c] * MU[k][S0][c];
             }
             dfwd<C>(qx, dqx);
-            dfwd<C>(PN[k][0], dpx);
+            dfwd<C>(PN[k][S0], dpx);
 #pragma unroll
             for (int c = 0; c < C; ++c) {
                 lvxm[c] = w.colok[c] ? b.lvx[k][c] + dqx[c] * g.rdx : 0.f;
@@ -835,13 +1146,13 @@ __global__ void __launch_bounds__(NTHR)
             dbwd<C>(wx, dwx);
 #pragma unroll
             for (int c = 0; c < C; ++c) {
-                const float dwz = kC1 * (WZ[k][2][c] - WZ[k][1][c]) + kC2 * (wzn[c] - WZ[k][0][c]);
+                const float dwz = kC1 * (WZ[k][S2][c] - WZ[k][S1][c]) + kC2 * (WZ[k][S3][c] - WZ[k][S0][c]);
                 tsum[c] = dwx[c] * g.rdx + dwz * g.rdz;
             }
             float opx[C], opz[C], ovx[C], ovz[C];
 #pragma unroll
             for (int c = 0; c < C; ++c) {
-                const float mux = MU[k][0][c], muz = MZ[k][0][c], p0 = PN[k][0][c];
+                const float mux = MU[k][S0][c], muz = MZ[k][S0][c], p0 = PN[k][S0][c];
                 const float z0 = t.z0[k][c], z1 = t.z1[k][c], p1 = t.pn1[k][c];
                 numK[c] += mux * ((p1 - z1) - xt.ax[c] * (p0 - z0)) + muz * (z1 - az * z0);
                 opx[c] = xt.ax[c] * mux + tsum[c];
@@ -856,30 +1167,15 @@ __global__ void __launch_bounds__(NTHR)
                 bst(rLout, zw[c], z.base + 3u * FB + ko, opz[c]);
             vst_row<C>(rLout, w, true, rb + ko, ovx);
             vst_row<C>(rLout, w, more, rb + rowN + FB + ko, ovz);
-#pragma unroll
-            for (int c = 0; c < C; ++c) {
-                WZ[k][0][c] = WZ[k][1][c];
-                WZ[k][1][c] = WZ[k][2][c];
-                WZ[k][2][c] = wzn[c];
-#pragma unroll
-                for (int q = 0; q < 3; ++q) {
-                    MU[k][q][c] = MU[k][q + 1][c];
-                    MZ[k][q][c] = MZ[k][q + 1][c];
-                    PN[k][q][c] = PN[k][q + 1][c];
-                }
-            }
         }
         // one reciprocal per row for the bulk-modulus sensitivity (1 ulp)
         float gk[C], gx[C], gz[C];
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            const float rK = KW[0][c] != 0.f ? __builtin_amdgcn_rcpf(KW[0][c]) : 0.f;
+            const float rK = KW[S0][c] != 0.f ? __builtin_amdgcn_rcpf(KW[S0][c]) : 0.f;
             gk[c] = t.gK[c] + numK[c] * rK;
             gx[c] = t.gX[c] + accX[c];
             gz[c] = t.gZ1[c] + accZ[c];
-            KW[0][c] = KW[1][c];
-            KW[1][c] = KW[2][c];
-            KW[2][c] = KW[3][c];
         }
         vst_row<C>(rG, w, true, rb, gk);
         vst_row<C>(rG, w, true, rb + FB, gx);
@@ -888,16 +1184,30 @@ __global__ void __launch_bounds__(NTHR)
 
     ARow<SPG, C> A, B;
     ALate<SPG, C> L;
+    using P0 = std::integral_constant<int, 0>;
+    using P1 = std::integral_constant<int, 1>;
+    using P2 = std::integral_constant<int, 2>;
+    using P3 = std::integral_constant<int, 3>;
     load_row(w.i0, A);
     for (int i = w.i0;;) {
         load_late(i, L);
         load_row(i + 1, B);
-        row(i, A, L);
+        row(P0{}, i, A, L);
         if (++i >= w.i1)
             break;
         load_late(i, L);
         load_row(i + 1, A);
-        row(i, B, L);
+        row(P1{}, i, B, L);
+        if (++i >= w.i1)
+            break;
+        load_late(i, L);
+        load_row(i + 1, B);
+        row(P2{}, i, A, L);
+        if (++i >= w.i1)
+            break;
+        load_late(i, L);
+        load_row(i + 1, A);
+        row(P3{}, i, B, L);
         if (++i >= w.i1)
             break;
     }
@@ -918,6 +1228,13 @@ void launch_f(const Geo &g, const float *tabs, const float *model, const SweepTa
                           tabs, model, T, S, sw, a);
 }
 template <int SPG, int C>
+void launch_f2(const Geo &g, const float *tabs, const float *model, const SweepTables *T, int S,
+               const Sweep &sw, const FwdStep2 &a, hipStream_t st, hipEvent_t e0, hipEvent_t e1)
+{
+    hipExtLaunchKernelGGL((k_fwd2<SPG, C>), dim3(blocks_of(sw)), dim3(NTHR), 0, st, e0, e1, 0, g,
+                          tabs, model, T, S, sw, a);
+}
+template <int SPG, int C>
 void launch_a(const Geo &g, const float *tabs, const float *model, const SweepTables *T, int S,
               const Sweep &sw, const AdjStep &a, hipStream_t st, hipEvent_t e0, hipEvent_t e1)
 {
@@ -926,6 +1243,13 @@ void launch_a(const Geo &g, const float *tabs, const float *model, const SweepTa
 }
 
 }  // namespace
+
+// Instantiated (shots per group, columns per lane) pairs of the two-step
+// forward kernel.
+bool fused2_supported(int spg, int cols)
+{
+    return (spg == 1 || spg == 2) && (cols == 1 || cols == 2 || (cols == 4 && spg == 1));
+}
 
 // Instantiated (shots per group, columns per lane) pairs.
 bool fused_supported(int spg, int cols)
@@ -938,8 +1262,15 @@ bool fused_supported(int spg, int cols)
     return false;
 }
 
-int strip_cols(int cols)
+int strip_cols(int cols, int steps)
 {
+    if (steps == 2) {
+        switch (cols) {
+        case 2: return Lanes<2, 2 * HALO>::W;
+        case 4: return Lanes<4, 2 * HALO>::W;
+        default: return Lanes<1, 2 * HALO>::W;
+        }
+    }
     switch (cols) {
     case 2: return Lanes<2>::W;
     case 4: return Lanes<4>::W;
@@ -947,22 +1278,13 @@ int strip_cols(int cols)
     }
 }
 
-int halo_cols(int cols)
-{
-    switch (cols) {
-    case 2: return Lanes<2>::HL * 2;
-    case 4: return Lanes<4>::HL * 4;
-    default: return Lanes<1>::HL;
-    }
-}
-
-Sweep sweep_of(const Geo &g, int S, int band_rows, int spg, int cols)
+Sweep sweep_of(const Geo &g, int S, int band_rows, int spg, int cols, int steps)
 {
     Sweep sw;
     sw.H = band_rows;
     sw.spg = spg;
     sw.cols = cols;
-    const int W = strip_cols(cols);
+    const int W = strip_cols(cols, steps);
     sw.nstrips = (g.Nx + W - 1) / W;
     sw.nbands = (g.Nz + band_rows - 1) / band_rows;
     sw.ngroups = (S + spg - 1) / spg;
@@ -989,6 +1311,20 @@ void launch_fused_fwd(const Geo &g, const float *tabs, const float *model,
                       hipStream_t st, hipEvent_t e0, hipEvent_t e1)
 {
     FWI_DISPATCH(launch_f, g, tabs, model, T, S, sw, a, st, e0, e1)
+}
+
+void launch_fused_fwd2(const Geo &g, const float *tabs, const float *model,
+                       const SweepTables *T, int S, const Sweep &sw, const FwdStep2 &a,
+                       hipStream_t st, hipEvent_t e0, hipEvent_t e1)
+{
+    switch (sw.cols * 16 + sw.spg) {
+    case 16 + 1: launch_f2<1, 1>(g, tabs, model, T, S, sw, a, st, e0, e1); break;
+    case 16 + 2: launch_f2<2, 1>(g, tabs, model, T, S, sw, a, st, e0, e1); break;
+    case 32 + 1: launch_f2<1, 2>(g, tabs, model, T, S, sw, a, st, e0, e1); break;
+    case 32 + 2: launch_f2<2, 2>(g, tabs, model, T, S, sw, a, st, e0, e1); break;
+    case 64 + 1: launch_f2<1, 4>(g, tabs, model, T, S, sw, a, st, e0, e1); break;
+    default: break;
+    }
 }
 
 void launch_fused_adj(const Geo &g, const float *tabs, const float *model,

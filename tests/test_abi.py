@@ -77,6 +77,14 @@ def test_bad_exec_rejected():
     assert rc == -1
     rc, _ = _create(exec_=L.FwiExec(0, 0, 0, 8, 2))
     assert rc == -1
+    rc, _ = _create(exec_=L.FwiExec(0, 0, 0, 0, 0, 3))
+    assert rc == -1
+    rc, _ = _create(exec_=L.FwiExec(0, 0, 0, 0, 0, 2, 0, 4, 0))
+    assert rc == -1
+    rc, _ = _create(exec_=L.FwiExec(0, 0, 0, 0, 0, 2, 0, 2, 4))
+    assert rc == -1
+    rc, _ = _create(exec_=L.FwiExec(0, 0, 0, 0, 0, 2, 2, 0, 0))
+    assert rc == -1
 
 
 def test_null_calls_rejected():
