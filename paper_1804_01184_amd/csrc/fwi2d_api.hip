@@ -452,8 +452,9 @@ void sweep_forward(const Ctx &c, int s0, int nb, bool keep, float *traces)
         }
         return out;
     };
+    // samples of levels in the store are taken in one launch at the end
     auto sample = [&](const State &st, int n) {
-        if (!traces)
+        if (!traces || (keep && n >= nlast))
             return;
         Timed tm(c.pl, c.st, FWI_KC_SAMPLE);
         launch_sample(g, st.p, st.pz, rec, real_shots(p, s0, nb), traces, nt, n, c.st);
@@ -492,6 +493,11 @@ void sweep_forward(const Ctx &c, int s0, int nb, bool keep, float *traces)
             cw = cw1;
             n += 1;
         }
+    }
+    if (traces && keep) {
+        Timed tm(c.pl, c.st, FWI_KC_SAMPLE);
+        launch_sample_hist(g, slot_p(nlast + 1).first.p, (long long)nb * p->ST, p->ST, rec,
+                           real_shots(p, s0, nb), traces, nt, nlast, nt - nlast, c.st);
     }
 }
 
@@ -812,16 +818,17 @@ fwi_status fwi_plan_create(const fwi_grid *grid, const fwi_acq *acq, const fwi_e
         // the batched kernels address a shot group's records, the model and
         // a partial gradient with 32-bit byte offsets below 2^31
         const long long lim = (1LL << 31) - 64LL * Nx;
-        // two-step forward kernel over the same padded shots: defaults one
-        // shot and one column per lane, bands giving about 4096 waves, 16 to
-        // 96 rows (its halo is 6 rows)
-        const int spg2 = ex.two_step_shots_per_group ? ex.two_step_shots_per_group : 1;
+        // two-step forward kernel over the same padded shots: defaults two
+        // shots (one if the padded count is odd) and one column per lane,
+        // bands giving about 8192 waves, 16 to 96 rows (its halo is 6 rows)
+        const int spg2 = ex.two_step_shots_per_group ? ex.two_step_shots_per_group
+                                                     : (p->Spad % 2 == 0 ? 2 : 1);
         const int cols2 = ex.two_step_lane_cols ? ex.two_step_lane_cols : 1;
         int H2 = ex.two_step_band_rows;
         if (H2 == 0) {
             Sweep one = sweep_of(g, p->Spad, (int)Nz, spg2, cols2, 2);
             long long per_band = (long long)one.nstrips * one.ngroups;
-            long long bands = std::max<long long>(1, (4096 + per_band - 1) / per_band);
+            long long bands = std::max<long long>(1, (8192 + per_band - 1) / per_band);
             H2 = (int)std::min<long long>(96, std::max<long long>(16, (Nz + bands - 1) / bands));
         }
         p->sweep2 = sweep_of(g, p->Spad, H2, spg2, cols2, 2);

@@ -100,6 +100,11 @@ void launch_cumulative_wavelet(const float *f, int per_shot, int S, int nt, floa
                                hipStream_t st);
 void launch_sample(const Geo &g, Fld p, Fld pz, const Rec &r, int S, float *traces, int nt,
                    int n, hipStream_t st);
+// Samples traces[s][r][n0 + m] for m < nsteps from stored pressure levels:
+// level m of shot s at hist + m * slot_stride + s * ss.
+void launch_sample_hist(const Geo &g, const float *hist, long long slot_stride, long long ss,
+                        const Rec &r, int S, float *traces, int nt, int n0, int nsteps,
+                        hipStream_t st);
 // shot0: shot index of lp.shot(0) (the table holds global shot indices).
 void launch_inject(const Geo &g, const Inj &inj, const float *resid, int nrec, int nt, int n,
                    Fld lp, int shot0, hipStream_t st);

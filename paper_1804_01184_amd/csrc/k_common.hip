@@ -191,6 +191,44 @@ __global__ void k_sample(Geo g, Fld p, Rec rec, int S, float *traces, int nt, in
     traces[(long long)t * nt + n] = v;
 }
 
+// Receiver samples of a run of stored pressure levels: trace sample n0 + m
+// of shot s is read from level slot m (at hist + m * slot_stride, shot s at
+// s * ss).  A block covers 64 receivers by 64 steps and writes through a
+// shared-memory transpose, so both the reads (along receivers) and the
+// writes (along time) are contiguous.
+constexpr int kST = 64;
+__global__ void __launch_bounds__(256) k_sample_hist(Geo g, const float *hist, long long slot_stride,
+                                                    long long ss, Rec rec, float *traces, int nt,
+                                                    int n0, int nsteps)
+{
+    __shared__ float tile[kST][kST + 1];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int r0 = blockIdx.x * kST, m0 = blockIdx.y * kST, s = blockIdx.z;
+    const int r = r0 + lane;
+    const bool rok = r < rec.nrec;
+    long long c = 0;
+    float4 w = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (rok) {
+        c = rec.idx[(long long)s * rec.nrec + r];
+        w = rec.w[(long long)s * rec.nrec + r];
+    }
+    for (int ml = wv; ml < kST; ml += 4) {
+        const int m = m0 + ml;
+        float v = 0.f;
+        if (rok && m < nsteps) {
+            const float *ps = hist + (long long)m * slot_stride + (long long)s * ss;
+            v = w.x * ps[c] + w.y * ps[c + 1] + w.z * ps[c + g.Nx] + w.w * ps[c + g.Nx + 1];
+        }
+        tile[ml][lane] = v;
+    }
+    __syncthreads();
+    for (int rl = wv; rl < kST; rl += 4) {
+        const int rr = r0 + rl, m = m0 + lane;
+        if (rr < rec.nrec && m < nsteps)
+            traces[((long long)s * rec.nrec + rr) * nt + n0 + m] = tile[lane][rl];
+    }
+}
+
 // lambda_p[s][node] += sum over receivers touching the node (ascending
 // receiver order) of weight * residual[s][r][n].  Receivers lie outside the
 // absorbing layer, where both split components share the main array.
@@ -422,6 +460,17 @@ void launch_sample(const Geo &g, Fld p, Fld, const Rec &r, int S, float *traces,
     int total = S * r.nrec;
     hipLaunchKernelGGL(k_sample, dim3(blocks_for(total)), dim3(kBlock), 0, st, g, p, r, S,
                        traces, nt, n);
+}
+
+void launch_sample_hist(const Geo &g, const float *hist, long long slot_stride, long long ss,
+                        const Rec &r, int S, float *traces, int nt, int n0, int nsteps,
+                        hipStream_t st)
+{
+    if (S <= 0 || r.nrec <= 0 || nsteps <= 0)
+        return;
+    dim3 grid(blocks_for(r.nrec, kST), blocks_for(nsteps, kST), S);
+    hipLaunchKernelGGL(k_sample_hist, grid, dim3(256), 0, st, g, hist, slot_stride, ss, r,
+                       traces, nt, n0, nsteps);
 }
 
 void launch_inject(const Geo &, const Inj &inj, const float *resid, int nrec, int nt, int n,

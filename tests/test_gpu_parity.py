@@ -216,6 +216,21 @@ def test_checkpointed_equals_full_history_bitwise(api, small):
     np.testing.assert_array_equal(out[0][1], out[1][1])
 
 
+@pytest.mark.parametrize("mode,ckpt", [("batched", 0), ("batched", 7), ("plain", 0)])
+def test_kept_sweep_traces_match_forward(api, small, mode, ckpt):
+    """Sweeps that keep the pressure history sample the stored levels in one
+    launch after the sweep (checkpointed sweeps only for the last segment);
+    their traces equal those sampled step by step."""
+    w = small.w
+    p = api.Plan(agrid(api, w), w.src_xz, w.rec_xz, mode=mode, ckpt_every=ckpt)
+    ref = p.forward("k-rho", small.K0, small.r0, small.f).cpu().numpy()
+    _, _, _, tr = p.gradient("k-rho", small.K0, small.r0, small.f, small.obs, want_traces=True)
+    np.testing.assert_array_equal(tr.cpu().numpy(), ref)
+    ws = p.new_workspace(api.L.FWI_OP_GRADIENT)
+    kept = p.forward_keep("k-rho", small.K0, small.r0, small.f, ws).cpu().numpy()
+    np.testing.assert_array_equal(kept, ref)
+
+
 def test_repeatable_bitwise(api, small):
     w = small.w
     p = api.Plan(agrid(api, w), w.src_xz, w.rec_xz)
