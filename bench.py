@@ -41,6 +41,9 @@ def parse():
     ap.add_argument("--shots-per-group", type=int, default=0)
     ap.add_argument("--lane-cols", type=int, default=0)
     ap.add_argument("--ckpt-every", type=int, default=0)
+    ap.add_argument("--no-tune", action="store_true",
+                    help="use the library's default decomposition instead of the autotuned "
+                         "one (the tuner also runs unless a decomposition is given)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=0, help="time steps of the CPU sample")
@@ -74,14 +77,21 @@ def algorithmic_bytes(plan_info, S):
     adjoint step: read and write the adjoint vx, vz, p (24 B) and its split
     (8 B), read p^n and p^{n+1} (8 B) and their splits (8 B), the model once
     and one read-modify-write of the three gradient arrays (12 + 24 B per
-    cell).  Re-reads the kernels make beyond this (halo rows, the model and
-    the partial gradient once per shot group) show in the measured traffic."""
+    cell);
+    two forward steps in one launch: read vx, vz, p and its split once
+    (12 B + 4 B per layer cell), write p^{n+1} for the history and vx, vz,
+    p^{n+2} (16 B) with both splits (8 B), the model once.
+    Re-reads the kernels make beyond this (halo rows, the model and the
+    partial gradient once per shot group) show in the measured traffic."""
     N = plan_info["Nz"] * plan_info["Nx"]
     fp = plan_info["pml_cells"] / N
     fwd = N * S * (24 + 8 * fp) + N * 12
     adj = N * S * (32 + 16 * fp) + N * (12 + 24)
-    return {"fwd_step": fwd, "adj_step": adj, "per_cell_fwd": fwd / (N * S),
-            "per_cell_adj": adj / (N * S), "pml_fraction": fp}
+    pair = N * S * (28 + 12 * fp) + N * 12
+    out = {"fwd_step": fwd, "adj_step": adj, "fwd_pair": pair, "pml_fraction": fp}
+    for k in ("fwd_step", "adj_step", "fwd_pair"):
+        out["per_cell_" + k] = out[k] / (N * S)
+    return out
 
 
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1804_01184_amd", "csrc", "k_fused.hip")
@@ -99,10 +109,10 @@ def measured_traffic(kernel, decomposition):
             sha = hashlib.sha256(fh.read()).hexdigest()
     except (OSError, ValueError):
         return None
-    if prof.get("source_sha256") != sha or prof.get("decomposition") != decomposition:
-        return None
     k = prof.get("kernels", {}).get(kernel)
-    return None if k is None else int(k["bytes_per_launch"])
+    if prof.get("source_sha256") != sha or k is None or k.get("decomposition") != decomposition:
+        return None
+    return int(k["bytes_per_launch"])
 
 
 def copy_calibration():
@@ -160,9 +170,17 @@ def main():
     f = torch.tensor(w.wavelet(), dtype=torch.float32, device=dev)
     vp0 = torch.tensor(w.vp_start, dtype=torch.float32, device=dev)
     rho0 = torch.tensor(w.rho_start, dtype=torch.float32, device=dev)
-    plan = api.Plan(grid, w.src_xz, w.rec_xz, band_rows=args.band_rows,
-                    shots_per_group=args.shots_per_group, lane_cols=args.lane_cols,
-                    ckpt_every=args.ckpt_every)
+    decomp = {"band_rows": args.band_rows, "shots_per_group": args.shots_per_group,
+              "lane_cols": args.lane_cols}
+    tuned = None
+    if not args.no_tune and not any(decomp.values()):
+        # the autotuner times the candidate decompositions on a short run of
+        # this shape (cached per shape and GPU), outside the timed region
+        from paper_1804_01184_amd import autotune
+        t = time.perf_counter()
+        decomp = autotune.tune(grid, w.src_xz, w.rec_xz)
+        tuned = {"seconds": round(time.perf_counter() - t, 2)}
+    plan = api.Plan(grid, w.src_xz, w.rec_xz, ckpt_every=args.ckpt_every, **decomp)
     info = plan.info
     obs = plan.forward("vp-rho", w.vp_true, w.rho_true, f)
     K0, r0 = api.model_convert("vp-rho", "k-rho", vp0, rho0)
@@ -207,19 +225,21 @@ def main():
     ab = algorithmic_bytes(info, S)
     roof = None
     if not args.no_kernel_timing:
-        dom = max(("fwd_step", "adj_step"), key=lambda k: per_class[k][1])
+        dom = max(("fwd_step", "adj_step", "fwd_pair"), key=lambda k: per_class[k][1])
         n_launch, dom_ms = per_class[dom]
         avg_s = dom_ms / n_launch * 1e-3
         achieved = ab[dom] / avg_s / 1e9
-        decomp = {"band_rows": info["band_rows"], "shots_per_group": info["shots_per_group"],
-                  "lane_cols": info["lane_cols"], "workload": w.name}
+        pre = "two_step_" if dom == "fwd_pair" else ""
+        kdec = {"band_rows": info[pre + "band_rows"],
+                "shots_per_group": info[pre + "shots_per_group"],
+                "lane_cols": info[pre + "lane_cols"], "workload": w.name}
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                 "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(achieved / PEAK_HBM_GBS, 4),
-                "traffic": measured_traffic(dom, decomp),
+                "traffic": measured_traffic(dom, kdec),
                 "avg_launch_us": round(avg_s * 1e6, 2), "launches": n_launch,
                 "bytes_per_launch": int(ab[dom]),
-                "bytes_per_cell_step": round(ab["per_cell_" + dom.split("_")[0]], 2)}
+                "bytes_per_cell_step": round(ab["per_cell_" + dom], 2)}
     classes = {k: {"launches": v[0], "ms": round(v[1], 3)} for k, v in per_class.items()
                if v[0]}
 
@@ -229,9 +249,7 @@ def main():
     if not args.no_plain and info["segments"] == 1:
         import math
         kc = int(math.ceil(math.sqrt(w.nt)))
-        pc = api.Plan(grid, w.src_xz, w.rec_xz, band_rows=args.band_rows,
-                      shots_per_group=args.shots_per_group, lane_cols=args.lane_cols,
-                      ckpt_every=kc)
+        pc = api.Plan(grid, w.src_xz, w.rec_xz, ckpt_every=kc, **decomp)
         pc.gradient("k-rho", K0, r0, f, obs)          # warm
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -259,7 +277,7 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        nt_s = args.cpu_steps or max(50, min(w.nt, int(1.0e8 / (info["Nz"] * info["Nx"]))))
+        nt_s = args.cpu_steps or max(50, min(w.nt, int(3.0e8 / (info["Nz"] * info["Nx"]))))
         cpu = cpu_baseline(w, nt_s)
         cpu["value"] = round(cpu["value"], 5)
         cpu["seconds"] = round(cpu["seconds"], 2)
@@ -275,7 +293,12 @@ def main():
                                f"chain-ruled to Vp-rho, Ip-rho, Vp-Ip",
                    "cell_steps": cells, "band_rows": info["band_rows"],
                    "shots_per_group": info["shots_per_group"], "lane_cols": info["lane_cols"],
-                   "shot_groups": G,
+                   "shot_groups": G, "two_step": info["two_step"],
+                   "two_step_band_rows": info["two_step_band_rows"],
+                   "two_step_shots_per_group": info["two_step_shots_per_group"],
+                   "two_step_lane_cols": info["two_step_lane_cols"],
+                   "decomposition": "autotuned" if tuned else "given" if any(
+                       v for k, v in decomp.items() if k != "two_step") else "default",
                    "ckpt_every": info["ckpt_every"], "segments": info["segments"]},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
                        "p99": round(float(np.percentile(lat, 99)), 3)},

@@ -18,7 +18,11 @@ def test_tune_and_cache(tmp_path, monkeypatch):
     g = api.Grid.of(w)
     best = autotune.tune(g, w.src_xz, w.rec_xz)
     Nz, Nx = g.padded
-    assert best in autotune.candidates(Nz, Nx, w.nshots)
+    assert (best["band_rows"], best["shots_per_group"], best["lane_cols"]) in \
+        autotune.candidates(Nz, Nx, w.nshots)
+    if best["two_step"] == 2:
+        assert (best["two_step_band_rows"], best["two_step_shots_per_group"],
+                best["two_step_lane_cols"]) in autotune.candidates2(Nz, Nx, w.nshots)
     assert (tmp_path / "tune.json").exists()
     assert autotune.tune(g, w.src_xz, w.rec_xz) == best
     f = w.wavelet()

@@ -16,6 +16,13 @@ def test_candidates_cover_rows_shot_groups_and_lane_widths():
         assert 512 <= waves <= 65536
     small = autotune.candidates(21, 21, 1)
     assert small and all(spg in (1, 2) for _, spg, _ in small)
+    assert [autotune.strip_cols(c, 2) for c in (1, 2, 4)] == [52, 116, 240]
+    c2 = autotune.candidates2(481, 481, 40)
+    assert {(spg, cols) for _, spg, cols in c2} == set(autotune.PAIRS2)
+    for H, spg, cols in c2:
+        assert H >= 16
+        waves = -(-481 // autotune.strip_cols(cols, 2)) * -(-481 // H) * -(-40 // spg)
+        assert 512 <= waves <= 65536
 
 
 def test_workloads_seeded_and_shaped():
