@@ -1,10 +1,11 @@
 """torch.autograd.Function over the HIP forward / adjoint pair.
 
-forward: fwi_forward_keep — modelled traces; the checkpoints (every k steps),
-the last segment's pressure history and the prepared model stay in a
+forward: fwi_forward_keep — modelled traces; what the backward needs (the
+whole pressure history when it fits the plan's budget, else checkpoints every
+k steps and the last segment's history) and the prepared model stay in a
 workspace held by the autograd context.  backward: fwi_adjoint_kept with the
-incoming gradient of the traces as adjoint source — segments are recomputed
-from their checkpoints, so memory is O(sqrt(nt) N) instead of O(nt N).
+incoming gradient of the traces as adjoint source — a checkpointed plan
+recomputes its segments, so memory is O(sqrt(nt) N) instead of O(nt N).
 
 Any loss written in torch on the traces differentiates through to the model
 parameters of the chosen parameterization (Table 1 of the paper).
