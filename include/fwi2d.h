@@ -221,6 +221,25 @@ fwi_status fwi_chain_rule(int32_t param, int64_t n, const float *m1, const float
  * g_xi = m0 * g, elementwise, in place on g (n cells). */
 fwi_status fwi_contrast_scale(int64_t n, const float *m0, float *g, void *stream);
 
+/* Steepest descent (the minimisation the paper uses, section "Modelling and
+ * Inversion") in the contrasts xi = (m - m0)/m0 of Table 1, for one
+ * parameter of n cells, all device arrays:
+ *   fwi_descent_direction: d = -dJ/dxi = -m0 g, and 0 where mask = 0
+ *     (mask may be NULL: every cell; a 0/1 mask restricts the update to a
+ *     known scatterer support).  d may alias g.
+ *   fwi_descent_apply: out = m + alpha m0 d, the model at contrast
+ *     xi + alpha d (out may alias m).  FWI_ENONFINITE if alpha is not finite.
+ *   fwi_descent_norms: out[0] = sum a^2 + sum b^2 and out[1] = the largest
+ *     |a|, |b| (b may be NULL; out is 2 device floats) in FP32, in a fixed
+ *     order (bitwise repeatable); n may be 0.
+ * FWI_EINVAL for a negative n or a NULL required array. */
+fwi_status fwi_descent_direction(int64_t n, const float *m0, const float *g, const float *mask,
+                                 float *d, void *stream);
+fwi_status fwi_descent_apply(int64_t n, const float *m, const float *m0, const float *d,
+                             float alpha, float *out, void *stream);
+fwi_status fwi_descent_norms(int64_t n, const float *a, const float *b, float *out,
+                             void *stream);
+
 /* Kernel classes of the per-launch timing below. */
 typedef enum {
     FWI_KC_FWD_STEP = 0,   /* batched forward step (all shots)                 */

@@ -24,7 +24,8 @@ FWI_OP_FORWARD, FWI_OP_MISFIT, FWI_OP_GRADIENT = 0, 1, 2
 SYMBOLS = ["fwi_plan_create", "fwi_plan_destroy", "fwi_plan_get_info", "fwi_workspace_bytes",
            "fwi_forward", "fwi_misfit", "fwi_gradient", "fwi_adjoint", "fwi_forward_keep",
            "fwi_adjoint_kept", "fwi_model_convert",
-           "fwi_chain_rule", "fwi_contrast_scale", "fwi_timing_enable", "fwi_timing_read",
+           "fwi_chain_rule", "fwi_contrast_scale", "fwi_descent_direction", "fwi_descent_apply",
+           "fwi_descent_norms", "fwi_timing_enable", "fwi_timing_read",
            "fwi_sync", "fwi_status_str", "fwi_last_error"]
 
 KERNEL_CLASSES = ["fwd_step", "adj_step", "plain_vel", "plain_pres", "plain_adj_a",
@@ -118,6 +119,12 @@ def lib():
     L.fwi_chain_rule.restype = st
     L.fwi_contrast_scale.argtypes = [i64, fp, fp, vp]
     L.fwi_contrast_scale.restype = st
+    L.fwi_descent_direction.argtypes = [i64, fp, fp, fp, fp, vp]
+    L.fwi_descent_direction.restype = st
+    L.fwi_descent_apply.argtypes = [i64, fp, fp, fp, ctypes.c_float, fp, vp]
+    L.fwi_descent_apply.restype = st
+    L.fwi_descent_norms.argtypes = [i64, fp, fp, fp, vp]
+    L.fwi_descent_norms.restype = st
     L.fwi_timing_enable.argtypes = [vp, i32]
     L.fwi_timing_enable.restype = st
     L.fwi_timing_read.argtypes = [vp, ctypes.POINTER(FwiTiming), i32]

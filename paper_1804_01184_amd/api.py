@@ -247,5 +247,34 @@ def contrast_scale(m0, g, stream=None):
     return g
 
 
+def descent_direction(m0, g, mask=None, out=None, stream=None):
+    """d = -m0 g (0 where mask == 0): steepest-descent direction in the
+    contrast (m - m0)/m0."""
+    m0, g = m0.contiguous(), g.contiguous()
+    d = torch.empty_like(g) if out is None else out
+    mk = mask.contiguous() if mask is not None else None
+    L.check(L.lib().fwi_descent_direction(g.numel(), _ptr(m0), _ptr(g), _ptr(mk), _ptr(d),
+                                          _stream(stream)))
+    return d
+
+
+def descent_apply(m, m0, d, alpha, out=None, stream=None):
+    """out = m + alpha m0 d: the model at contrast xi + alpha d."""
+    m, m0, d = m.contiguous(), m0.contiguous(), d.contiguous()
+    o = torch.empty_like(m) if out is None else out
+    L.check(L.lib().fwi_descent_apply(m.numel(), _ptr(m), _ptr(m0), _ptr(d), float(alpha),
+                                      _ptr(o), _stream(stream)))
+    return o
+
+
+def descent_norms(a, b=None, out=None, stream=None):
+    """Device tensor [sum a^2 + sum b^2, max |a|, |b|] (fixed order)."""
+    a = a.contiguous()
+    bb = b.contiguous() if b is not None else None
+    o = torch.empty(2, dtype=torch.float32, device=a.device) if out is None else out
+    L.check(L.lib().fwi_descent_norms(a.numel(), _ptr(a), _ptr(bb), _ptr(o), _stream(stream)))
+    return o
+
+
 def sync(stream=None):
     L.check(L.lib().fwi_sync(_stream(stream)))

@@ -1187,6 +1187,38 @@ fwi_status fwi_contrast_scale(int64_t n, const float *m0, float *g, void *stream
     return launched("contrast_scale");
 }
 
+fwi_status fwi_descent_direction(int64_t n, const float *m0, const float *g, const float *mask,
+                                 float *d, void *stream)
+{
+    if (n < 0 || (n > 0 && (!m0 || !g || !d)))
+        return fail(FWI_EINVAL, "bad size or NULL array");
+    if (n == 0)
+        return FWI_OK;
+    launch_descent_dir(n, m0, g, mask, d, (hipStream_t)stream);
+    return launched("descent_direction");
+}
+
+fwi_status fwi_descent_apply(int64_t n, const float *m, const float *m0, const float *d,
+                             float alpha, float *out, void *stream)
+{
+    if (n < 0 || (n > 0 && (!m || !m0 || !d || !out)))
+        return fail(FWI_EINVAL, "bad size or NULL array");
+    if (!std::isfinite(alpha))
+        return fail(FWI_ENONFINITE, "step length is not finite");
+    if (n == 0)
+        return FWI_OK;
+    launch_descent_apply(n, m, m0, d, alpha, out, (hipStream_t)stream);
+    return launched("descent_apply");
+}
+
+fwi_status fwi_descent_norms(int64_t n, const float *a, const float *b, float *out, void *stream)
+{
+    if (n < 0 || !out || (n > 0 && !a))
+        return fail(FWI_EINVAL, "bad size or NULL array");
+    launch_norms2(n, a, b, out, (hipStream_t)stream);
+    return launched("descent_norms");
+}
+
 fwi_status fwi_timing_enable(fwi_plan *p, int32_t enable)
 {
     if (!p)

@@ -121,6 +121,14 @@ void launch_chain_rule(int param, long long n, const float *m1, const float *m2,
                        const float *gK, const float *grho, float *g1, float *g2,
                        hipStream_t st);
 void launch_contrast_scale(long long n, const float *m0, float *g, hipStream_t st);
+// Steepest descent in the contrasts: d = -m0 g (0 where mask = 0; mask may
+// be null), out = m + alpha m0 d, out[0] = sum a^2 + sum b^2 and
+// out[1] = max |a|, |b| (b may be null).
+void launch_descent_dir(long long n, const float *m0, const float *g, const float *mask,
+                        float *d, hipStream_t st);
+void launch_descent_apply(long long n, const float *m, const float *m0, const float *d,
+                          float alpha, float *out, hipStream_t st);
+void launch_norms2(long long n, const float *a, const float *b, float *out, hipStream_t st);
 
 // ----------------------------------------------------------------- plain
 // One shot per launch.  Output arrays may alias the inputs.

@@ -417,6 +417,57 @@ __global__ void k_contrast_scale(long long n, const float *m0, float *g)
         g[c] *= m0[c];
 }
 
+// Steepest-descent direction in the contrast xi = (m - m0)/m0 of Table 1:
+// d = -dJ/dxi = -m0 g, zero where mask = 0 (a known scatterer support).
+__global__ void k_descent_dir(long long n, const float *m0, const float *g, const float *mask,
+                              float *d)
+{
+    long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n)
+        return;
+    const float v = -(m0[c] * g[c]);
+    d[c] = mask && mask[c] == 0.0f ? 0.0f : v;
+}
+
+// The model at contrast xi + alpha d: out = m + alpha m0 d.
+__global__ void k_descent_apply(long long n, const float *m, const float *m0, const float *d,
+                                float alpha, float *out)
+{
+    long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < n)
+        out[c] = m[c] + alpha * (m0[c] * d[c]);
+}
+
+// out[0] = sum a^2 + sum b^2, out[1] = max |a|, |b| in one workgroup:
+// per-thread strided passes in a fixed order, then a fixed tree (the same
+// bits on every call).
+__global__ void __launch_bounds__(kBlock) k_norms2(long long n, const float *a, const float *b,
+                                                   float *out)
+{
+    __shared__ float part[kBlock], top[kBlock];
+    float acc = 0.0f, mx = 0.0f;
+    for (long long c = threadIdx.x; c < n; c += kBlock) {
+        const float x = a[c], y = b ? b[c] : 0.0f;
+        acc += x * x;
+        acc += y * y;
+        mx = fmaxf(mx, fmaxf(fabsf(x), fabsf(y)));
+    }
+    part[threadIdx.x] = acc;
+    top[threadIdx.x] = mx;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            part[threadIdx.x] += part[threadIdx.x + w];
+            top[threadIdx.x] = fmaxf(top[threadIdx.x], top[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = part[0];
+        out[1] = top[0];
+    }
+}
+
 }  // namespace
 
 void launch_fill(float *p, long long n, float v, hipStream_t st)
@@ -531,6 +582,25 @@ void launch_chain_rule(int param, long long n, const float *m1, const float *m2,
 void launch_contrast_scale(long long n, const float *m0, float *g, hipStream_t st)
 {
     hipLaunchKernelGGL(k_contrast_scale, dim3(blocks_for(n)), dim3(kBlock), 0, st, n, m0, g);
+}
+
+void launch_descent_dir(long long n, const float *m0, const float *g, const float *mask,
+                        float *d, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_descent_dir, dim3(blocks_for(n)), dim3(kBlock), 0, st, n, m0, g, mask,
+                       d);
+}
+
+void launch_descent_apply(long long n, const float *m, const float *m0, const float *d,
+                          float alpha, float *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_descent_apply, dim3(blocks_for(n)), dim3(kBlock), 0, st, n, m, m0, d,
+                       alpha, out);
+}
+
+void launch_norms2(long long n, const float *a, const float *b, float *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_norms2, dim3(1), dim3(kBlock), 0, st, n, a, b, out);
 }
 
 }  // namespace fwi

@@ -1,0 +1,198 @@
+"""Steepest-descent FWI in the contrasts of Table 1 (the minimisation the
+paper uses for its parameterization comparison, section "Modelling and
+Inversion"; convergence compared per parameterization in Table 5).
+
+The unknowns are the contrasts xi = (m - m0)/m0 of the two parameters of the
+chosen parameterization relative to the starting model m0, so the descent
+direction is d = -dJ/dxi = -m0 dJ/dm (Table 1), optionally restricted by a
+0/1 mask to a known scatterer support (the "shape known" cases of the
+scatterer table).  The paper does not state its step-length rule; the one
+used here is a parabolic line search:
+
+1. J0 and the gradient at the current model (one gradient call);
+2. slope s = <dJ/dxi, d> = -|d|^2;
+3. trial step a1: the previous accepted step, or at the first iteration
+   tau / max|d| (a largest contrast change of tau; the gradient of an
+   unknown-shape problem peaks near the sources and receivers, where a step
+   sized by a mean would leave the scheme's stability range);
+4. J1 = J(a1) (one forward and misfit; a non-finite misfit counts as
+   +infinity); curvature c = (J1 - J0 - s a1)/a1^2;
+5. a2 = -s / (2c) if c > 0, else grow * a1 (a1 / grow if J1 is infinite);
+   a2 <= max_ratio * a1; J2 = J(a2) (one more forward);
+6. the step is whichever of a1, a2 gives the lower misfit (a1 on a tie);
+   if neither lowers J0, the smaller of the two is halved up to
+   `backtracks` times until one does; if none does, the iteration stops.
+
+Every array operation runs in the library's kernels (gradient, forward,
+misfit, fwi_descent_direction / fwi_descent_apply / fwi_descent_norms); the
+step-length arithmetic on the handful of scalars runs on the host in FP64.
+
+``python -m paper_1804_01184_amd.inversion`` runs the loop on config 1
+(point velocity-only scatterer, shape known) and config 2 (Gaussian
+velocity-only scatterer, shape unknown) in all five parameterizations and
+prints one JSON line: misfit per iteration and the loop's throughput.
+"""
+from __future__ import annotations
+
+import json
+import math
+import sys
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import api
+
+PARAMS = ("vp-rho", "ip-rho", "vp-ip", "k-rho", "invk-invrho")
+LETTER = {"vp-rho": "A", "ip-rho": "B", "vp-ip": "C", "k-rho": "D", "invk-invrho": "E"}
+
+
+@dataclass
+class DescentResult:
+    J: list = field(default_factory=list)       # misfit at iterates 0, 1, ...
+    alpha: list = field(default_factory=list)   # accepted step of each iteration
+    forwards: int = 0                           # line-search forward evaluations
+    gradients: int = 0
+    m1: torch.Tensor = None
+    m2: torch.Tensor = None
+    stopped: bool = False                       # no step lowered the misfit
+
+
+def steepest_descent(plan, param, m1, m2, wavelet, observed, iters, mask=None, tau=0.01,
+                     grow=4.0, max_ratio=10.0, backtracks=5):
+    """Runs `iters` iterations from the model (m1, m2) (which also defines
+    the contrasts); returns a DescentResult with the final model."""
+    dev = plan.device
+    m0a = api._dev_f32(m1, dev).clone()
+    m0b = api._dev_f32(m2, dev).clone()
+    w = api._dev_f32(wavelet, dev)
+    obs = api._dev_f32(observed, dev)
+    mk = api._dev_f32(mask, dev) if mask is not None else None
+    ma, mb = m0a.clone(), m0b.clone()
+    ta, tb = torch.empty_like(ma), torch.empty_like(mb)
+    res = DescentResult()
+
+    def value(a, da, db):
+        api.descent_apply(ma, m0a, da, a, out=ta)
+        api.descent_apply(mb, m0b, db, a, out=tb)
+        tr = plan.forward(param, ta, tb, w)
+        J, _ = plan.misfit(tr, obs, residual=False)
+        res.forwards += 1
+        v = float(J.item())
+        return v if math.isfinite(v) else math.inf
+
+    trial = None
+    for _ in range(iters):
+        Jk, ga, gb = plan.gradient(param, ma, mb, w, obs)
+        res.gradients += 1
+        J0 = float(Jk.item())
+        if not res.J:
+            res.J.append(J0)
+        da = api.descent_direction(m0a, ga, mk, out=ga)
+        db = api.descent_direction(m0b, gb, mk, out=gb)
+        ss, dmax = (float(x) for x in api.descent_norms(da, db).cpu())
+        if not ss > 0.0:
+            res.stopped = True
+            break
+        slope = -ss
+        a1 = trial if trial is not None else tau / dmax
+        J1 = value(a1, da, db)
+        if math.isinf(J1):
+            a2 = a1 / grow
+        else:
+            c = (J1 - J0 - slope * a1) / (a1 * a1)
+            a2 = -slope / (2.0 * c) if c > 0.0 else grow * a1
+            a2 = min(a2, max_ratio * a1)
+        J2 = value(a2, da, db)
+        a, Ja = (a1, J1) if J1 <= J2 else (a2, J2)
+        if not Ja < J0:
+            a = min(a1, a2)
+            for _ in range(backtracks):
+                a *= 0.5
+                Ja = value(a, da, db)
+                if Ja < J0:
+                    break
+            else:
+                res.stopped = True
+                break
+        api.descent_apply(ma, m0a, da, a, out=ma)
+        api.descent_apply(mb, m0b, db, a, out=mb)
+        res.alpha.append(a)
+        res.J.append(Ja)
+        trial = a
+    res.m1, res.m2 = ma, mb
+    return res
+
+
+# ------------------------------------------------------------ measurement
+
+def _problem(w, dev):
+    g = api.Grid.of(w)
+    f = torch.tensor(w.wavelet(), dtype=torch.float32, device=dev)
+    return g, f
+
+
+def _run(w, iters, mask_cells=None, dev=None):
+    g, f = _problem(w, dev)
+    plan = api.Plan(g, w.src_xz, w.rec_xz, device=dev)
+    Kt = torch.tensor(w.rho_true * w.vp_true ** 2, dtype=torch.float32, device=dev)
+    rt = torch.tensor(w.rho_true, dtype=torch.float32, device=dev)
+    obs = plan.forward("k-rho", Kt, rt, f)
+    K0 = torch.tensor(w.rho_start * w.vp_start ** 2, dtype=torch.float32, device=dev)
+    r0 = torch.tensor(w.rho_start, dtype=torch.float32, device=dev)
+    mask = None
+    if mask_cells is not None:
+        mask = torch.zeros(w.nz, w.nx, dtype=torch.float32, device=dev)
+        for i, j in mask_cells:
+            mask[i, j] = 1.0
+    out = {}
+    cells = w.cell_steps()
+    for p in PARAMS:
+        m1, m2 = api.model_convert("k-rho", p, K0, r0)
+        t1, t2 = api.model_convert("k-rho", p, Kt, rt)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = steepest_descent(plan, p, m1, m2, f, obs, iters, mask=mask)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        passes = r.gradients + r.forwards
+        rec = {"J": [float(x) for x in r.J], "alpha": [float(a) for a in r.alpha],
+               "J_final_over_J0": float(r.J[-1] / r.J[0]), "gradients": r.gradients,
+               "forwards": r.forwards, "seconds": round(dt, 3),
+               "gcell_per_s": round(cells * passes / dt / 1e9, 2), "stopped": r.stopped}
+        if mask_cells is not None:
+            i, j = mask_cells[0]
+            xa = float((r.m1[i, j] / m1[i, j] - 1.0).item())
+            xb = float((r.m2[i, j] / m2[i, j] - 1.0).item())
+            ta = float((t1[i, j] / m1[i, j] - 1.0).item())
+            tb = float((t2[i, j] / m2[i, j] - 1.0).item())
+            rec["contrast"] = [xa, xb]
+            rec["true_contrast"] = [ta, tb]
+        out[f"({LETTER[p]}) {p}"] = rec
+    return out
+
+
+def main(argv=None):
+    import argparse
+    from . import workloads as W
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--iters-c1", type=int, default=15)
+    ap.add_argument("--iters-c2", type=int, default=4)
+    ap.add_argument("--no-c2", action="store_true")
+    a = ap.parse_args(argv)
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    rec = {"loop": "steepest descent in the contrasts, parabolic line search"}
+    w1 = W.config1()
+    ci, cj = np.argwhere(w1.rho_true * w1.vp_true ** 2 != w1.rho_start * w1.vp_start ** 2)[0]
+    rec["c1_point_vp_only_shape_known"] = _run(w1, a.iters_c1, mask_cells=[(int(ci), int(cj))],
+                                               dev=dev)
+    if not a.no_c2:
+        rec["c2_gaussian_vp_only_shape_unknown"] = _run(W.config2(), a.iters_c2, dev=dev)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])

@@ -94,3 +94,15 @@ def test_null_calls_rejected():
     assert lib.fwi_chain_rule(9, 10, None, None, None, None, None, None, None) == -1
     assert lib.fwi_model_convert(0, 1, -1, None, None, None, None, None) == -1
     assert lib.fwi_contrast_scale(0, None, None, None) == 0
+
+
+def test_descent_helpers_validate_before_touching_the_device():
+    lib = L.lib()
+    p = ctypes.c_void_p(16)   # never dereferenced: validation fails first
+    assert lib.fwi_descent_direction(-1, p, p, None, p, None) == -1
+    assert lib.fwi_descent_direction(8, None, p, None, p, None) == -1
+    assert lib.fwi_descent_apply(8, p, p, None, ctypes.c_float(0.5), p, None) == -1
+    assert lib.fwi_descent_apply(0, p, p, p, ctypes.c_float(float("inf")), p,
+                                 None) == -5
+    assert lib.fwi_descent_norms(-2, p, None, p, None) == -1
+    assert lib.fwi_descent_norms(4, p, None, None, None) == -1
