@@ -982,9 +982,13 @@ fwi_status fwi_plan_create(const fwi_grid *grid, const fwi_acq *acq, const fwi_e
     st_host.src_ij = p->src_ij;
     st_host.src_w = p->src_w;
     st_host.nt = G.nt;
-    bool ok = true;
+    // uploads and the table kernel run on a private stream, and only that
+    // stream is waited for: work other streams have in flight (a server
+    // creating plans while earlier requests run) is not drained
+    hipStream_t ps = nullptr;
+    bool ok = hipStreamCreateWithFlags(&ps, hipStreamNonBlocking) == hipSuccess;
     auto up = [&](void *dst, const void *src, size_t bytes) {
-        if (bytes && hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) != hipSuccess)
+        if (ok && bytes && hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, ps) != hipSuccess)
             ok = false;
     };
     up(p->src_ij, p->h_src_ij.data(), sizeof(int2) * S);
@@ -997,8 +1001,14 @@ fwi_status fwi_plan_create(const fwi_grid *grid, const fwi_acq *acq, const fwi_e
     up(p->inj_crec, inj_crec.data(), sizeof(int) * inj_crec.size());
     up(p->inj_cw, inj_cw.data(), sizeof(float) * inj_cw.size());
     up(p->sweep_tabs, &st_host, sizeof(SweepTables));
-    launch_pml_tables(g, G.vmax, G.npml > 0 ? G.pml_r : 0.5, G.dx, G.dz, G.dt, p->pml, nullptr);
-    if (!ok || hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+    if (ok)
+        launch_pml_tables(g, G.vmax, G.npml > 0 ? G.pml_r : 0.5, G.dx, G.dz, G.dt, p->pml, ps);
+    if (ok && (hipGetLastError() != hipSuccess || hipStreamSynchronize(ps) != hipSuccess))
+        ok = false;
+    if (ps)
+        (void)hipStreamDestroy(ps);
+    if (!ok) {
+        (void)hipGetLastError();
         (void)hipFree(p->dev);
         delete p;
         return fail(FWI_EDEVICE, "uploading plan tables failed");

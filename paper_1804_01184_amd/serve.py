@@ -10,11 +10,21 @@ while others run are admitted as slots and memory free up.  Each result is
 computed by the same deterministic kernels whatever else runs, so it is the
 same alone and in the mix.
 
+A request keeps its whole pressure history when that fits one slot's share
+of the budget, else the plan checkpoints every ceil(sqrt(nt)) steps, so one
+large request does not hold the memory the others need to run alongside.
+
 Reports per-request latency (completion - arrival), p50/p99, and aggregate
-Gcell-updates/s over the makespan.
+Gcell-updates/s over the makespan.  ``python -m paper_1804_01184_amd.serve``
+serves a seeded Poisson stream of config-4 requests and prints one JSON
+line.
 """
 from __future__ import annotations
 
+import json
+import math
+import sys
+import threading
 import time
 from collections import deque
 from dataclasses import dataclass, field
@@ -69,6 +79,11 @@ class _Job:
         self.event = torch.cuda.Event()
         self.bufs = None
         self.admitted = None
+        self.thread = None
+        self.error = None
+
+    def submitted(self):
+        return self.thread is not None and not self.thread.is_alive()
 
 
 def footprint(plan: Plan, req: Request):
@@ -81,7 +96,10 @@ def footprint(plan: Plan, req: Request):
 
 class GradientServer:
     def __init__(self, max_slots=4, hbm_budget=None, device=None, plan_kw=None):
-        self.device = torch.device(device if device is not None else "cuda")
+        dev = torch.device(device if device is not None else "cuda")
+        if dev.index is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
         total = torch.cuda.get_device_properties(self.device).total_memory
         self.budget = int(hbm_budget if hbm_budget is not None else 0.7 * total)
         self.max_slots = max_slots
@@ -89,20 +107,46 @@ class GradientServer:
         self.plan_kw = plan_kw or {}
         self.log = []
 
+    def plan_for(self, q):
+        """The request's plan: whole history if it fits a slot's share of
+        the budget, else sqrt(nt) checkpoints (unless plan_kw fixes it)."""
+        plan = Plan(q.grid, q.src_xz, q.rec_xz, device=self.device, **self.plan_kw)
+        if "ckpt_every" not in self.plan_kw and \
+                footprint(plan, q) > self.budget / self.max_slots:
+            k = int(math.ceil(math.sqrt(q.grid.nt)))
+            plan = Plan(q.grid, q.src_xz, q.rec_xz, device=self.device, ckpt_every=k,
+                        **self.plan_kw)
+        return plan
+
     def _start(self, job, now):
+        # a gradient enqueues thousands of launches and the enqueue blocks
+        # once the device queue is full, so each job is submitted from a
+        # thread of its own (the library calls release the GIL): the serving
+        # loop keeps admitting and retiring meanwhile
         r = job.req
         dev = self.device
-        with torch.cuda.stream(job.stream):
-            m1 = torch.as_tensor(r.m1, dtype=torch.float32).to(dev, non_blocking=True)
-            m2 = torch.as_tensor(r.m2, dtype=torch.float32).to(dev, non_blocking=True)
-            f = torch.as_tensor(r.wavelet, dtype=torch.float32).to(dev, non_blocking=True)
-            obs = r.observed.to(dev, non_blocking=True)
-            J = torch.empty(1, dtype=torch.float32, device=dev)
-            g1, g2 = torch.empty_like(m1), torch.empty_like(m1)
-            job.plan.gradient(r.param, m1, m2, f, obs, stream=job.stream, out=(J, g1, g2))
-            job.event.record(job.stream)
-        job.bufs = (m1, m2, f, obs, J, g1, g2)
+
+        def submit():
+            try:
+                torch.cuda.set_device(dev)
+                with torch.cuda.stream(job.stream):
+                    m1 = torch.as_tensor(r.m1, dtype=torch.float32).to(dev, non_blocking=True)
+                    m2 = torch.as_tensor(r.m2, dtype=torch.float32).to(dev, non_blocking=True)
+                    f = torch.as_tensor(r.wavelet, dtype=torch.float32).to(dev,
+                                                                           non_blocking=True)
+                    obs = r.observed.to(dev, non_blocking=True)
+                    J = torch.empty(1, dtype=torch.float32, device=dev)
+                    g1, g2 = torch.empty_like(m1), torch.empty_like(m1)
+                    job.plan.gradient(r.param, m1, m2, f, obs, stream=job.stream,
+                                      out=(J, g1, g2))
+                    job.event.record(job.stream)
+                job.bufs = (m1, m2, f, obs, J, g1, g2)
+            except BaseException as e:   # re-raised by the serving loop
+                job.error = e
+
         job.admitted = now
+        job.thread = threading.Thread(target=submit, daemon=True)
+        job.thread.start()
 
     def run(self, requests, verbose=False):
         """Serves `requests` in real time (arrival = seconds after the call);
@@ -119,7 +163,7 @@ class GradientServer:
             now = time.perf_counter() - t0
             while pending and pending[0].arrival <= now:
                 q = pending.popleft()
-                plan = Plan(q.grid, q.src_xz, q.rec_xz, device=self.device, **self.plan_kw)
+                plan = self.plan_for(q)
                 fp = footprint(plan, q)
                 if fp > self.budget:
                     raise RuntimeError(f"request {q.id} needs {fp} bytes > budget {self.budget}")
@@ -138,7 +182,9 @@ class GradientServer:
                     running.append(job)
             progressed = False
             for job in list(running):
-                if job.event.query():
+                if job.submitted() and job.error is not None:
+                    raise job.error
+                if job.submitted() and job.event.query():
                     t_done = time.perf_counter() - t0
                     m1, m2, f, obs, J, g1, g2 = job.bufs
                     res = Result(job.req.id, job.req.arrival, job.admitted, t_done,
@@ -195,3 +241,63 @@ def make_requests(specs, device=None, param="vp-rho", nrec=360, npml=40):
         out.append(Request(s["id"], s["arrival"], g, w.src_xz, w.rec_xz, param, m1, m2, f,
                            obs_h, meta=s))
     return out
+
+
+def main(argv=None):
+    """Serves a seeded Poisson stream of config-4 gradient requests (sides
+    201..1201 + 40 PML, 8-64 shots, 1000-4000 steps) and prints one JSON
+    line: latency percentiles, aggregate rate, and the same requests run one
+    after another for comparison."""
+    import argparse
+    from . import workloads as W
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--requests", type=int, default=24)
+    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--load", type=float, default=0.8,
+                    help="offered load as a fraction of the measured serial capacity")
+    a = ap.parse_args(argv)
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    specs = W.serving_requests(a.requests, rate_hz=1.0)
+    print(f"preparing {len(specs)} requests", file=sys.stderr, flush=True)
+    reqs = make_requests(specs, device=dev)
+    server = GradientServer(max_slots=a.slots, device=dev)
+    # serial pass: each request alone, back to back (its service time)
+    service = {}
+    for q in reqs:
+        plan = server.plan_for(q)
+        m1 = torch.as_tensor(q.m1, dtype=torch.float32, device=dev)
+        m2 = torch.as_tensor(q.m2, dtype=torch.float32, device=dev)
+        f = torch.as_tensor(q.wavelet, dtype=torch.float32, device=dev)
+        obs = q.observed.to(dev)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        plan.gradient(q.param, m1, m2, f, obs)
+        torch.cuda.synchronize()
+        service[q.id] = time.perf_counter() - t
+        del plan
+        print(f"  alone: request {q.id} {q.meta['n']}^2 x {q.meta['shots']} shots x "
+              f"{q.meta['nt']} steps: {service[q.id]:.3f} s", file=sys.stderr, flush=True)
+    mean_s = float(np.mean(list(service.values())))
+    cells = sum(q.cell_steps for q in reqs)
+    out = {"slots": a.slots, "mean_service_alone_s": mean_s,
+           "serial_gcells": cells / sum(service.values()) / 1e9,
+           "requests_spec": [{k: s[k] for k in ("n", "shots", "nt")} for s in specs]}
+    # Poisson arrivals rescaled so the offered load is a.load of the serial
+    # capacity; then a burst (every request at t = 0) for the capacity
+    for name, arrivals in (("poisson", [s["arrival"] * mean_s / a.load for s in specs]),
+                           ("burst", [0.0] * len(specs))):
+        for q, t in zip(reqs, arrivals):
+            q.arrival = t
+        res = server.run(reqs)
+        rec = summary(res, server.makespan)
+        if name == "poisson":
+            rec["offered_load"] = a.load
+        out[name] = rec
+        print(f"{name}: p50 {rec['p50_ms']:.0f} ms, p99 {rec['p99_ms']:.0f} ms, "
+              f"{rec['aggregate_gcells']:.1f} Gcell-updates/s", file=sys.stderr, flush=True)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])
