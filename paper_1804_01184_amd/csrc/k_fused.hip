@@ -140,6 +140,13 @@ __device__ inline void vst(rsrc_t r, unsigned voff, unsigned soff, const float (
 // by-value min / max (reference-returning overloads applied to kernel
 // arguments would force a private copy of the argument struct)
 __device__ inline int imin(int a, int b) { return a < b ? a : b; }
+
+// Read-only tables seen through the constant address space: a load at a
+// uniform index becomes a scalar load, which keeps the per-row table values
+// off the vector memory path (the kernels' stores would otherwise stop the
+// compiler from proving the tables unchanged inside the row loops).
+typedef const __attribute__((address_space(4))) float cfloat;
+__device__ inline cfloat *ctab(const float *p) { return (cfloat *)p; }
 __device__ inline int imax(int a, int b) { return a > b ? a : b; }
 __device__ inline int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
@@ -389,8 +396,8 @@ __global__ void __launch_bounds__(NTHR)
     XTab<C> xt;
     xtab<C>(g, tabs, w, xt);
     // z tables: alpha, beta at nodes, alpha_h, beta_h at half nodes
-    const float *__restrict__ zaz = tabs + 4 * g.Nx, *__restrict__ zbz = zaz + g.Nz;
-    const float *__restrict__ zahz = zbz + g.Nz, *__restrict__ zbhz = zahz + g.Nz;
+    cfloat *zaz = ctab(tabs + 4 * g.Nx), *zbz = zaz + g.Nz;
+    cfloat *zahz = zbz + g.Nz, *zbhz = zahz + g.Nz;
     const unsigned FB = 4u * (unsigned)g.N;
     const rsrc_t rM = res(model, 3u * FB);   // K, bx, bz at 0, FB, 2 FB
     const unsigned rowN = 4u * (unsigned)g.Nx;
@@ -576,8 +583,8 @@ __global__ void __launch_bounds__(NTHR)
         return;
     XTab<C> xt;
     xtab<C>(g, tabs, w, xt);
-    const float *__restrict__ zaz = tabs + 4 * g.Nx, *__restrict__ zbz = zaz + g.Nz;
-    const float *__restrict__ zahz = zbz + g.Nz, *__restrict__ zbhz = zahz + g.Nz;
+    cfloat *zaz = ctab(tabs + 4 * g.Nx), *zbz = zaz + g.Nz;
+    cfloat *zahz = zbz + g.Nz, *zbhz = zahz + g.Nz;
     const unsigned FB = 4u * (unsigned)g.N;
     const rsrc_t rM = res(model, 3u * FB);
     const unsigned rowN = 4u * (unsigned)g.Nx;
@@ -585,7 +592,7 @@ __global__ void __launch_bounds__(NTHR)
     const rsrc_t rPmid = grp_res(a.pmid, w.s0, SPG);
     const rsrc_t rPout = grp_res(a.pout, w.s0, SPG), rVout = grp_res(a.vout, w.s0, SPG);
     // z tables with zero outside the grid (step-one rows run past it)
-    auto zt = [&](const float *t, int r) -> float { return row_ok(g, r) ? t[r] : 0.f; };
+    auto zt = [&](cfloat *t, int r) -> float { return row_ok(g, r) ? t[r] : 0.f; };
     // row byte offset of row r plus `extra`, or 0 when row r is outside the
     // grid (its lane offset is then kOOB)
     auto rofs = [&](int r, unsigned extra) -> unsigned {
