@@ -23,8 +23,11 @@ import torch
 from . import _lib as L
 from .api import Grid, Plan
 
-ROWS = (8, 12, 16, 24, 32, 48, 64, 96, 128)
-ROWS2 = (16, 24, 32, 48, 64, 96)
+# band heights: every height from 8 to 16 (the kernels are bounded per CU,
+# so how evenly the workgroups of a height spread over the CUs matters as
+# much as the height), then coarser steps
+ROWS = (8, 9, 10, 11, 12, 13, 14, 15, 16, 20, 24, 32, 48, 64, 96, 128)
+ROWS2 = (12, 14, 16, 18, 20, 24, 28, 32, 48, 64, 96)
 # supported (shots per group, columns per lane) pairs of the one-step
 # kernels and of the two-step forward kernel
 PAIRS = ((1, 1), (2, 1), (4, 1), (8, 1), (1, 2), (2, 2), (4, 2), (1, 4), (2, 4))
@@ -47,7 +50,7 @@ def cache_path():
 
 
 def _key(Nz, Nx, S, npml, arch):
-    return f"{arch}:{Nz}x{Nx}:S{S}:pml{npml}:v3"
+    return f"{arch}:{Nz}x{Nx}:S{S}:pml{npml}:v4"
 
 
 def _arch():

@@ -20,7 +20,7 @@ def test_candidates_cover_rows_shot_groups_and_lane_widths():
     c2 = autotune.candidates2(481, 481, 40)
     assert {(spg, cols) for _, spg, cols in c2} == set(autotune.PAIRS2)
     for H, spg, cols in c2:
-        assert H >= 16
+        assert H >= 12
         waves = -(-481 // autotune.strip_cols(cols, 2)) * -(-481 // H) * -(-40 // spg)
         assert 512 <= waves <= 65536
 
