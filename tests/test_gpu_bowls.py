@@ -1,0 +1,59 @@
+"""Error bowls on the GPU against the FP64 oracle (config 1, point
+scatterer (i), a 3 x 3 grid of contrasts around the true ones, all five
+parameterizations).
+
+Tolerance: J is the square of a residual d(x) - d(x*) that is about
+|x - x*| (here 2.5 %) times the scatterer's share of the traces, so the
+1e-4 trace parity becomes about 1e-2 of the bowl's largest misfit; the
+fitted axis ratio and angle (what the paper reads off the bowls) are
+compared at 3 % and 2 degrees."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1804_01184_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1804_01184_amd import api, bowls
+    w = W.config1()
+    g = O.Grid(w.nz, w.nx, w.dz, w.dx, w.npml, w.nt, w.dt, w.vmax, w.pml_r)
+    f = w.wavelet()
+    Kt = w.rho_true * w.vp_true ** 2
+    obs = O.forward_krho(g, w.src_xz, w.rec_xz, Kt, w.rho_true, f)
+    return torch, api, bowls, w, g, f, obs
+
+
+@pytest.mark.parametrize("param", ["vp-rho", "ip-rho", "vp-ip", "k-rho", "invk-invrho"])
+def test_bowl_matches_oracle(env, param):
+    torch, api, bowls, w, g, f, obs = env
+    K0 = w.rho_start * w.vp_start ** 2
+    Kt = w.rho_true * w.vp_true ** 2
+    prof = (Kt != K0).astype(np.float64)
+    i0, j0 = np.argwhere(prof)[0]
+    m0a, m0b = O.krho_to_model(O.PARAMS[param], K0, w.rho_start)
+    ta, tb = O.krho_to_model(O.PARAMS[param], Kt, w.rho_true)
+    xt = (ta[i0, j0] / m0a[i0, j0] - 1.0, tb[i0, j0] / m0b[i0, j0] - 1.0)
+    half = 0.5 * max(abs(xt[0]), abs(xt[1]))
+    xa = np.linspace(xt[0] - half, xt[0] + half, 3)
+    xb = np.linspace(xt[1] - half, xt[1] + half, 3)
+    ref = np.empty((3, 3))
+    for i, a in enumerate(xa):
+        for j, b in enumerate(xb):
+            d = O.forward(g, O.PARAMS[param], m0a * (1 + a * prof), m0b * (1 + b * prof),
+                          w.src_xz, w.rec_xz, f)
+            ref[i, j] = O.misfit(d, obs)[0]
+    plan = api.Plan(api.Grid.of(w), w.src_xz, w.rec_xz)
+    got = bowls.bowl(plan, param, m0a, m0b, prof, f, obs.astype(np.float32), xa, xb)
+    assert np.abs(got - ref).max() <= 1e-2 * ref.max()
+    rg, ag = bowls.bowl_shape(bowls.fit_quadratic(xa, xb, got, xt)[0])
+    rr, ar = bowls.bowl_shape(bowls.fit_quadratic(xa, xb, ref, xt)[0])
+    assert rg == pytest.approx(rr, rel=3e-2)
+    dang = abs(ag - ar) % 180.0
+    assert min(dang, 180.0 - dang) <= 2.0

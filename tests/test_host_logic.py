@@ -1,6 +1,7 @@
 """Host-side logic that needs no GPU: autotuner candidate sets, workload
 generators (seeded, reproducible, shapes of the configurations)."""
 import numpy as np
+import pytest
 
 from paper_1804_01184_amd import workloads as W
 
@@ -49,3 +50,32 @@ def test_serving_request_stream_seeded():
     assert all(201 <= r["n"] <= 1201 and 8 <= r["shots"] <= 64 and 1000 <= r["nt"] <= 4000
                for r in r1)
     assert all(r1[k]["arrival"] < r1[k + 1]["arrival"] for k in range(49))
+
+
+def test_bowl_fit_recovers_quadratic_and_shape():
+    from paper_1804_01184_amd import bowls
+    rng = np.random.default_rng(4)
+    xa = np.linspace(-0.1, 0.3, 9)
+    xb = np.linspace(0.2, 0.5, 7)
+    H = np.array([[3.0, 1.2], [1.2, 2.0]])
+    g = np.array([0.4, -0.7])
+    c0 = 0.25
+    ctr = (0.1, 0.35)
+    A, B = np.meshgrid(xa - ctr[0], xb - ctr[1], indexing="ij")
+    J = c0 + g[0] * A + g[1] * B + 0.5 * (H[0, 0] * A * A + 2 * H[0, 1] * A * B + H[1, 1] * B * B)
+    Hf, gf, cf = bowls.fit_quadratic(xa, xb, J, ctr)
+    np.testing.assert_allclose(Hf, H, rtol=1e-9)
+    np.testing.assert_allclose(gf, g, rtol=1e-9, atol=1e-12)
+    assert cf == pytest.approx(c0, rel=1e-9)
+    # shapes: a circle; axes along the parameters; the long axis at 45 deg
+    assert bowls.bowl_shape(np.eye(2))[0] == pytest.approx(1.0)
+    r, ang = bowls.bowl_shape(np.diag([4.0, 1.0]))
+    assert r == pytest.approx(2.0) and ang == pytest.approx(90.0)
+    r, ang = bowls.bowl_shape(np.diag([1.0, 9.0]))
+    assert r == pytest.approx(3.0) and ang in (pytest.approx(0.0), pytest.approx(180.0))
+    t = np.radians(30.0)
+    R = np.array([[np.cos(t), -np.sin(t)], [np.sin(t), np.cos(t)]])
+    Hr = R @ np.diag([1.0, 16.0]) @ R.T        # small curvature along 30 deg
+    r, ang = bowls.bowl_shape(Hr)
+    assert r == pytest.approx(4.0) and ang == pytest.approx(30.0)
+    del rng
