@@ -174,6 +174,16 @@ fwi_status fwi_forward(fwi_plan *plan, int32_t param, const float *m1, const flo
 fwi_status fwi_misfit(fwi_plan *plan, const float *traces, const float *observed,
                       float *residual, float *J, void *ws, size_t ws_bytes, void *stream);
 
+/* The misfit restricted to a subset of the data, as in the limited-aperture
+ * regimes of section "Hierarchical Inversion": weights [S][nrec] (device,
+ * one per trace, e.g. 0/1 by scattering angle); residual = w (traces -
+ * observed) (may be NULL; it is the adjoint source of this misfit for
+ * fwi_adjoint), J[0] = 1/2 sum w (traces - observed)^2, fixed-order
+ * reduction.  Same workspace as fwi_misfit. */
+fwi_status fwi_misfit_weighted(fwi_plan *plan, const float *traces, const float *observed,
+                               const float *weights, float *residual, float *J, void *ws,
+                               size_t ws_bytes, void *stream);
+
 /* Misfit and gradient (scheme III): J[0] as fwi_misfit, and g1, g2 = dJ/dm1,
  * dJ/dm2 per cell (no cell-area factor) at (m1, m2) in parameterization
  * `param`.  traces may be NULL; if given it receives the modelled data. */

@@ -159,15 +159,23 @@ class Plan:
                                     _ptr(traces), _ptr(ws), ws.numel(), _stream(stream)))
         return traces
 
-    def misfit(self, traces, observed, residual=True, stream=None):
-        """(J [1], residual or None)."""
+    def misfit(self, traces, observed, residual=True, weights=None, stream=None):
+        """(J [1], residual or None); weights [S][nrec] restrict the misfit
+        to a subset of the traces (residual = w (traces - observed))."""
         traces = _dev_f32(traces, self.device)
         observed = _dev_f32(observed, self.device)
         r = torch.empty_like(traces) if residual else None
         J = torch.empty(1, dtype=torch.float32, device=self.device)
         ws = self.workspace(L.FWI_OP_MISFIT)
-        L.check(L.lib().fwi_misfit(self._h, _ptr(traces), _ptr(observed), _ptr(r), _ptr(J),
-                                   _ptr(ws), ws.numel(), _stream(stream)))
+        if weights is None:
+            L.check(L.lib().fwi_misfit(self._h, _ptr(traces), _ptr(observed), _ptr(r), _ptr(J),
+                                       _ptr(ws), ws.numel(), _stream(stream)))
+        else:
+            w = _dev_f32(weights, self.device)
+            assert w.numel() == self.nshots * self.nrec
+            L.check(L.lib().fwi_misfit_weighted(self._h, _ptr(traces), _ptr(observed), _ptr(w),
+                                                _ptr(r), _ptr(J), _ptr(ws), ws.numel(),
+                                                _stream(stream)))
         return J, r
 
     def gradient(self, param, m1, m2, wavelet, observed, want_traces=False, stream=None,

@@ -20,7 +20,6 @@ import time
 import numpy as np
 import torch
 
-from . import _lib as L
 from .api import Grid, Plan
 
 # band heights: every height from 8 to 16 (the kernels are bounded per CU,
@@ -199,4 +198,4 @@ def tuned_plan(grid: Grid, src_xz, rec_xz, **kw):
     return Plan(grid, src_xz, rec_xz, **{**best, **kw})
 
 
-__all__ = ["tune", "tuned_plan", "candidates", "candidates2", "measure", "L"]
+__all__ = ["tune", "tuned_plan", "candidates", "candidates2", "measure"]

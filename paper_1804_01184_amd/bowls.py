@@ -55,21 +55,23 @@ def bowl_shape(H):
     return ratio, ang
 
 
-def bowl(plan, param, m0a, m0b, profile, wavelet, observed, xa, xb):
-    """J on the grid xa x xb (device forward + misfit per point)."""
+def bowl(plan, param, m0a, m0b, profile, wavelet, observed, xa, xb, weights=None):
+    """J on the grid xa x xb (device forward + misfit per point); weights
+    [S][nrec] restrict the misfit to a subset of the traces."""
     dev = plan.device
     m0a = api._dev_f32(m0a, dev)
     m0b = api._dev_f32(m0b, dev)
     s = api._dev_f32(profile, dev)
     f = api._dev_f32(wavelet, dev)
     obs = api._dev_f32(observed, dev)
+    wt = api._dev_f32(weights, dev) if weights is not None else None
     J = np.empty((len(xa), len(xb)))
     for i, a in enumerate(xa):
         ma = m0a * (1.0 + float(a) * s)
         for j, b in enumerate(xb):
             mb = m0b * (1.0 + float(b) * s)
             d = plan.forward(param, ma, mb, f)
-            J[i, j] = float(plan.misfit(d, obs, residual=False)[0].item())
+            J[i, j] = float(plan.misfit(d, obs, residual=False, weights=wt)[0].item())
     return J
 
 

@@ -1100,6 +1100,25 @@ fwi_status fwi_misfit(fwi_plan *p, const float *traces, const float *observed, f
     return launched("misfit");
 }
 
+fwi_status fwi_misfit_weighted(fwi_plan *p, const float *traces, const float *observed,
+                               const float *weights, float *residual, float *J, void *ws,
+                               size_t ws_bytes, void *stream)
+{
+    fwi_status st = check_call(p, ws, ws_bytes, FWI_OP_MISFIT);
+    if (st != FWI_OK)
+        return st;
+    if (!traces || !observed || !weights || !J)
+        return fail(FWI_EINVAL, "NULL array");
+    long long n = (long long)p->S * p->nrec * p->grid.nt;
+    Layout L = layout(p, FWI_OP_MISFIT);
+    {
+        Timed tm(p, (hipStream_t)stream, FWI_KC_OTHER);
+        launch_misfit(traces, observed, residual, n, (float *)((char *)ws + L.partials),
+                      misfit_blocks(n), J, (hipStream_t)stream, weights, p->grid.nt);
+    }
+    return launched("misfit_weighted");
+}
+
 fwi_status fwi_gradient(fwi_plan *p, int32_t param, const float *m1, const float *m2,
                         const float *wavelet, const float *observed, float *J, float *g1,
                         float *g2, float *traces, void *ws, size_t ws_bytes, void *stream)

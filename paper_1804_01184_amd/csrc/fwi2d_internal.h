@@ -108,8 +108,10 @@ void launch_sample_hist(const Geo &g, const float *hist, long long slot_stride, 
 // shot0: shot index of lp.shot(0) (the table holds global shot indices).
 void launch_inject(const Geo &g, const Inj &inj, const float *resid, int nrec, int nt, int n,
                    Fld lp, int shot0, hipStream_t st);
+// wt (may be null): one weight per trace of nt samples.
 void launch_misfit(const float *d, const float *dobs, float *resid, long long n,
-                   float *partials, int nblocks, float *J, hipStream_t st);
+                   float *partials, int nblocks, float *J, hipStream_t st,
+                   const float *wt = nullptr, int nt = 1);
 int misfit_blocks(long long n);
 // fold: scratch of 2 N floats.
 void launch_finalize(const Geo &g, int param, const float *m1, const float *m2,

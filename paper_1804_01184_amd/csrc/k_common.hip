@@ -253,18 +253,30 @@ __device__ inline float wave_sum(float v)
 }
 
 // Residual and per-block partial sums of r^2 (grid-stride, fixed grid).
-__global__ void k_misfit_partial(const float *d, const float *dobs, float *resid, long long n,
-                                 float *partials)
+// With trace weights w (one per trace of nt samples): residual w (d - dobs)
+// and sums of w (d - dobs)^2.
+__global__ void k_misfit_partial(const float *d, const float *dobs, const float *wt, int nt,
+                                 float *resid, long long n, float *partials)
 {
     __shared__ float ws[kBlock / 64];
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     long long stride = (long long)gridDim.x * blockDim.x;
     float acc = 0.0f;
-    for (; i < n; i += stride) {
-        float r = d[i] - dobs[i];
-        if (resid)
-            resid[i] = r;
-        acc += r * r;
+    if (wt) {
+        for (; i < n; i += stride) {
+            const float e = d[i] - dobs[i];
+            const float r = wt[i / nt] * e;
+            if (resid)
+                resid[i] = r;
+            acc += e * r;
+        }
+    } else {
+        for (; i < n; i += stride) {
+            float r = d[i] - dobs[i];
+            if (resid)
+                resid[i] = r;
+            acc += r * r;
+        }
     }
     acc = wave_sum(acc);
     if ((threadIdx.x & 63) == 0)
@@ -544,10 +556,11 @@ int misfit_blocks(long long n)
 }
 
 void launch_misfit(const float *d, const float *dobs, float *resid, long long n,
-                   float *partials, int nblocks, float *J, hipStream_t st)
+                   float *partials, int nblocks, float *J, hipStream_t st, const float *wt,
+                   int nt)
 {
-    hipLaunchKernelGGL(k_misfit_partial, dim3(nblocks), dim3(kBlock), 0, st, d, dobs, resid, n,
-                       partials);
+    hipLaunchKernelGGL(k_misfit_partial, dim3(nblocks), dim3(kBlock), 0, st, d, dobs, wt, nt,
+                       resid, n, partials);
     hipLaunchKernelGGL(k_misfit_final, dim3(1), dim3(kBlock), 0, st, (const float *)partials,
                        nblocks, J);
 }

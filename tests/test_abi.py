@@ -106,3 +106,9 @@ def test_descent_helpers_validate_before_touching_the_device():
                                  None) == -5
     assert lib.fwi_descent_norms(-2, p, None, p, None) == -1
     assert lib.fwi_descent_norms(4, p, None, None, None) == -1
+
+
+def test_weighted_misfit_validates_plan_and_arrays():
+    lib = L.lib()
+    p = ctypes.c_void_p(16)
+    assert lib.fwi_misfit_weighted(None, p, p, p, None, p, None, 0, None) == -1

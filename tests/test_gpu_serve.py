@@ -3,8 +3,6 @@ mix, admission respects the HBM budget, every request completes."""
 import numpy as np
 import pytest
 
-from paper_1804_01184_amd import workloads as W
-
 pytestmark = pytest.mark.gpu
 
 

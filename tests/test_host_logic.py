@@ -79,3 +79,16 @@ def test_bowl_fit_recovers_quadratic_and_shape():
     r, ang = bowls.bowl_shape(Hr)
     assert r == pytest.approx(4.0) and ang == pytest.approx(30.0)
     del rng
+
+
+def test_scattering_angles_and_aperture_weights():
+    from paper_1804_01184_amd import patterns as P
+    src = [[0.0, -10.0], [10.0, 0.0]]
+    rec = [[[0.0, -5.0], [5.0, 0.0], [0.0, 7.0], [-3.0, -3.0]]] * 2
+    th = P.scattering_angles((0.0, 0.0), src, rec)
+    np.testing.assert_allclose(th[0], [0.0, 90.0, 180.0, 45.0], atol=1e-9)
+    np.testing.assert_allclose(th[1], [90.0, 0.0, 90.0, 135.0], atol=1e-9)
+    w = P.angle_weights(th, 0.0, 90.0)
+    np.testing.assert_array_equal(w, [[1, 1, 0, 1], [1, 1, 1, 0]])
+    assert w.dtype == np.float32
+    np.testing.assert_array_equal(P.angle_weights(th, 135.0, 180.0), [[0, 0, 1, 0], [0, 0, 0, 1]])
