@@ -41,16 +41,21 @@ from . import INVK_INVRHO, IP_RHO, K_RHO, VP_IP, VP_RHO, krho_to_model, model_to
 
 def green(omega, pts, cells, K0, rho0):
     """(G, Gx, Gz) [F][P][C] complex: G0 between each point and each cell
-    centre and its gradient with respect to the cell position."""
+    centre and its gradient with respect to the cell position.  A cell
+    whose centre coincides with the point is left out (0): the paper is
+    silent there, and the density term of the Born integral is not
+    integrable at a source or receiver."""
     omega = np.asarray(omega, float)
     pts = np.asarray(pts, float).reshape(-1, 2)
     cells = np.asarray(cells, float).reshape(-1, 2)
     k = omega * np.sqrt(rho0 / K0)
     d = cells[None, :, :] - pts[:, None, :]
     r = np.sqrt(np.sum(d * d, axis=-1))
-    kr = k[:, None, None] * r[None]
-    G = 0.25j * rho0 * hankel1(0, kr)
-    dG = -0.25j * rho0 * k[:, None, None] * hankel1(1, kr) / r[None]
+    live = r > 0
+    rs = np.where(live, r, 1.0)
+    kr = k[:, None, None] * rs[None]
+    G = np.where(live[None], 0.25j * rho0 * hankel1(0, kr), 0.0)
+    dG = np.where(live[None], -0.25j * rho0 * k[:, None, None] * hankel1(1, kr) / rs[None], 0.0)
     return G, dG * d[None, :, :, 0], dG * d[None, :, :, 1]
 
 
@@ -140,3 +145,24 @@ def chain(scheme, param, xa, xb, gK, gR, K0, rho0, h=1e-7):
     dKa, dRa = (pa[0] - ma[0]) / (2 * h), (pa[1] - ma[1]) / (2 * h)
     dKb, dRb = (pb[0] - mb[0]) / (2 * h), (pb[1] - mb[1]) / (2 * h)
     return dKa * gK + dRa * gR, dKb * gK + dRb * gR
+
+
+def reduced_hessian(omega, spec, src, rec, x0, K0, rho0, param):
+    """Reduced Hessian of a point scatterer at x0 (section "Point-scatterer
+    Analysis"): H = sum_w |S|^2 sum_{s,r} conj(W) W^T, with the modelling
+    vector W = A^T (w^2/K0 G0(xr; x0) G0(x0; xs), -(1/rho0) grad G0(xr; x0) .
+    grad G0(x0; xs)) and A the scheme-I map of `param`; 2x2 complex."""
+    x0 = np.asarray(x0, float).reshape(1, 2)
+    Gs, Gsx, Gsz = (t[:, :, 0] for t in green(omega, src, x0, K0, rho0))   # [F][S]
+    Gr, Grx, Grz = (t[:, :, 0] for t in green(omega, rec, x0, K0, rho0))   # [F][R]
+    w2 = np.asarray(omega, float) ** 2
+    WK = (w2 / K0)[:, None, None] * Gs[:, :, None] * Gr[:, None, :]
+    WR = -(Gsx[:, :, None] * Grx[:, None, :] + Gsz[:, :, None] * Grz[:, None, :]) / rho0
+    A = linear_map(param)
+    Wp = [A[0, i] * WK + A[1, i] * WR for i in range(2)]
+    s2 = np.abs(np.asarray(spec)) ** 2
+    H = np.empty((2, 2), complex)
+    for i in range(2):
+        for j in range(2):
+            H[i, j] = np.sum(s2[:, None, None] * np.conj(Wp[i]) * Wp[j])
+    return H

@@ -38,6 +38,9 @@ def test_green_solves_helmholtz_and_has_the_source_singularity():
     G = B.green([w], np.zeros(2), r, K0, RHO0)[0][0, 0]
     assert (G[0] - G[1]).real == pytest.approx(-RHO0 / (2 * math.pi) * math.log(0.5), rel=1e-6)
     assert abs((G[0] - G[1]).imag) <= 1e-6 * abs(G[0] - G[1])
+    # a cell on the point is left out
+    G, Gx, Gz = B.green([w], np.zeros(2), np.zeros((1, 2)), K0, RHO0)
+    assert G[0, 0, 0] == 0 and Gx[0, 0, 0] == 0 and Gz[0, 0, 0] == 0
 
 
 def test_green_gradient_is_the_derivative():
@@ -159,3 +162,28 @@ def test_schemes_linear_map_and_chain_rule(param):
         e[i] = 1e-6
         assert ga[i] == pytest.approx((J(xa + e, xb) - J(xa - e, xb)) / 2e-6, rel=1e-5, abs=1e-8)
         assert gb[i] == pytest.approx((J(xa, xb + e) - J(xa, xb - e)) / 2e-6, rel=1e-5, abs=1e-8)
+
+
+def test_reduced_hessian_of_a_circular_acquisition():
+    # sources and receivers evenly on a circle of radius a around x0: the
+    # scatterer sees every source and receiver at the same distance, so
+    #   H_KK = Ns Nr |S|^2 (w^2 rho0^2 / (16 K0))^2 |H0(ka)|^4,
+    #   H_rr = Ns Nr / 2 |S|^2 (rho0 k^2 / 16)^2 |H1(ka)|^4  (mean cos^2 = 1/2),
+    # and the cross term vanishes (mean cos = 0), in 1/K-1/rho; in another
+    # parameterization the Hessian is A^T H A.
+    from scipy.special import hankel1
+    Ns, Nr, a = 12, 30, 490.0
+    src, rec = W.point_ring(Ns, Nr, a)
+    w, S = 2 * math.pi * 17.0, 0.3 - 0.4j
+    k = w * math.sqrt(RHO0 / K0)
+    H = B.reduced_hessian([w], [S], src, rec, (0.0, 0.0), K0, RHO0, O.INVK_INVRHO)
+    hkk = Ns * Nr * abs(S) ** 2 * (w * w * RHO0 ** 2 / (16 * K0)) ** 2 * abs(hankel1(0, k * a)) ** 4
+    hrr = Ns * Nr / 2 * abs(S) ** 2 * (RHO0 * k * k / 16) ** 2 * abs(hankel1(1, k * a)) ** 4
+    assert H[0, 0].real == pytest.approx(hkk, rel=1e-10)
+    assert H[1, 1].real == pytest.approx(hrr, rel=1e-10)
+    assert abs(H[0, 1]) <= 1e-10 * hkk
+    assert abs(H[0, 0].imag) <= 1e-12 * hkk
+    for p in (O.VP_RHO, O.IP_RHO, O.VP_IP, O.K_RHO):
+        A = B.linear_map(p)
+        np.testing.assert_allclose(B.reduced_hessian([w], [S], src, rec, (0.0, 0.0), K0, RHO0, p),
+                                   A.T @ H @ A, rtol=1e-10, atol=1e-10 * hkk)
