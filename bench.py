@@ -54,6 +54,9 @@ def parse():
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="no per-launch event timing (for hardware-counter runs); the "
                          "roofline entry is then omitted")
+    ap.add_argument("--born", action="store_true",
+                    help="schemes I/II instead: one Born gradient per step (frequency-domain "
+                         "config 2), one JSON line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB elementwise kernel (reads 1 GiB, writes 1 GiB) and "
                          "exit: the reference for the HBM traffic counters")
@@ -148,8 +151,87 @@ def cpu_baseline(w, steps):
                       f"(gradient in Vp-rho, FP64, OpenMP)"}
 
 
+def born_cpu_baseline(w, xk, xr, flops):
+    """The FP64 oracle's Born data on a bounded sample: one frequency, one
+    source, half the receivers, every cell."""
+    from oracle import born as OB
+    f = len(w.freqs) // 2
+    rec = w.rec_xz[::2]
+    t = time.perf_counter()
+    OB.scattered(w.omega[f:f + 1], w.src_xz[:1], rec, w.cells, w.dA, w.K0, w.rho0, xk, xr)
+    dt = time.perf_counter() - t
+    frac = 1.0 / (len(w.freqs) * len(w.src_xz)) * len(rec) / len(w.rec_xz)
+    return {"value": round(flops * frac / dt / 1e12, 6), "unit": "TFLOP/s", "kind": "oracle",
+            "cores": 1, "seconds": round(dt, 2),
+            "sample": f"Born data of one frequency, one source, {len(rec)} receivers and all "
+                      f"{len(xk)} cells (FP64 numpy/scipy); rate counted as 24 flops per "
+                      f"(frequency, source, receiver, cell)"}
+
+
+def born_main(args):
+    """One step = one scheme-II gradient: contrast map, Born data, misfit,
+    adjoint (gradient in the inverse contrasts), chain rule; the Green
+    tables are built once per geometry, before the timed region."""
+    import torch
+    from paper_1804_01184_amd import born, workloads as W
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    w = W.born_config2()
+    sz = w.sizes()
+    m = born.measure(w, reps=max(args.steps, 1), device=dev)
+    prob = born.BornProblem.of(w, dev)
+    xa = torch.tensor(w.xa.ravel(), dtype=torch.float32, device=dev)
+    xb = torch.tensor(w.xb.ravel(), dtype=torch.float32, device=dev)
+    q = prob.data(*born.contrasts(2, w.param, xa, xb))
+    za, zb = torch.zeros_like(xa), torch.zeros_like(xb)
+    d = torch.empty_like(q)
+
+    def step():
+        xk, xr = born.contrasts(2, w.param, za, zb)
+        prob.data(xk, xr, out=d)
+        _, r = prob.misfit(d, q)
+        gK, gR = prob.gradient(r)
+        return born.chain(2, w.param, za, zb, gK, gR)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t) * 1e3 / args.steps
+    flops = m["flops_per_launch"]
+    dom = "data" if m["data"]["ms"] >= m["gradient"]["ms"] else "gradient"
+    roof = {"bound": "alu", "achieved": round(m[dom]["tflops"], 3),
+            "peak": born.PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(m[dom]["tflops"] / born.PEAK_FP32_TFLOPS, 4), "traffic": None,
+            "kernel": "k_born_data" if dom == "data" else "k_born_grad",
+            "frac_of_nonpacked_fp32": round(m[dom]["tflops"] / born.PEAK_FP32_NONPACKED_TFLOPS, 4),
+            "flops_per_launch": flops, "avg_ms": round(m[dom]["ms"], 4)}
+    xk, xr = (t_.cpu().numpy().astype(np.float64) for t_ in m["contrasts"])
+    cpu = None if args.no_cpu else born_cpu_baseline(w, xk, xr, flops)
+    rec = {"metric": "Born gradient (schemes I/II): TFLOP/s of the data and adjoint sums",
+           "value": round(2 * flops / (ms * 1e-3) / 1e12, 3), "unit": "TFLOP/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": f"{w.name}: {w.nz}x{w.nx} cells at {w.dx:g} m, "
+                                  f"{sz['S']} sources x {sz['R']} receivers, {sz['F']} "
+                                  f"frequencies, scheme II in {w.param}",
+                      **sz},
+           "kernels_ms": {"green_tables": round(m["green"]["ms"], 3),
+                          "data": round(m["data"]["ms"], 3),
+                          "gradient": round(m["gradient"]["ms"], 3)},
+           "roofline": roof, "cpu_baseline": cpu}
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     args = parse()
+    if args.born:
+        born_main(args)
+        return
     if args.copy_calibration:
         copy_calibration()
         return

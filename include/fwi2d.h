@@ -250,6 +250,107 @@ fwi_status fwi_descent_apply(int64_t n, const float *m, const float *m0, const f
 fwi_status fwi_descent_norms(int64_t n, const float *a, const float *b, float *out,
                              void *stream);
 
+/* ------------------------------------------------------------------------
+ * Schemes I and II: Born modelling in the frequency domain (section
+ * "Modelling and Inversion") around a homogeneous reference medium (K0,
+ * rho0), with the contrasts xi_{1/K} = K0/K - 1 and xi_{1/rho} = rho0/rho - 1
+ * of Table 1 (E) on a set of C cells of area dA.
+ *
+ * Conventions: time dependence exp(-i w t); L0 = w^2/K0 + div (1/rho0) grad
+ * and L0 G0 = -delta, so G0(r) = (i rho0/4) H0(k r) with k = w sqrt(rho0/K0)
+ * and H0 the Hankel function of the first kind; gradients are taken with
+ * respect to the cell position.  Born data for source s, receiver r and
+ * angular frequency w_f, with source spectrum S_f:
+ *   d = S_f [G0(x_r; x_s) + dA sum_c (w_f^2/K0 G0(x_r; x_c) G0(x_c; x_s) xi_{1/K}
+ *         - (1/rho0) grad G0(x_r; x_c) . grad G0(x_c; x_s) xi_{1/rho})].
+ * Misfit J = 1/2 sum |d - q|^2 over frequencies, sources and receivers.
+ *
+ * Complex arrays are interleaved (re, im) FP32 pairs.  Every array argument
+ * is device memory; every call is asynchronous on `stream` (NULL: the null
+ * stream).  Argument errors return before any work is enqueued.
+ * ---------------------------------------------------------------------- */
+
+/* Green function tables: for F angular frequencies omega [F] (rad/s), C cell
+ * centres cells [C][2] and P points pts [P][2] ((x, z) in metres), writes
+ * G [F][C][P] = G0(pts[p]; cells[c]) and its gradient with respect to the
+ * cell position, Gx and Gz (same layout; both NULL or both non-NULL).  The
+ * Hankel functions are evaluated in FP64 (ascending series up to k r = 12,
+ * Hankel's asymptotic expansion beyond) and rounded to FP32.  A point that
+ * coincides with a cell centre gets 0 (the singular self term is left out).
+ * Tables of the sources (pts = sources) and of the receivers (pts =
+ * receivers) feed fwi_born_data and fwi_born_gradient; the direct wave
+ * G0(x_r; x_s) is the table with cells = sources and pts = receivers
+ * ([F][S][R]).  FWI_EINVAL for negative sizes, K0 or rho0 not positive, or a
+ * NULL required array. */
+fwi_status fwi_born_green(int32_t F, const float *omega, int32_t C, const float *cells,
+                          int32_t P, const float *pts, double K0, double rho0, float *G,
+                          float *Gx, float *Gz, void *stream);
+
+/* Workspace bytes (256-byte aligned) that fwi_born_data, fwi_born_gradient
+ * and fwi_born_misfit need for these sizes (partial sums of the split
+ * launches).  The workspace is only used during the call's kernels; calls
+ * on one workspace must be ordered (same stream). */
+size_t fwi_born_workspace_bytes(int32_t F, int32_t S, int32_t R, int32_t C);
+
+/* Born data d [F][S][R] (formula above) from the contrasts xiK, xiR [C], the
+ * source tables Gs, Gsx, Gsz [F][C][S], the receiver tables Gr, Grx, Grz
+ * [F][C][R] and the direct wave Gd [F][S][R] (NULL: scattered data only).
+ * spec [F] complex.  FP32 arithmetic with FP32 accumulation: per frequency
+ * the cells are cut into ranges summed in a fixed order (bitwise
+ * repeatable).  FWI_EWORKSPACE if work is NULL, misaligned or smaller than
+ * fwi_born_workspace_bytes. */
+fwi_status fwi_born_data(int32_t F, const float *omega, const float *spec, int32_t S,
+                         int32_t R, int32_t C, double K0, double rho0, double dA,
+                         const float *xiK, const float *xiR, const float *Gs, const float *Gsx,
+                         const float *Gsz, const float *Gr, const float *Grx, const float *Grz,
+                         const float *Gd, float *d, void *work, size_t work_bytes,
+                         void *stream);
+
+/* J[0] = 1/2 sum_i |d_i - q_i|^2 over n complex values and, unless resid is
+ * NULL, resid = d - q (fixed-order reduction). */
+fwi_status fwi_born_misfit(int64_t n, const float *d, const float *q, float *resid, float *J,
+                           void *work, size_t work_bytes, void *stream);
+
+/* Gradient of J in the inverse contrasts for the residual resid = d - q
+ * [F][S][R] complex: gK[c] = dJ/dxi_{1/K}(c), gR[c] = dJ/dxi_{1/rho}(c), the
+ * real part of sum conj(resid) dd/dxi, i.e. the adjoint of the Born
+ * operator applied to the residual.  Tables as fwi_born_data.  Frequencies
+ * are cut into ranges summed in a fixed order. */
+fwi_status fwi_born_gradient(int32_t F, const float *omega, const float *spec, int32_t S,
+                             int32_t R, int32_t C, double K0, double rho0, double dA,
+                             const float *resid, const float *Gs, const float *Gsx,
+                             const float *Gsz, const float *Gr, const float *Grx,
+                             const float *Grz, float *gK, float *gR, void *work,
+                             size_t work_bytes, void *stream);
+
+/* Inverse contrasts (xiK, xiR) of the contrasts (xa, xb) = (m - m0)/m0 of a
+ * parameterization (fwi_param) in a homogeneous background, n cells.
+ * scheme 2: the exact map of Table 2 (the model m0 (1 + x) converted to K
+ * and rho); scheme 1: its linearisation at zero contrast (the role of
+ * Table 3).  FWI_EINVAL for another scheme or parameterization. */
+fwi_status fwi_born_contrasts(int32_t scheme, int32_t param, int64_t n, const float *xa,
+                              const float *xb, float *xiK, float *xiR, void *stream);
+
+/* Chain rule of fwi_born_contrasts: (ga, gb) = dJ/d(xa, xb) from (gK, gR) =
+ * dJ/d(xiK, xiR) at the contrasts (xa, xb); scheme 1 with the linear map,
+ * scheme 2 with the Jacobian of the exact map. */
+fwi_status fwi_born_chain(int32_t scheme, int32_t param, int64_t n, const float *xa,
+                          const float *xb, const float *gK, const float *gR, float *ga,
+                          float *gb, void *stream);
+
+/* Reduced Hessian of a point scatterer (section "Point-scatterer
+ * Analysis"): H = sum_f |S_f|^2 sum_{s,r} conj(W) W^T with the modelling
+ * vector W = A^T (w^2/K0 Gr Gs, -(1/rho0)(Grx Gsx + Grz Gsz)), A the scheme-I
+ * map of `param` (A = identity for FWI_INVK_INVRHO), from the tables at the
+ * scatterer: Gs, Gsx, Gsz [F][S] and Gr, Grx, Grz [F][R] (fwi_born_green with
+ * C = 1).  H [2][2] complex (8 floats; H[1][0] = conj H[0][1]).  FP64
+ * accumulation in a fixed order. */
+fwi_status fwi_born_hessian(int32_t F, const float *omega, const float *spec, int32_t S,
+                            int32_t R, double K0, double rho0, const float *Gs,
+                            const float *Gsx, const float *Gsz, const float *Gr,
+                            const float *Grx, const float *Grz, int32_t param, float *H,
+                            void *stream);
+
 /* Kernel classes of the per-launch timing below. */
 typedef enum {
     FWI_KC_FWD_STEP = 0,   /* batched forward step (all shots)                 */

@@ -25,7 +25,9 @@ SYMBOLS = ["fwi_plan_create", "fwi_plan_destroy", "fwi_plan_get_info", "fwi_work
            "fwi_forward", "fwi_misfit", "fwi_misfit_weighted", "fwi_gradient", "fwi_adjoint", "fwi_forward_keep",
            "fwi_adjoint_kept", "fwi_model_convert",
            "fwi_chain_rule", "fwi_contrast_scale", "fwi_descent_direction", "fwi_descent_apply",
-           "fwi_descent_norms", "fwi_timing_enable", "fwi_timing_read",
+           "fwi_descent_norms", "fwi_born_green", "fwi_born_workspace_bytes", "fwi_born_data",
+           "fwi_born_misfit", "fwi_born_gradient", "fwi_born_contrasts", "fwi_born_chain",
+           "fwi_born_hessian", "fwi_timing_enable", "fwi_timing_read",
            "fwi_sync", "fwi_status_str", "fwi_last_error"]
 
 KERNEL_CLASSES = ["fwd_step", "adj_step", "plain_vel", "plain_pres", "plain_adj_a",
@@ -127,6 +129,26 @@ def lib():
     L.fwi_descent_apply.restype = st
     L.fwi_descent_norms.argtypes = [i64, fp, fp, fp, vp]
     L.fwi_descent_norms.restype = st
+    dbl = ctypes.c_double
+    L.fwi_born_green.argtypes = [i32, fp, i32, fp, i32, fp, dbl, dbl, fp, fp, fp, vp]
+    L.fwi_born_green.restype = st
+    L.fwi_born_workspace_bytes.argtypes = [i32, i32, i32, i32]
+    L.fwi_born_workspace_bytes.restype = sz
+    L.fwi_born_data.argtypes = [i32, fp, fp, i32, i32, i32, dbl, dbl, dbl, fp, fp,
+                                fp, fp, fp, fp, fp, fp, fp, fp, vp, sz, vp]
+    L.fwi_born_data.restype = st
+    L.fwi_born_misfit.argtypes = [i64, fp, fp, fp, fp, vp, sz, vp]
+    L.fwi_born_misfit.restype = st
+    L.fwi_born_gradient.argtypes = [i32, fp, fp, i32, i32, i32, dbl, dbl, dbl, fp,
+                                    fp, fp, fp, fp, fp, fp, fp, fp, vp, sz, vp]
+    L.fwi_born_gradient.restype = st
+    L.fwi_born_contrasts.argtypes = [i32, i32, i64, fp, fp, fp, fp, vp]
+    L.fwi_born_contrasts.restype = st
+    L.fwi_born_chain.argtypes = [i32, i32, i64, fp, fp, fp, fp, fp, fp, vp]
+    L.fwi_born_chain.restype = st
+    L.fwi_born_hessian.argtypes = [i32, fp, fp, i32, i32, dbl, dbl, fp, fp, fp, fp, fp, fp,
+                                   i32, fp, vp]
+    L.fwi_born_hessian.restype = st
     L.fwi_timing_enable.argtypes = [vp, i32]
     L.fwi_timing_enable.restype = st
     L.fwi_timing_read.argtypes = [vp, ctypes.POINTER(FwiTiming), i32]

@@ -1,0 +1,272 @@
+"""Schemes I and II: Born modelling in the frequency domain (section
+"Modelling and Inversion") and the point-scatterer analysis (section
+"Point-scatterer Analysis"), on the library's HIP kernels.
+
+A BornProblem holds, on the device, the Green function tables of one
+acquisition over one set of cells (computed once: the geometry does not
+change during an inversion), and evaluates
+
+- data(xiK, xiR): Born data in the inverse contrasts of Table 1 (E);
+- misfit(d, q): J = 1/2 sum |d - q|^2 and the residual;
+- gradient(resid): dJ/dxi_{1/K}, dJ/dxi_{1/rho} (the adjoint Born operator);
+- contrasts / chain: the scheme-II exact map (Table 2) or its scheme-I
+  linearisation from the contrasts of another parameterization, and the
+  chain rule back;
+
+and reduced_hessian() gives the 2x2 Hessian of a point scatterer in any
+parameterization.  ``python -m paper_1804_01184_amd.born`` measures the
+kernels on the frequency-domain form of config 2 and prints the reduced
+Hessians of the circular acquisition, as one JSON line.
+"""
+from __future__ import annotations
+
+import json
+import math
+import sys
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from .api import _ptr, _stream, param_id
+
+
+def _f32(x, dev):
+    return torch.as_tensor(np.ascontiguousarray(np.asarray(x, np.float32)), device=dev)
+
+
+def _c64(x, dev):
+    return torch.as_tensor(np.ascontiguousarray(np.asarray(x, np.complex64)), device=dev)
+
+
+def green(omega, cells, pts, K0, rho0, grad=True, stream=None):
+    """Tables (G, Gx, Gz) [F][C][P] complex64 on the device of `omega` (a
+    float32 device tensor); cells, pts [n][2] device float32."""
+    F, C, P = omega.numel(), cells.shape[0], pts.shape[0]
+    dev = omega.device
+    G = torch.empty((F, C, P), dtype=torch.complex64, device=dev)
+    Gx = torch.empty_like(G) if grad else None
+    Gz = torch.empty_like(G) if grad else None
+    L.check(L.lib().fwi_born_green(F, _ptr(omega), C, _ptr(cells), P, _ptr(pts), float(K0),
+                                   float(rho0), _ptr(G), _ptr(Gx), _ptr(Gz), _stream(stream)))
+    return G, Gx, Gz
+
+
+class BornProblem:
+    """Born modelling of S sources and R receivers (every source recorded by
+    the same receivers) over C cells of area dA, around (K0, rho0)."""
+
+    def __init__(self, omega, spec, src_xz, rec_xz, cells_xz, dA, K0, rho0, device=None):
+        dev = torch.device(device) if device is not None else torch.device(
+            "cuda", torch.cuda.current_device())
+        self.device = dev
+        self.omega = _f32(omega, dev)
+        self.spec = _c64(spec, dev)
+        self.src = _f32(np.asarray(src_xz).reshape(-1, 2), dev)
+        self.rec = _f32(np.asarray(rec_xz).reshape(-1, 2), dev)
+        self.cells = _f32(np.asarray(cells_xz).reshape(-1, 2), dev)
+        self.dA, self.K0, self.rho0 = float(dA), float(K0), float(rho0)
+        self.F, self.S = self.omega.numel(), self.src.shape[0]
+        self.R, self.C = self.rec.shape[0], self.cells.shape[0]
+        nb = L.lib().fwi_born_workspace_bytes(self.F, self.S, self.R, self.C)
+        self.work = torch.empty(max(int(nb), 256), dtype=torch.uint8, device=dev)
+        self.tables()
+
+    @classmethod
+    def of(cls, w, device=None):
+        """Problem of a workloads.BornWorkload."""
+        return cls(w.omega, w.spec, w.src_xz, w.rec_xz, w.cells, w.dA, w.K0, w.rho0, device)
+
+    def tables(self, stream=None):
+        """(Re)computes the source, receiver and direct-wave tables."""
+        self.Gs = green(self.omega, self.cells, self.src, self.K0, self.rho0, stream=stream)
+        self.Gr = green(self.omega, self.cells, self.rec, self.K0, self.rho0, stream=stream)
+        self.Gd = green(self.omega, self.src, self.rec, self.K0, self.rho0, grad=False,
+                        stream=stream)[0]
+
+    def _cell(self, x):
+        t = x if isinstance(x, torch.Tensor) else torch.as_tensor(np.asarray(x, np.float32))
+        t = t.to(device=self.device, dtype=torch.float32).reshape(-1).contiguous()
+        assert t.numel() == self.C
+        return t
+
+    def data(self, xiK, xiR, direct=True, out=None, stream=None):
+        """Born data [F][S][R] complex64 for the inverse contrasts."""
+        xiK, xiR = self._cell(xiK), self._cell(xiR)
+        d = torch.empty((self.F, self.S, self.R), dtype=torch.complex64,
+                        device=self.device) if out is None else out
+        L.check(L.lib().fwi_born_data(
+            self.F, _ptr(self.omega), _ptr(self.spec), self.S, self.R, self.C, self.K0,
+            self.rho0, self.dA, _ptr(xiK), _ptr(xiR), *(_ptr(t) for t in self.Gs),
+            *(_ptr(t) for t in self.Gr), _ptr(self.Gd) if direct else None, _ptr(d),
+            _ptr(self.work), self.work.numel(), _stream(stream)))
+        return d
+
+    def misfit(self, d, q, residual=True, stream=None):
+        """(J [1] device float32, resid = d - q or None)."""
+        d, q = d.contiguous(), q.contiguous()
+        J = torch.empty(1, dtype=torch.float32, device=self.device)
+        r = torch.empty_like(d) if residual else None
+        L.check(L.lib().fwi_born_misfit(d.numel(), _ptr(d), _ptr(q), _ptr(r), _ptr(J),
+                                        _ptr(self.work), self.work.numel(), _stream(stream)))
+        return J, r
+
+    def gradient(self, resid, stream=None):
+        """(dJ/dxi_{1/K}, dJ/dxi_{1/rho}) [C] for resid = d - q."""
+        resid = resid.contiguous()
+        gK = torch.empty(self.C, dtype=torch.float32, device=self.device)
+        gR = torch.empty_like(gK)
+        L.check(L.lib().fwi_born_gradient(
+            self.F, _ptr(self.omega), _ptr(self.spec), self.S, self.R, self.C, self.K0,
+            self.rho0, self.dA, _ptr(resid), *(_ptr(t) for t in self.Gs),
+            *(_ptr(t) for t in self.Gr), _ptr(gK), _ptr(gR), _ptr(self.work),
+            self.work.numel(), _stream(stream)))
+        return gK, gR
+
+    def table_bytes(self):
+        return sum(t.numel() * 8 for t in (*self.Gs, *self.Gr, self.Gd))
+
+
+def contrasts(scheme, param, xa, xb, stream=None):
+    """(xi_{1/K}, xi_{1/rho}) of the contrasts (xa, xb) of `param`: scheme 2
+    exact, scheme 1 linearised."""
+    xa, xb = xa.contiguous(), xb.contiguous()
+    k, r = torch.empty_like(xa), torch.empty_like(xa)
+    L.check(L.lib().fwi_born_contrasts(int(scheme), param_id(param), xa.numel(), _ptr(xa),
+                                       _ptr(xb), _ptr(k), _ptr(r), _stream(stream)))
+    return k, r
+
+
+def chain(scheme, param, xa, xb, gK, gR, stream=None):
+    """(dJ/dxa, dJ/dxb) from (dJ/dxi_{1/K}, dJ/dxi_{1/rho})."""
+    xa, xb, gK, gR = (x.contiguous() for x in (xa, xb, gK, gR))
+    ga, gb = torch.empty_like(gK), torch.empty_like(gK)
+    L.check(L.lib().fwi_born_chain(int(scheme), param_id(param), gK.numel(), _ptr(xa),
+                                   _ptr(xb), _ptr(gK), _ptr(gR), _ptr(ga), _ptr(gb),
+                                   _stream(stream)))
+    return ga, gb
+
+
+def reduced_hessian(omega, spec, src_xz, rec_xz, x0, K0, rho0, param, device=None,
+                    stream=None):
+    """2x2 complex reduced Hessian (numpy) of a point scatterer at x0 in
+    `param` (scheme I map) for every source recorded by every receiver."""
+    dev = torch.device(device) if device is not None else torch.device(
+        "cuda", torch.cuda.current_device())
+    om = _f32(omega, dev)
+    sp = _c64(spec, dev)
+    src = _f32(np.asarray(src_xz).reshape(-1, 2), dev)
+    rec = _f32(np.asarray(rec_xz).reshape(-1, 2), dev)
+    cell = _f32(np.asarray(x0, float).reshape(1, 2), dev)
+    Gs = green(om, cell, src, K0, rho0, stream=stream)
+    Gr = green(om, cell, rec, K0, rho0, stream=stream)
+    H = torch.empty(8, dtype=torch.float32, device=dev)
+    L.check(L.lib().fwi_born_hessian(om.numel(), _ptr(om), _ptr(sp), src.shape[0], rec.shape[0],
+                                     float(K0), float(rho0), *(_ptr(t) for t in Gs),
+                                     *(_ptr(t) for t in Gr), param_id(param), _ptr(H),
+                                     _stream(stream)))
+    h = H.cpu().numpy().astype(np.float64)
+    return (h[0::2] + 1j * h[1::2]).reshape(2, 2)
+
+
+def hessian_summary(H):
+    """Eigen-analysis of the Gauss-Newton Hessian Re H: eigenvalues,
+    condition number, angle of the principal eigenvector (degrees in
+    [0, 180)) and the normalised cross term."""
+    Hr = np.real(H)
+    w, v = np.linalg.eigh(0.5 * (Hr + Hr.T))
+    ang = float(np.degrees(np.arctan2(v[1, 1], v[0, 1])) % 180.0)
+    return {"eig": w.tolist(), "cond": float(w[1] / w[0]) if w[0] > 0 else float("inf"),
+            "principal_deg": ang,
+            "cross": float(Hr[0, 1] / math.sqrt(abs(Hr[0, 0] * Hr[1, 1])))}
+
+
+# FP32 FMA rate of the chip (256 CUs x 2.4 GHz): 157.3 TFLOP/s counts
+# packed FP32; the library is built without packed FP32 instructions, which
+# halves the vector rate available to these kernels.
+PEAK_FP32_TFLOPS = 157.3
+PEAK_FP32_NONPACKED_TFLOPS = 78.6
+
+PARAMS = ("vp-rho", "ip-rho", "vp-ip", "k-rho", "invk-invrho")
+
+
+def _events_ms(fn, reps):
+    st = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fn()
+    torch.cuda.synchronize()
+    a.record(st)
+    for _ in range(reps):
+        fn()
+    b.record(st)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def measure(w, reps=5, device=None):
+    """Times table construction, Born data and gradient on the workload
+    (HIP events on the current stream; inputs resident before timing) and
+    returns a dict with the rates and the ALU roofline entry."""
+    dev = torch.device(device) if device is not None else torch.device(
+        "cuda", torch.cuda.current_device())
+    sz = w.sizes()
+    F, S, R, C = sz["F"], sz["S"], sz["R"], sz["C"]
+    prob = BornProblem.of(w, dev)
+    xa = _f32(w.xa.ravel(), dev)
+    xb = _f32(w.xb.ravel(), dev)
+    xk, xr = contrasts(2, w.param, xa, xb)
+    q = prob.data(xk, xr)                       # observed: true contrasts
+    zero = torch.zeros_like(xk)
+    d0 = prob.data(zero, zero)
+    J, res = prob.misfit(d0, q)
+    ms_green = _events_ms(prob.tables, 1)
+    ms_data = _events_ms(lambda: prob.data(xk, xr, out=d0), reps)
+    ms_grad = _events_ms(lambda: prob.gradient(res), reps)
+    flops = 24.0 * F * S * R * C               # 3 complex multiply-adds per (f, s, r, c)
+    evals = F * C * (S + R) + F * S * R
+    out = {"workload": w.name, "sizes": sz, "J0": float(J.item()),
+           "table_GB": prob.table_bytes() / 1e9,
+           "green": {"ms": ms_green, "hankel_evals_per_s": evals / (ms_green * 1e-3)},
+           "data": {"ms": ms_data, "tflops": flops / (ms_data * 1e-3) / 1e12},
+           "gradient": {"ms": ms_grad, "tflops": flops / (ms_grad * 1e-3) / 1e12},
+           "flops_per_launch": flops, "contrasts": (xk, xr)}
+    return out
+
+
+def hessians(w, n_src=36, n_rec=180, radius=490.0, device=None):
+    """Reduced Hessians of the circular acquisition (sources and receivers
+    on a ring around the scatterer) at the workload's frequencies."""
+    from . import workloads as W
+    src, rec = W.point_ring(n_src, n_rec, radius)
+    return {p: hessian_summary(reduced_hessian(w.omega, w.spec, src, rec, (0.0, 0.0), w.K0,
+                                               w.rho0, p, device)) for p in PARAMS}
+
+
+def main(argv=None):
+    import argparse
+    from . import workloads as W
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2"])
+    ap.add_argument("--freqs", type=int, default=32)
+    ap.add_argument("--reps", type=int, default=5)
+    a = ap.parse_args(argv)
+    torch.cuda.set_device(0)
+    w = W.born_config2(a.freqs) if a.workload == "c2" else W.born_config1(a.freqs)
+    out = measure(w, a.reps)
+    out.pop("contrasts")
+    for k in ("data", "gradient"):
+        out[k]["frac"] = out[k]["tflops"] / PEAK_FP32_TFLOPS
+        out[k]["frac_nonpacked"] = out[k]["tflops"] / PEAK_FP32_NONPACKED_TFLOPS
+    print(f"green {out['green']['ms']:.1f} ms, data {out['data']['ms']:.2f} ms "
+          f"({out['data']['tflops']:.1f} TFLOP/s), gradient {out['gradient']['ms']:.2f} ms "
+          f"({out['gradient']['tflops']:.1f} TFLOP/s)", file=sys.stderr, flush=True)
+    hs = hessians(w)
+    for p, h in hs.items():
+        print(f"reduced Hessian {p}: cond {h['cond']:.2f}, cross {h['cross']:+.3f}, "
+              f"principal {h['principal_deg']:.1f} deg", file=sys.stderr, flush=True)
+    out["reduced_hessian_ring_490m"] = hs
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])

@@ -14,7 +14,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libfwi2d.so")
-SOURCES = ["fwi2d_api.hip", "k_common.hip", "k_plain.hip", "k_fused.hip"]
+SOURCES = ["fwi2d_api.hip", "k_common.hip", "k_plain.hip", "k_fused.hip", "k_born.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # -ffp-contract=on: multiply-adds are fused only within one source

@@ -1248,6 +1248,183 @@ fwi_status fwi_descent_norms(int64_t n, const float *a, const float *b, float *o
     return launched("descent_norms");
 }
 
+// ------------------------------------------------------------------ born
+namespace {
+
+bool born_sizes_ok(int F, int S, int R, int C)
+{
+    return F >= 0 && S >= 0 && R >= 0 && C >= 0 && F <= 65535 && S <= 65535 * 64 &&
+           (long long)S * R < (1LL << 31);
+}
+
+bool born_media_ok(double K0, double rho0)
+{
+    return std::isfinite(K0) && std::isfinite(rho0) && K0 > 0.0 && rho0 > 0.0;
+}
+
+struct BornWs {
+    size_t data, grad, misfit, total;
+};
+
+BornWs born_ws(int F, int S, int R, int C)
+{
+    BornSplit b = born_data_split(F, S, R, C);
+    BornWs w;
+    w.data = align_up((size_t)b.nsplit * F * S * R * 2 * sizeof(float), kAlign);
+    w.grad = align_up((size_t)2 * std::max(b.fsplit, 1) * C * sizeof(float), kAlign);
+    w.misfit = align_up((size_t)misfit_blocks(2LL * F * S * R) * sizeof(float), kAlign);
+    w.total = std::max(w.data, std::max(w.grad, w.misfit));
+    return w;
+}
+
+fwi_status born_work_ok(void *work, size_t bytes, size_t need)
+{
+    if (need == 0)
+        return FWI_OK;
+    if (!work || ((uintptr_t)work % kAlign) != 0 || bytes < need)
+        return fail(FWI_EWORKSPACE, "workspace needs %zu bytes, 256-byte aligned (got %zu)",
+                    need, work ? bytes : (size_t)0);
+    return FWI_OK;
+}
+
+}  // namespace
+
+fwi_status fwi_born_green(int32_t F, const float *omega, int32_t C, const float *cells,
+                          int32_t P, const float *pts, double K0, double rho0, float *G,
+                          float *Gx, float *Gz, void *stream)
+{
+    if (F < 0 || C < 0 || P < 0)
+        return fail(FWI_EINVAL, "negative size");
+    if (!born_media_ok(K0, rho0))
+        return fail(FWI_EINVAL, "K0 and rho0 must be positive and finite");
+    if ((Gx == nullptr) != (Gz == nullptr))
+        return fail(FWI_EINVAL, "Gx and Gz must both be given or both be NULL");
+    const long long n = (long long)F * C * P;
+    if (n == 0)
+        return FWI_OK;
+    if (!omega || !cells || !pts || !G)
+        return fail(FWI_EINVAL, "NULL array");
+    launch_born_green(F, C, P, omega, cells, pts, K0, rho0, G, Gx, Gz, (hipStream_t)stream);
+    return launched("born_green");
+}
+
+size_t fwi_born_workspace_bytes(int32_t F, int32_t S, int32_t R, int32_t C)
+{
+    if (!born_sizes_ok(F, S, R, C))
+        return 0;
+    return born_ws(F, S, R, C).total;
+}
+
+fwi_status fwi_born_data(int32_t F, const float *omega, const float *spec, int32_t S,
+                         int32_t R, int32_t C, double K0, double rho0, double dA,
+                         const float *xiK, const float *xiR, const float *Gs, const float *Gsx,
+                         const float *Gsz, const float *Gr, const float *Grx, const float *Grz,
+                         const float *Gd, float *d, void *work, size_t work_bytes,
+                         void *stream)
+{
+    if (!born_sizes_ok(F, S, R, C))
+        return fail(FWI_EINVAL, "bad sizes (negative, F > 65535, S > 4194240 or S R >= 2^31)");
+    if (!born_media_ok(K0, rho0) || !std::isfinite(dA) || dA <= 0.0)
+        return fail(FWI_EINVAL, "K0, rho0 and dA must be positive and finite");
+    if ((long long)F * S * R == 0)
+        return FWI_OK;
+    if (!omega || !spec || !d)
+        return fail(FWI_EINVAL, "NULL array");
+    if (C > 0 && (!xiK || !xiR || !Gs || !Gsx || !Gsz || !Gr || !Grx || !Grz))
+        return fail(FWI_EINVAL, "NULL contrast or table");
+    BornWs w = born_ws(F, S, R, C);
+    fwi_status st = born_work_ok(work, work_bytes, w.data);
+    if (st != FWI_OK)
+        return st;
+    launch_born_data(born_data_split(F, S, R, C), F, S, R, C, omega, spec, K0, rho0, dA, xiK,
+                     xiR, Gs, Gsx, Gsz, Gr, Grx, Grz, Gd, d, (float *)work,
+                     (hipStream_t)stream);
+    return launched("born_data");
+}
+
+fwi_status fwi_born_misfit(int64_t n, const float *d, const float *q, float *resid, float *J,
+                           void *work, size_t work_bytes, void *stream)
+{
+    if (n < 0 || !J || (n > 0 && (!d || !q)))
+        return fail(FWI_EINVAL, "bad size or NULL array");
+    if (n > (1LL << 40))
+        return fail(FWI_EINVAL, "n too large");
+    const size_t need = align_up((size_t)misfit_blocks(2 * n) * sizeof(float), kAlign);
+    fwi_status st = born_work_ok(work, work_bytes, need);
+    if (st != FWI_OK)
+        return st;
+    launch_misfit(d, q, resid, 2 * n, (float *)work, misfit_blocks(2 * n), J,
+                  (hipStream_t)stream);
+    return launched("born_misfit");
+}
+
+fwi_status fwi_born_gradient(int32_t F, const float *omega, const float *spec, int32_t S,
+                             int32_t R, int32_t C, double K0, double rho0, double dA,
+                             const float *resid, const float *Gs, const float *Gsx,
+                             const float *Gsz, const float *Gr, const float *Grx,
+                             const float *Grz, float *gK, float *gR, void *work,
+                             size_t work_bytes, void *stream)
+{
+    if (!born_sizes_ok(F, S, R, C))
+        return fail(FWI_EINVAL, "bad sizes (negative, F > 65535, S > 4194240 or S R >= 2^31)");
+    if (!born_media_ok(K0, rho0) || !std::isfinite(dA) || dA <= 0.0)
+        return fail(FWI_EINVAL, "K0, rho0 and dA must be positive and finite");
+    if (C == 0)
+        return FWI_OK;
+    if (!gK || !gR)
+        return fail(FWI_EINVAL, "NULL gradient array");
+    const bool any = (long long)F * S * R > 0;
+    if (any && (!omega || !spec || !resid || !Gs || !Gsx || !Gsz || !Gr || !Grx || !Grz))
+        return fail(FWI_EINVAL, "NULL array");
+    BornWs w = born_ws(F, S, R, C);
+    fwi_status st = born_work_ok(work, work_bytes, any ? w.grad : 0);
+    if (st != FWI_OK)
+        return st;
+    launch_born_gradient(born_data_split(F, S, R, C), F, S, R, C, omega, spec, K0, rho0, dA,
+                         resid, Gs, Gsx, Gsz, Gr, Grx, Grz, gK, gR, (float *)work,
+                         (hipStream_t)stream);
+    return launched("born_gradient");
+}
+
+fwi_status fwi_born_contrasts(int32_t scheme, int32_t param, int64_t n, const float *xa,
+                              const float *xb, float *xiK, float *xiR, void *stream)
+{
+    if ((scheme != 1 && scheme != 2) || !valid_param(param) || n < 0 ||
+        (n > 0 && (!xa || !xb || !xiK || !xiR)))
+        return fail(FWI_EINVAL, "bad scheme, parameterization, size or NULL array");
+    launch_born_contrasts(scheme, param, n, xa, xb, xiK, xiR, (hipStream_t)stream);
+    return launched("born_contrasts");
+}
+
+fwi_status fwi_born_chain(int32_t scheme, int32_t param, int64_t n, const float *xa,
+                          const float *xb, const float *gK, const float *gR, float *ga,
+                          float *gb, void *stream)
+{
+    if ((scheme != 1 && scheme != 2) || !valid_param(param) || n < 0 ||
+        (n > 0 && (!gK || !gR || !ga || !gb || (scheme == 2 && (!xa || !xb)))))
+        return fail(FWI_EINVAL, "bad scheme, parameterization, size or NULL array");
+    launch_born_chain(scheme, param, n, xa, xb, gK, gR, ga, gb, (hipStream_t)stream);
+    return launched("born_chain");
+}
+
+fwi_status fwi_born_hessian(int32_t F, const float *omega, const float *spec, int32_t S,
+                            int32_t R, double K0, double rho0, const float *Gs,
+                            const float *Gsx, const float *Gsz, const float *Gr,
+                            const float *Grx, const float *Grz, int32_t param, float *H,
+                            void *stream)
+{
+    if (!born_sizes_ok(F, S, R, 1) || !valid_param(param) || !H)
+        return fail(FWI_EINVAL, "bad sizes, parameterization or NULL output");
+    if (!born_media_ok(K0, rho0))
+        return fail(FWI_EINVAL, "K0 and rho0 must be positive and finite");
+    if ((long long)F * S * R > 0 &&
+        (!omega || !spec || !Gs || !Gsx || !Gsz || !Gr || !Grx || !Grz))
+        return fail(FWI_EINVAL, "NULL array");
+    launch_born_hessian(F, S, R, omega, spec, K0, rho0, Gs, Gsx, Gsz, Gr, Grx, Grz, param, H,
+                        (hipStream_t)stream);
+    return launched("born_hessian");
+}
+
 fwi_status fwi_timing_enable(fwi_plan *p, int32_t enable)
 {
     if (!p)

@@ -221,4 +221,42 @@ void launch_fused_fwd2(const Geo &g, const float *tabs, const float *model,
                        const SweepTables *tab_dev, int S, const Sweep &sw, const FwdStep2 &a,
                        hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 
+
+// ------------------------------------------------------------------ born
+// Decomposition of the Born data and gradient launches.
+struct BornSplit {
+    int ts;               // source chunk width (template instance)
+    int block, rtiles;    // data: receivers per block, receiver tiles
+    int schunks;          // source chunks
+    int nsplit;           // data: cell ranges summed by the finishing kernel
+    int cells_per_split;
+    int cblocks;          // gradient: blocks of 256 cells
+    int fsplit;           // gradient: frequency ranges
+    int freqs_per_split;
+};
+BornSplit born_data_split(int F, int S, int R, int C);
+void launch_born_green(int F, int C, int P, const float *omega, const float *cells,
+                       const float *pts, double K0, double rho0, float *G, float *Gx, float *Gz,
+                       hipStream_t st);
+// part: nsplit * F * S * R complex.
+void launch_born_data(const BornSplit &b, int F, int S, int R, int C, const float *omega,
+                      const float *spec, double K0, double rho0, double dA, const float *xiK,
+                      const float *xiR, const float *Gs, const float *Gsx, const float *Gsz,
+                      const float *Gr, const float *Grx, const float *Grz, const float *Gd,
+                      float *d, float *part, hipStream_t st);
+// part: 2 * fsplit * C floats.
+void launch_born_gradient(const BornSplit &b, int F, int S, int R, int C, const float *omega,
+                          const float *spec, double K0, double rho0, double dA,
+                          const float *resid, const float *Gs, const float *Gsx,
+                          const float *Gsz, const float *Gr, const float *Grx, const float *Grz,
+                          float *gK, float *gR, float *part, hipStream_t st);
+void launch_born_contrasts(int scheme, int param, long long n, const float *xa, const float *xb,
+                           float *xk, float *xr, hipStream_t st);
+void launch_born_chain(int scheme, int param, long long n, const float *xa, const float *xb,
+                       const float *gK, const float *gR, float *ga, float *gb, hipStream_t st);
+void launch_born_hessian(int F, int S, int R, const float *omega, const float *spec, double K0,
+                         double rho0, const float *Gs, const float *Gsx, const float *Gsz,
+                         const float *Gr, const float *Grx, const float *Grz, int param,
+                         float *H, hipStream_t st);
+
 }  // namespace fwi

@@ -263,3 +263,86 @@ def serving_requests(n_requests=200, seed=None, side=(201, 1201), shots=(8, 64),
             "seed": int(rng.integers(0, 2**31 - 1)),
         })
     return out
+
+
+def ricker_spectrum(freqs, fpeak, t0=None):
+    """Fourier transform, int f(t) exp(i w t) dt, of the unit-peak Ricker
+    wavelet delayed by t0 = 1.5 / fpeak, at frequencies `freqs` (Hz):
+    (2 w^2 / (sqrt(pi) wp^3)) exp(-w^2 / wp^2) exp(i w t0), wp = 2 pi fpeak."""
+    t0 = 1.5 / fpeak if t0 is None else t0
+    w = 2.0 * math.pi * np.asarray(freqs, float)
+    wp = 2.0 * math.pi * fpeak
+    return 2.0 * w * w / (math.sqrt(math.pi) * wp ** 3) * np.exp(-(w / wp) ** 2) * \
+        np.exp(1j * w * t0)
+
+
+@dataclass
+class BornWorkload:
+    """A frequency-domain problem around a homogeneous background: cells
+    (nodes of an nz x nx grid), acquisition, frequencies, source spectrum,
+    and the true contrasts (xa, xb) of one parameterization."""
+    name: str
+    nz: int
+    nx: int
+    dz: float
+    dx: float
+    K0: float
+    rho0: float
+    freqs: np.ndarray          # [F] Hz
+    spec: np.ndarray           # [F] complex
+    src_xz: np.ndarray         # [S][2]
+    rec_xz: np.ndarray         # [R][2] (shared by every source)
+    param: str
+    xa: np.ndarray             # [nz][nx]
+    xb: np.ndarray
+
+    @property
+    def omega(self):
+        return 2.0 * math.pi * self.freqs
+
+    @property
+    def cells(self):
+        z, x = np.mgrid[0:self.nz, 0:self.nx]
+        return np.stack([x.ravel() * self.dx, z.ravel() * self.dz], axis=1)
+
+    @property
+    def dA(self):
+        return self.dx * self.dz
+
+    def sizes(self):
+        return dict(F=len(self.freqs), S=len(self.src_xz), R=len(self.rec_xz),
+                    C=self.nz * self.nx)
+
+
+def born_config1(nf=32):
+    """Frequency-domain form of config 1: 101 x 101 cells at 5 m,
+    background 2000 m/s and 2000 kg/m^3, +10 % K at the centre cell, one
+    source 150 m above it, 180 receivers on a 200 m ring, nf frequencies
+    2, 4, ... Hz of a 25 Hz Ricker wavelet."""
+    nz = nx = 101
+    xa = np.zeros((nz, nx))
+    xa[50, 50] = 0.1
+    freqs = 2.0 * np.arange(1, nf + 1)
+    return BornWorkload("born-c1-point-101", nz, nx, 5.0, 5.0, 2000.0 * 2000.0 ** 2, 2000.0,
+                        freqs, ricker_spectrum(freqs, 25.0), np.array([[250.0, 100.0]]),
+                        ring(180, 200.0, 250.0, 250.0), "k-rho", xa, np.zeros((nz, nx)))
+
+
+def born_config2(nf=32, seed=None):
+    """Frequency-domain form of config 2: 401 x 401 cells at 5 m, the same
+    seeded Gaussian Vp contrast at fixed density, 40 sources and 360
+    receivers on an 800 m ring, nf frequencies 2, 4, ... Hz of a 25 Hz
+    Ricker wavelet."""
+    w = config2(seed)
+    xa = w.vp_true / w.vp_start - 1.0
+    freqs = 2.0 * np.arange(1, nf + 1)
+    return BornWorkload("born-c2-gauss-401", w.nz, w.nx, w.dz, w.dx, 2000.0 * 2000.0 ** 2,
+                        2000.0, freqs, ricker_spectrum(freqs, 25.0), w.src_xz,
+                        np.ascontiguousarray(w.rec_xz[0]), "vp-rho", xa,
+                        np.zeros((w.nz, w.nx)))
+
+
+def point_ring(n_src, n_rec, radius, x0=(0.0, 0.0)):
+    """Sources and receivers evenly on a circle around x0 (the circular
+    acquisition of the point-scatterer analysis)."""
+    return ring(n_src, radius, x0[0], x0[1]), ring(n_rec, radius, x0[0], x0[1], offset=0.5)

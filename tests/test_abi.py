@@ -112,3 +112,40 @@ def test_weighted_misfit_validates_plan_and_arrays():
     lib = L.lib()
     p = ctypes.c_void_p(16)
     assert lib.fwi_misfit_weighted(None, p, p, p, None, p, None, 0, None) == -1
+
+
+def test_born_argument_validation():
+    lib = L.lib()
+    buf = np.zeros(64, np.float32)
+    p = ctypes.c_void_p(buf.ctypes.data)
+    K0, rho0 = 8e9, 2000.0
+    # negative size, non-positive medium, Gx without Gz
+    assert lib.fwi_born_green(-1, p, 1, p, 1, p, K0, rho0, p, p, p, None) == -1
+    assert lib.fwi_born_green(1, p, 1, p, 1, p, 0.0, rho0, p, p, p, None) == -1
+    assert lib.fwi_born_green(1, p, 1, p, 1, p, K0, float("nan"), p, p, p, None) == -1
+    assert lib.fwi_born_green(1, p, 1, p, 1, p, K0, rho0, p, p, None, None) == -1
+    assert lib.fwi_born_green(1, None, 1, p, 1, p, K0, rho0, p, None, None, None) == -1
+    assert lib.fwi_born_green(0, None, 1, None, 1, None, K0, rho0, None, None, None, None) == 0
+    assert lib.fwi_born_workspace_bytes(-1, 1, 1, 1) == 0
+    assert lib.fwi_born_workspace_bytes(70000, 1, 1, 1) == 0
+    need = lib.fwi_born_workspace_bytes(2, 3, 70, 300)
+    assert need > 0 and need % 256 == 0
+    args = [2, p, p, 3, 70, 300, K0, rho0, 25.0] + [p] * 10
+    # workspace missing or too small: refused before any launch
+    assert lib.fwi_born_data(*args, None, need, None) == -7
+    assert lib.fwi_born_data(*args, p, need - 256, None) == -7
+    assert lib.fwi_born_data(2, p, p, 3, 70, 300, K0, rho0, -1.0, *([p] * 10), p, need,
+                             None) == -1
+    assert lib.fwi_born_data(2, p, p, 3, 70, 300, K0, rho0, 25.0, None, *([p] * 9), p, need,
+                             None) == -1
+    assert lib.fwi_born_gradient(2, p, p, 3, 70, 300, K0, rho0, 25.0, *([p] * 9), None, need,
+                                 None) == -7
+    assert lib.fwi_born_gradient(2, p, p, 3, 70, 300, K0, rho0, 25.0, *([p] * 7), None, p, p,
+                                 need, None) == -1
+    assert lib.fwi_born_misfit(-1, p, p, p, p, p, 256, None) == -1
+    assert lib.fwi_born_misfit(100, p, p, p, p, None, 0, None) == -7
+    assert lib.fwi_born_contrasts(3, 0, 1, p, p, p, p, None) == -1
+    assert lib.fwi_born_contrasts(1, 5, 1, p, p, p, p, None) == -1
+    assert lib.fwi_born_chain(2, 1, 1, None, p, p, p, p, p, None) == -1
+    assert lib.fwi_born_hessian(1, p, p, 1, 1, K0, rho0, *([p] * 6), 7, p, None) == -1
+    assert lib.fwi_born_hessian(1, p, p, 1, 1, K0, rho0, *([p] * 6), 0, None, None) == -1

@@ -1,0 +1,227 @@
+"""Schemes I and II (Born modelling) on the GPU against the FP64 oracle
+(oracle/born.py), through the C ABI.
+
+Error measure: max |gpu - oracle| / max |oracle| per array.  Bounds: 1e-5
+for the Green tables (FP64 Hankel functions rounded to FP32), 1e-4 for data,
+gradients and the reduced Hessian (FP32 sums over cells, sources and
+receivers), 1e-5 for the elementwise maps.  The oracle takes the same
+FP32-rounded inputs (positions, frequencies, spectrum, contrasts, residual)
+in FP64.  Shapes cover every source-chunk width of the kernels, ragged
+receiver tiles, cell chunks and cell blocks, more than 64 sources, and the
+full frequency-domain config-2 problem on sampled outputs plus the adjoint
+dot product."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import born as OB
+from paper_1804_01184_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+K0, RHO0 = 2000.0 * 2000.0 ** 2, 2000.0
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1804_01184_amd import born
+    torch.cuda.set_device(0)
+    return torch, born
+
+
+def maxrel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def f32(x):
+    return np.asarray(x, np.float32).astype(np.float64)
+
+
+def c64(x):
+    return np.asarray(x, np.complex64).astype(np.complex128)
+
+
+def problem(seed, F, S, R, C):
+    """Cells on a 5 m patch around the origin, sources and receivers on
+    rings of 200-400 m, frequencies 3-60 Hz (k r from 0.01 to 75: both
+    branches of the Hankel evaluation), contrasts within +-0.2."""
+    rng = np.random.default_rng(seed)
+    n = max(1, int(math.ceil(math.sqrt(C))))
+    z, x = np.divmod(np.arange(C), n)
+    cells = np.stack([x * 5.0 - 100.0, z * 5.0 - 100.0], axis=1)
+    th_s = rng.uniform(0, 2 * math.pi, S)
+    th_r = rng.uniform(0, 2 * math.pi, R)
+    src = np.stack([300 * np.cos(th_s), 300 * np.sin(th_s)], axis=1)
+    rr = rng.uniform(200, 400, R)
+    rec = np.stack([rr * np.cos(th_r), rr * np.sin(th_r)], axis=1)
+    freqs = np.sort(rng.uniform(3.0, 60.0, F))
+    spec = W.ricker_spectrum(freqs, 25.0)
+    xiK = rng.uniform(-0.2, 0.2, C)
+    xiR = rng.uniform(-0.2, 0.2, C)
+    return dict(omega=f32(2 * math.pi * freqs), spec=c64(spec), src=f32(src), rec=f32(rec),
+                cells=f32(cells), xiK=f32(xiK), xiR=f32(xiR), dA=25.0)
+
+
+def gpu_problem(born, p):
+    return born.BornProblem(p["omega"], p["spec"], p["src"], p["rec"], p["cells"], p["dA"],
+                            K0, RHO0)
+
+
+def test_green_tables_match_oracle(env):
+    torch, born = env
+    p = problem(1, 4, 3, 50, 200)
+    # one receiver on a cell centre: the singular self term is left out
+    p["rec"][7] = p["cells"][123]
+    prob = gpu_problem(born, p)
+    ref = OB.green(p["omega"], p["rec"], p["cells"], K0, RHO0)      # [F][R][C]
+    for g, r in zip(prob.Gr, ref):
+        g = g.cpu().numpy().transpose(0, 2, 1).astype(np.complex128)     # -> [F][R][C]
+        assert np.all(g[:, 7, 123] == 0) and np.all(r[:, 7, 123] == 0)
+        assert maxrel(g, r) <= 1e-5
+        # per frequency too (amplitudes fall with frequency for the gradient)
+        for f in range(g.shape[0]):
+            assert maxrel(g[f], r[f]) <= 1e-5
+    ref_s = OB.green(p["omega"], p["src"], p["cells"], K0, RHO0)
+    for g, r in zip(prob.Gs, ref_s):
+        assert maxrel(g.cpu().numpy().transpose(0, 2, 1), r) <= 1e-5
+    gd = OB.direct(p["omega"], p["src"], p["rec"], K0, RHO0)
+    assert maxrel(prob.Gd.cpu().numpy(), gd) <= 1e-5
+
+
+SHAPES = [(3, 1, 70, 300), (2, 3, 37, 529), (2, 17, 64, 1000), (1, 41, 130, 777),
+          (2, 70, 20, 400), (5, 8, 200, 33)]
+
+
+@pytest.mark.parametrize("F,S,R,C", SHAPES)
+def test_data_and_gradient_match_oracle(env, F, S, R, C):
+    torch, born = env
+    p = problem(F * 1000 + S * 10 + R + C, F, S, R, C)
+    prob = gpu_problem(born, p)
+    args = (p["omega"], p["spec"], p["src"], p["rec"], p["cells"], p["dA"], K0, RHO0)
+    xK = torch.tensor(p["xiK"], dtype=torch.float32, device="cuda")
+    xR = torch.tensor(p["xiR"], dtype=torch.float32, device="cuda")
+    d = prob.data(xK, xR, direct=False).cpu().numpy()
+    ref = p["spec"][:, None, None] * OB.scattered(p["omega"], p["src"], p["rec"], p["cells"],
+                                                  p["dA"], K0, RHO0, p["xiK"], p["xiR"])
+    assert maxrel(d, ref) <= 1e-4
+    full = prob.data(xK, xR).cpu().numpy()
+    assert maxrel(full, OB.data(*args, p["xiK"], p["xiR"])) <= 1e-4
+    rng = np.random.default_rng(C)
+    res = c64(rng.standard_normal((F, S, R)) + 1j * rng.standard_normal((F, S, R)))
+    gK, gR = prob.gradient(torch.tensor(res.astype(np.complex64), device="cuda"))
+    rK, rR = OB.gradient(*args[:5], p["dA"], K0, RHO0, res)
+    assert maxrel(gK.cpu().numpy(), rK) <= 1e-4
+    assert maxrel(gR.cpu().numpy(), rR) <= 1e-4
+    # bitwise repeatable
+    assert np.array_equal(prob.data(xK, xR, direct=False).cpu().numpy(), d)
+    gK2, _ = prob.gradient(torch.tensor(res.astype(np.complex64), device="cuda"))
+    assert torch.equal(gK, gK2)
+
+
+def test_misfit(env):
+    torch, born = env
+    p = problem(4, 2, 3, 20, 50)
+    prob = gpu_problem(born, p)
+    rng = np.random.default_rng(4)
+    d = (rng.standard_normal((2, 3, 20)) + 1j * rng.standard_normal((2, 3, 20))).astype(np.complex64)
+    q = (rng.standard_normal((2, 3, 20)) + 1j * rng.standard_normal((2, 3, 20))).astype(np.complex64)
+    J, r = prob.misfit(torch.tensor(d, device="cuda"), torch.tensor(q, device="cuda"))
+    Jr, rr = OB.misfit(c64(d), c64(q))
+    assert float(J.item()) == pytest.approx(Jr, rel=1e-5)
+    assert maxrel(r.cpu().numpy(), rr) <= 1e-6
+
+
+def test_edge_cases(env):
+    torch, born = env
+    p = problem(5, 2, 3, 10, 0)
+    prob = gpu_problem(born, p)
+    e = torch.zeros(0, device="cuda")
+    d = prob.data(e, e).cpu().numpy()           # no cells: the direct wave
+    ref = p["spec"][:, None, None] * OB.direct(p["omega"], p["src"], p["rec"], K0, RHO0)
+    assert maxrel(d, ref) <= 1e-5
+    # no sources: gradient zero
+    q = problem(6, 2, 1, 10, 40)
+    q["src"] = q["src"][:0]
+    pr = gpu_problem(born, q)
+    gK, gR = pr.gradient(torch.zeros((2, 0, 10), dtype=torch.complex64, device="cuda"))
+    assert float(gK.abs().max()) == 0.0 and float(gR.abs().max()) == 0.0
+    assert pr.data(torch.zeros(40, device="cuda"), torch.zeros(40, device="cuda")).numel() == 0
+
+
+@pytest.mark.parametrize("scheme", [1, 2])
+@pytest.mark.parametrize("param", range(5))
+def test_contrast_maps_and_chain(env, scheme, param):
+    torch, born = env
+    rng = np.random.default_rng(10 * scheme + param)
+    xa, xb = f32(rng.uniform(-0.3, 0.3, 1000)), f32(rng.uniform(-0.3, 0.3, 1000))
+    gK, gR = f32(rng.standard_normal(1000)), f32(rng.standard_normal(1000))
+    t = [torch.tensor(v, dtype=torch.float32, device="cuda") for v in (xa, xb, gK, gR)]
+    k, r = born.contrasts(scheme, param, t[0], t[1])
+    rk, rr = OB.to_inverse_contrasts(scheme, param, xa, xb, K0, RHO0)
+    assert maxrel(k.cpu().numpy(), rk) <= 1e-5
+    assert maxrel(r.cpu().numpy(), rr) <= 1e-5
+    ga, gb = born.chain(scheme, param, *t)
+    ra, rb = OB.chain(scheme, param, xa, xb, gK, gR, K0, RHO0)
+    assert maxrel(ga.cpu().numpy(), ra) <= 1e-5
+    assert maxrel(gb.cpu().numpy(), rb) <= 1e-5
+
+
+@pytest.mark.parametrize("param", range(5))
+def test_reduced_hessian_matches_oracle(env, param):
+    torch, born = env
+    src, rec = W.point_ring(12, 90, 490.0)
+    src, rec = f32(src), f32(rec)
+    freqs = np.array([5.0, 12.0, 25.0, 40.0])
+    om, sp = f32(2 * math.pi * freqs), c64(W.ricker_spectrum(freqs, 25.0))
+    H = born.reduced_hessian(om, sp, src, rec, (0.0, 0.0), K0, RHO0, param)
+    ref = OB.reduced_hessian(om, sp, src, rec, (0.0, 0.0), K0, RHO0, param)
+    assert maxrel(H, ref) <= 1e-4
+
+
+@pytest.fixture(scope="module")
+def config2(env):
+    torch, born = env
+    w = W.born_config2()
+    prob = born.BornProblem.of(w)
+    return w, prob
+
+
+def test_full_size_sampled_outputs_and_dot_product(env, config2):
+    torch, born = env
+    w, prob = config2
+    sz = w.sizes()
+    F, S, R, C = sz["F"], sz["S"], sz["R"], sz["C"]
+    xa = torch.tensor(w.xa.ravel(), dtype=torch.float32, device="cuda")
+    xb = torch.tensor(w.xb.ravel(), dtype=torch.float32, device="cuda")
+    xK, xR = born.contrasts(2, w.param, xa, xb)
+    d = prob.data(xK, xR, direct=False).cpu().numpy()
+    om, sp = f32(w.omega), c64(w.spec)
+    src, rec, cells = f32(w.src_xz), f32(w.rec_xz), f32(w.cells)
+    xKn, xRn = f32(xK.cpu().numpy()), f32(xR.cpu().numpy())
+    rng = np.random.default_rng(2)
+    picks = [(F - 1, 0, 0), (0, S - 1, R - 1)] + [
+        (int(rng.integers(F)), int(rng.integers(S)), int(rng.integers(R))) for _ in range(4)]
+    scale = np.abs(d).max()
+    for f, s, r in picks:
+        ref = sp[f] * OB.scattered(om[f:f + 1], src[s:s + 1], rec[r:r + 1], cells, w.dA,
+                                   w.K0, w.rho0, xKn, xRn)[0, 0, 0]
+        assert abs(d[f, s, r] - ref) <= 1e-4 * scale, (f, s, r)
+    # gradient at sampled cells for a seeded residual
+    res = c64((rng.standard_normal((F, S, R)) + 1j * rng.standard_normal((F, S, R))) * scale)
+    gK, gR = prob.gradient(torch.tensor(res.astype(np.complex64), device="cuda"))
+    gK, gR = gK.cpu().numpy(), gR.cpu().numpy()
+    idx = np.concatenate([[0, C - 1, C // 2], rng.integers(0, C, 5)])
+    rK, rR = OB.gradient(om, sp, src, rec, cells[idx], w.dA, w.K0, w.rho0, res)
+    assert np.abs(gK[idx] - rK).max() <= 1e-4 * np.abs(gK).max()
+    assert np.abs(gR[idx] - rR).max() <= 1e-4 * np.abs(gR).max()
+    # adjoint: <L xi, res> = xiK . gK + xiR . gR
+    lhs = float(np.real(np.sum(np.conj(res) * d.astype(np.complex128))))
+    rhs = float(np.dot(xKn, gK.astype(np.float64)) + np.dot(xRn, gR.astype(np.float64)))
+    assert lhs == pytest.approx(rhs, rel=1e-4)
