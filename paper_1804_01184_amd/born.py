@@ -169,6 +169,39 @@ def reduced_hessian(omega, spec, src_xz, rec_xz, x0, K0, rho0, param, device=Non
     return (h[0::2] + 1j * h[1::2]).reshape(2, 2)
 
 
+def descent(prob, scheme, param, observed, iters, mask=None, direct=True, **kw):
+    """Steepest descent over the contrasts (xa, xb) of `param` from zero
+    (the homogeneous background), with Born modelling through the scheme's
+    map (scheme 1 linear, scheme 2 exact) against `observed` [F][S][R]
+    complex; the step-length rule of inversion.descend.  direct=False:
+    `observed` holds scattered data only and the modelled data leave out
+    the direct wave too (the same residual without the FP32 cancellation of
+    the direct wave).  Returns its DescentResult (m1, m2: the final
+    contrasts)."""
+    from . import inversion
+    dev = prob.device
+    ones = torch.ones(prob.C, dtype=torch.float32, device=dev)
+    zero = torch.zeros_like(ones)
+    q = observed.contiguous()
+    mk = mask.to(device=dev, dtype=torch.float32).reshape(-1).contiguous() \
+        if mask is not None else None
+    d = torch.empty((prob.F, prob.S, prob.R), dtype=torch.complex64, device=dev)
+
+    def grad_fn(xa, xb):
+        prob.data(*contrasts(scheme, param, xa, xb), direct=direct, out=d)
+        J, r = prob.misfit(d, q)
+        gK, gR = prob.gradient(r)
+        ga, gb = chain(scheme, param, xa, xb, gK, gR)
+        return J, ga, gb
+
+    def value_fn(xa, xb):
+        prob.data(*contrasts(scheme, param, xa, xb), direct=direct, out=d)
+        return prob.misfit(d, q, residual=False)[0]
+
+    return inversion.descend(grad_fn, value_fn, ones, ones, iters, mask=mk,
+                             start=(zero, zero), **kw)
+
+
 def hessian_summary(H):
     """Eigen-analysis of the Gauss-Newton Hessian Re H: eigenvalues,
     condition number, angle of the principal eigenvector (degrees in
@@ -242,6 +275,48 @@ def hessians(w, n_src=36, n_rec=180, radius=490.0, device=None):
                                                w.rho0, p, device)) for p in PARAMS}
 
 
+def invert_point(w, iters, device=None):
+    """Schemes I and II on a point scatterer whose position is known (only
+    its cell is updated): observed data from the true contrasts through the
+    exact map (both schemes), misfit per iteration in each
+    parameterization, and the contrasts reached."""
+    dev = torch.device(device) if device is not None else torch.device(
+        "cuda", torch.cuda.current_device())
+    prob = BornProblem.of(w, dev)
+    xa = _f32(w.xa.ravel(), dev)
+    xb = _f32(w.xb.ravel(), dev)
+    q = prob.data(*contrasts(2, w.param, xa, xb), direct=False)
+    c = int(np.argmax(np.abs(w.xa.ravel()) + np.abs(w.xb.ravel())))
+    mask = torch.zeros(prob.C, dtype=torch.float32, device=dev)
+    mask[c] = 1.0
+    # true contrasts of the scatterer in each parameterization, from the
+    # exact map of the workload's parameterization (host FP64 arithmetic on
+    # two scalars: K/K0 and rho/rho0)
+    a0, b0 = float(w.xa.ravel()[c]), float(w.xb.ravel()[c])
+    kr = {"k-rho": (1 + a0, 1 + b0), "vp-rho": ((1 + a0) ** 2 * (1 + b0), 1 + b0),
+          "ip-rho": ((1 + a0) ** 2 / (1 + b0), 1 + b0),
+          "vp-ip": ((1 + a0) * (1 + b0), (1 + b0) / (1 + a0)),
+          "invk-invrho": (1 / (1 + a0), 1 / (1 + b0))}[w.param]
+    k, r = kr
+    true = {"k-rho": (k - 1, r - 1), "vp-rho": (math.sqrt(k / r) - 1, r - 1),
+            "ip-rho": (math.sqrt(k * r) - 1, r - 1),
+            "vp-ip": (math.sqrt(k / r) - 1, math.sqrt(k * r) - 1),
+            "invk-invrho": (1 / k - 1, 1 / r - 1)}
+    out = {"workload": w.name, "iters": iters, "scatterer_cell": c}
+    for scheme in (1, 2):
+        rec = {}
+        for p in PARAMS:
+            res = descent(prob, scheme, p, q, iters, mask=mask, direct=False)
+            rec[p] = {"J": [float(x) for x in res.J],
+                      "J_final_over_J0": float(res.J[-1] / res.J[0]),
+                      "contrast": [float(res.m1[c]), float(res.m2[c])],
+                      "true_contrast": list(true[p]), "stopped": res.stopped}
+            print(f"scheme {scheme} {p}: J/J0 {rec[p]['J_final_over_J0']:.2e} after "
+                  f"{len(res.alpha)} steps", file=sys.stderr, flush=True)
+        out[f"scheme_{scheme}"] = rec
+    return out
+
+
 def main(argv=None):
     import argparse
     from . import workloads as W
@@ -249,7 +324,14 @@ def main(argv=None):
     ap.add_argument("--workload", default="c2", choices=["c1", "c2"])
     ap.add_argument("--freqs", type=int, default=32)
     ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--invert", type=int, default=0, metavar="ITERS",
+                    help="instead: schemes I and II steepest descent on scatterer (i) "
+                         "(frequency-domain config 1, shape known) for ITERS iterations")
     a = ap.parse_args(argv)
+    if a.invert:
+        torch.cuda.set_device(0)
+        print(json.dumps(invert_point(W.born_config1(a.freqs), a.invert)), flush=True)
+        return
     torch.cuda.set_device(0)
     w = W.born_config2(a.freqs) if a.workload == "c2" else W.born_config1(a.freqs)
     out = measure(w, a.reps)

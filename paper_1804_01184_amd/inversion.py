@@ -60,32 +60,30 @@ class DescentResult:
     stopped: bool = False                       # no step lowered the misfit
 
 
-def steepest_descent(plan, param, m1, m2, wavelet, observed, iters, mask=None, tau=0.01,
-                     grow=4.0, max_ratio=10.0, backtracks=5):
-    """Runs `iters` iterations from the model (m1, m2) (which also defines
-    the contrasts); returns a DescentResult with the final model."""
-    dev = plan.device
-    m0a = api._dev_f32(m1, dev).clone()
-    m0b = api._dev_f32(m2, dev).clone()
-    w = api._dev_f32(wavelet, dev)
-    obs = api._dev_f32(observed, dev)
-    mk = api._dev_f32(mask, dev) if mask is not None else None
-    ma, mb = m0a.clone(), m0b.clone()
+def descend(grad_fn, value_fn, m0a, m0b, iters, mask=None, start=None, tau=0.01, grow=4.0,
+            max_ratio=10.0, backtracks=5):
+    """The loop above over any objective: grad_fn(ma, mb) -> (J [1] device,
+    dJ/dma, dJ/dmb); value_fn(ma, mb) -> J [1] device.  The contrasts are
+    taken relative to (m0a, m0b) (d = -m0 g; iterate m + alpha m0 d); the
+    iterate starts at `start` (default m0).  Returns a DescentResult."""
+    mk = mask
+    if start is None:
+        ma, mb = m0a.clone(), m0b.clone()
+    else:
+        ma, mb = start[0].clone(), start[1].clone()
     ta, tb = torch.empty_like(ma), torch.empty_like(mb)
     res = DescentResult()
 
     def value(a, da, db):
         api.descent_apply(ma, m0a, da, a, out=ta)
         api.descent_apply(mb, m0b, db, a, out=tb)
-        tr = plan.forward(param, ta, tb, w)
-        J, _ = plan.misfit(tr, obs, residual=False)
         res.forwards += 1
-        v = float(J.item())
+        v = float(value_fn(ta, tb).item())
         return v if math.isfinite(v) else math.inf
 
     trial = None
     for _ in range(iters):
-        Jk, ga, gb = plan.gradient(param, ma, mb, w, obs)
+        Jk, ga, gb = grad_fn(ma, mb)
         res.gradients += 1
         J0 = float(Jk.item())
         if not res.J:
@@ -124,6 +122,26 @@ def steepest_descent(plan, param, m1, m2, wavelet, observed, iters, mask=None, t
         trial = a
     res.m1, res.m2 = ma, mb
     return res
+
+
+def steepest_descent(plan, param, m1, m2, wavelet, observed, iters, mask=None, **kw):
+    """Runs `iters` iterations from the model (m1, m2) (which also defines
+    the contrasts); returns a DescentResult with the final model."""
+    dev = plan.device
+    m0a = api._dev_f32(m1, dev).clone()
+    m0b = api._dev_f32(m2, dev).clone()
+    w = api._dev_f32(wavelet, dev)
+    obs = api._dev_f32(observed, dev)
+    mk = api._dev_f32(mask, dev) if mask is not None else None
+
+    def grad_fn(ma, mb):
+        return plan.gradient(param, ma, mb, w, obs)
+
+    def value_fn(ta, tb):
+        tr = plan.forward(param, ta, tb, w)
+        return plan.misfit(tr, obs, residual=False)[0]
+
+    return descend(grad_fn, value_fn, m0a, m0b, iters, mask=mk, **kw)
 
 
 # ------------------------------------------------------------ measurement
