@@ -226,6 +226,8 @@ void launch_fused_fwd2(const Geo &g, const float *tabs, const float *model,
 // Decomposition of the Born data and gradient launches.
 struct BornSplit {
     int ts;               // source chunk width (template instance)
+    int ns;               // data on the matrix cores: 16-wide source tiles per wave (0: off)
+    int nrg, sgroups;     // matrix-core data: 32-receiver groups, source groups
     int block, rtiles;    // data: receivers per block, receiver tiles
     int schunks;          // source chunks
     int nsplit;           // data: cell ranges summed by the finishing kernel

@@ -208,6 +208,153 @@ __global__ __launch_bounds__(512) void k_born_data(int F, int S, int R, int C, i
             out[(long long)(s0 + s) * R + r] = acc[s];
 }
 
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// The same partial sums on the matrix cores: per frequency and cell range,
+// D[r][s] = sum_k A[k][r] B[k][s] with k running over (table, cell) and
+// complex entries, A = coefficient x receiver table, B = source table.
+// v_mfma_f32_16x16x4f32 takes A[i][k] from lane 16k + i, B[k][j] from lane
+// 16k + j and leaves D[4 (l / 16) + v][l % 16] in register v of lane l.  A
+// complex product is two real ones over k = (cell pair) x (re, im part):
+// lanes 0-31 carry two cells' real parts, lanes 32-63 their imaginary
+// parts, so that Re D = sum ar br - ai bi and Im D = sum ar bi + ai br.
+// A wave computes 32 receivers x 16 NS sources; the four waves of a block
+// take consecutive receiver groups of one (frequency, cell range, source
+// group), and blocks are remapped so that those of one cell range run on
+// one XCD (its L2 serves the shared source tables).
+template <int NS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_born_data_mfma(
+    int F, int S, int R, int C, int nsplit, int cells_per_split, int sgroups, int nrg,
+    long long nblocks, const float *omega, float dA_K0, float cR, const float *xiK,
+    const float *xiR, const float2 *Gs, const float2 *Gsx, const float2 *Gsz, const float2 *Gr,
+    const float2 *Grx, const float2 *Grz, float2 *part)
+{
+    const long long per = (nblocks + 7) / 8;
+    const long long w = (long long)(blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (w >= nblocks)
+        return;
+    const int bpr = (nrg + 3) / 4;
+    const int rb = (int)(w % bpr);
+    long long fsg = w / bpr;
+    const int sg = (int)(fsg % sgroups);
+    fsg /= sgroups;
+    const int split = (int)(fsg % nsplit);
+    const int f = (int)(fsg / nsplit);
+    const int rg = rb * 4 + (int)(threadIdx.x >> 6);
+    if (rg >= nrg)
+        return;
+    const int l = threadIdx.x & 63;
+    const int li = l & 15, kk = l >> 4, cpar = kk & 1;
+    const bool second = kk >= 2;
+    const int r0 = rg * 32, s0 = sg * 16 * NS;
+    int rA[2], sB[NS];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+        rA[t] = min(r0 + 16 * t + li, R - 1);
+#pragma unroll
+    for (int t = 0; t < NS; ++t)
+        sB[t] = min(s0 + 16 * t + li, S - 1);
+    const int c_begin = split * cells_per_split;
+    const int c_end = min(C, c_begin + cells_per_split);
+    const float wf = omega[f];
+    const float aK = wf * wf * dA_K0;
+    v4f dre[2][NS], dim[2][NS];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < NS; ++b) {
+            dre[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+            dim[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+        }
+    // operands of one cell pair: the receiver-table part this lane needs
+    // (real part in lanes 0-31, imaginary part in lanes 32-63) and the full
+    // source-table value; two pairs in flight, loaded one pair ahead of the
+    // products.  A pair past the range loads the last cell and weighs 0.
+    struct Pair {
+        float a[3][2];
+        float2 b[3][NS];
+        float xk, xr;
+        bool ok;
+    };
+    const int part_off = second ? 1 : 0;
+    const float *Gr1 = (const float *)Gr, *Grx1 = (const float *)Grx, *Grz1 = (const float *)Grz;
+    auto load = [&](int c0, Pair &P) {
+        P.ok = c0 + cpar < c_end;
+        const int c = P.ok ? c0 + cpar : c_end - 1;
+        P.xk = xiK[c];
+        P.xr = xiR[c];
+        const long long oA = ((long long)f * C + c) * R, oB = ((long long)f * C + c) * S;
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            const long long o = 2 * (oA + rA[a]) + part_off;
+            P.a[0][a] = Gr1[o];
+            P.a[1][a] = Grx1[o];
+            P.a[2][a] = Grz1[o];
+        }
+#pragma unroll
+        for (int b = 0; b < NS; ++b) {
+            P.b[0][b] = Gs[oB + sB[b]];
+            P.b[1][b] = Gsx[oB + sB[b]];
+            P.b[2][b] = Gsz[oB + sB[b]];
+        }
+    };
+    auto product = [&](const Pair &P) {
+        const float qK = P.ok ? aK * P.xk : 0.f;
+        const float qR = P.ok ? cR * P.xr : 0.f;
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            const float q = t == 0 ? qK : qR;
+            float aRe[2], aIm[2], bRe[NS], bIm[NS];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                const float v = q * P.a[t][a];
+                aRe[a] = second ? -v : v;
+                aIm[a] = v;
+            }
+#pragma unroll
+            for (int b = 0; b < NS; ++b) {
+                bRe[b] = second ? P.b[t][b].y : P.b[t][b].x;
+                bIm[b] = second ? P.b[t][b].x : P.b[t][b].y;
+            }
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < NS; ++b) {
+                    dre[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(aRe[a], bRe[b], dre[a][b],
+                                                                     0, 0, 0);
+                    dim[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(aIm[a], bIm[b], dim[a][b],
+                                                                     0, 0, 0);
+                }
+        }
+    };
+    Pair P0, P1;
+    load(c_begin, P0);
+    // the scheduling barriers keep each pair's loads ahead of the other
+    // pair's products (left alone, the scheduler sinks them next to their
+    // uses and the products wait on fresh loads)
+    for (int c0 = c_begin; c0 < c_end; c0 += 4) {
+        load(c0 + 2, P1);
+        __builtin_amdgcn_sched_barrier(0);
+        product(P0);
+        __builtin_amdgcn_sched_barrier(0);
+        load(c0 + 4, P0);
+        __builtin_amdgcn_sched_barrier(0);
+        product(P1);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    float2 *out = part + ((long long)split * F + f) * S * R;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < NS; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = r0 + 16 * a + 4 * kk + v, sc = s0 + 16 * b + li;
+                if (r < R && sc < S)
+                    out[(long long)sc * R + r] = make_float2(dre[a][b][v], dim[a][b][v]);
+            }
+}
+
 // d[f][s][r] = spec[f] (Gd[f][s][r] + sum_split part[split][f][s][r]);
 // Gd may be null (scattered data only).
 __global__ __launch_bounds__(256) void k_born_finish(long long n, int SR, int nsplit,
@@ -546,13 +693,37 @@ BornSplit born_data_split(int F, int S, int R, int C)
 {
     BornSplit b;
     b.ts = born_ts(S);
-    const int nw = std::max(1, std::min(8, (R + 63) / 64));
-    b.block = 64 * nw;
-    b.rtiles = (R + b.block - 1) / b.block;
-    b.schunks = (S + b.ts - 1) / b.ts;
-    const long long base = (long long)F * b.rtiles * b.schunks;
-    const int max_split = std::max(1, (C + kCB - 1) / kCB);
-    long long want = base > 0 ? (2048 + base - 1) / base : 1;
+    // matrix-core path from 12 sources: 16-wide source tiles
+    b.ns = S >= 12 ? std::min(4, (S + 15) / 16) : 0;
+    int step = kCB;
+    long long base;
+    long long target;
+    if (b.ns) {
+        b.nrg = (R + 31) / 32;
+        b.sgroups = (S + 16 * b.ns - 1) / (16 * b.ns);
+        base = (long long)F * b.sgroups * b.nrg;       // waves per cell range
+        target = 16384;
+        step = 2;
+        b.block = 256;
+        b.rtiles = b.schunks = 0;
+    } else {
+        const int nw = std::max(1, std::min(8, (R + 63) / 64));
+        b.block = 64 * nw;
+        b.rtiles = (R + b.block - 1) / b.block;
+        b.schunks = (S + b.ts - 1) / b.ts;
+        base = (long long)F * b.rtiles * b.schunks;   // blocks per cell range
+        target = 2048;
+        b.nrg = b.sgroups = 0;
+    }
+    const int max_split = std::max(1, (C + step - 1) / step);
+    long long want = base > 0 ? (target + base - 1) / base : 1;
+    if (b.ns && base > 0) {
+        // whole rounds of resident blocks: 256 CUs x 4 blocks of 4 waves
+        // (4 waves per SIMD); 8 rounds, rounded down so that the last round
+        // is full rather than nearly empty
+        const long long cap = 256LL * 4 * 8, blocks_per_range = base / b.nrg * ((b.nrg + 3) / 4);
+        want = std::max(1LL, cap / std::max(1LL, blocks_per_range));
+    }
     b.nsplit = (int)std::max(1LL, std::min<long long>(want, max_split));
     if (C == 0)
         b.nsplit = 0;
@@ -569,6 +740,19 @@ BornSplit born_data_split(int F, int S, int R, int C)
     if (F > 0)
         b.fsplit = (F + b.freqs_per_split - 1) / b.freqs_per_split;
     return b;
+}
+
+template <int NS>
+static void data_mfma(const BornSplit &b, int F, int S, int R, int C, const float *omega,
+                      float dA_K0, float cR, const float *xiK, const float *xiR,
+                      const float2 *Gs, const float2 *Gsx, const float2 *Gsz, const float2 *Gr,
+                      const float2 *Grx, const float2 *Grz, float2 *part, hipStream_t st)
+{
+    const long long nblocks = (long long)F * b.nsplit * b.sgroups * ((b.nrg + 3) / 4);
+    const long long grid = (nblocks + 7) / 8 * 8;
+    hipLaunchKernelGGL(k_born_data_mfma<NS>, dim3((unsigned)grid), dim3(256), 0, st, F, S, R, C,
+                       b.nsplit, b.cells_per_split, b.sgroups, b.nrg, nblocks, omega, dA_K0, cR,
+                       xiK, xiR, Gs, Gsx, Gsz, Gr, Grx, Grz, part);
 }
 
 template <int TS>
@@ -593,7 +777,15 @@ void launch_born_data(const BornSplit &b, int F, int S, int R, int C, const floa
         return;
     const float dA_K0 = (float)(dA / K0), cR = (float)(-dA / rho0);
     auto g2 = [](const float *p) { return (const float2 *)p; };
-    if (b.nsplit > 0) {
+    if (b.nsplit > 0 && b.ns > 0) {
+#define BORN_MFMA(N)                                                                       \
+    case N:                                                                                \
+        data_mfma<N>(b, F, S, R, C, omega, dA_K0, cR, xiK, xiR, g2(Gs), g2(Gsx), g2(Gsz),  \
+                     g2(Gr), g2(Grx), g2(Grz), (float2 *)part, st);                        \
+        break;
+        switch (b.ns) { BORN_MFMA(1) BORN_MFMA(2) BORN_MFMA(3) BORN_MFMA(4) }
+#undef BORN_MFMA
+    } else if (b.nsplit > 0) {
 #define BORN_DATA(T)                                                                       \
     case T:                                                                                \
         data_ts<T>(b, F, S, R, C, omega, dA_K0, cR, xiK, xiR, g2(Gs), g2(Gsx), g2(Gsz),    \
