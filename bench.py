@@ -99,16 +99,18 @@ def algorithmic_bytes(plan_info, S):
 
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1804_01184_amd", "csrc", "k_fused.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+BORN_SOURCE = os.path.join(ROOT, "paper_1804_01184_amd", "csrc", "k_born.hip")
+BORN_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_born.json")
 
 
-def measured_traffic(kernel, decomposition):
+def measured_traffic(kernel, decomposition, traffic_file=TRAFFIC_FILE, source=KERNEL_SOURCE):
     """HBM bytes per launch of `kernel` from the committed counter profile
     (FETCH_SIZE and WRITE_SIZE scaled by the copy calibration), or None if
     the profile was taken with another kernel source or decomposition."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(traffic_file) as fh:
             prof = json.load(fh)
-        with open(KERNEL_SOURCE, "rb") as fh:
+        with open(source, "rb") as fh:
             sha = hashlib.sha256(fh.read()).hexdigest()
     except (OSError, ValueError):
         return None
@@ -203,11 +205,13 @@ def born_main(args):
     ms = (time.perf_counter() - t) * 1e3 / args.steps
     flops = m["flops_per_launch"]
     dom = "data" if m["data"]["ms"] >= m["gradient"]["ms"] else "gradient"
-    roof = {"bound": "alu", "achieved": round(m[dom]["tflops"], 3),
+    kname = "k_born_data_mfma" if dom == "data" else "k_born_grad_mfma"
+    roof = {"bound": "mfma", "achieved": round(m[dom]["tflops"], 3),
             "peak": born.PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(m[dom]["tflops"] / born.PEAK_FP32_TFLOPS, 4), "traffic": None,
-            "kernel": "k_born_data" if dom == "data" else "k_born_grad",
-            "frac_of_nonpacked_fp32": round(m[dom]["tflops"] / born.PEAK_FP32_NONPACKED_TFLOPS, 4),
+            "frac": round(m[dom]["tflops"] / born.PEAK_FP32_TFLOPS, 4),
+            "traffic": measured_traffic(kname, {"workload": w.name, **sz}, BORN_TRAFFIC_FILE,
+                                        BORN_SOURCE),
+            "traffic_unit": "bytes per launch", "kernel": kname,
             "flops_per_launch": flops, "avg_ms": round(m[dom]["ms"], 4)}
     xk, xr = (t_.cpu().numpy().astype(np.float64) for t_ in m["contrasts"])
     cpu = None if args.no_cpu else born_cpu_baseline(w, xk, xr, flops)

@@ -1271,7 +1271,8 @@ BornWs born_ws(int F, int S, int R, int C)
     BornSplit b = born_data_split(F, S, R, C);
     BornWs w;
     w.data = align_up((size_t)b.nsplit * F * S * R * 2 * sizeof(float), kAlign);
-    w.grad = align_up((size_t)2 * std::max(b.fsplit, 1) * C * sizeof(float), kAlign);
+    w.grad = born_grad_wt_offset(b, C) +
+             (b.ns ? align_up((size_t)F * S * R * 2 * sizeof(float), kAlign) : 0);
     w.misfit = align_up((size_t)misfit_blocks(2LL * F * S * R) * sizeof(float), kAlign);
     w.total = std::max(w.data, std::max(w.grad, w.misfit));
     return w;

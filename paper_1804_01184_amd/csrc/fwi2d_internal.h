@@ -237,6 +237,9 @@ struct BornSplit {
     int freqs_per_split;
 };
 BornSplit born_data_split(int F, int S, int R, int C);
+// Byte offset, in the gradient workspace, of the transposed weights of the
+// matrix-core gradient (F S R complex) after the 2 fsplit C partial sums.
+size_t born_grad_wt_offset(const BornSplit &b, int C);
 void launch_born_green(int F, int C, int P, const float *omega, const float *cells,
                        const float *pts, double K0, double rho0, float *G, float *Gx, float *Gz,
                        hipStream_t st);
@@ -246,7 +249,8 @@ void launch_born_data(const BornSplit &b, int F, int S, int R, int C, const floa
                       const float *xiR, const float *Gs, const float *Gsx, const float *Gsz,
                       const float *Gr, const float *Grx, const float *Grz, const float *Gd,
                       float *d, float *part, hipStream_t st);
-// part: 2 * fsplit * C floats.
+// part: 2 * fsplit * C floats (and, on the matrix-core path, F S R complex
+// weights at born_grad_wt_offset).
 void launch_born_gradient(const BornSplit &b, int F, int S, int R, int C, const float *omega,
                           const float *spec, double K0, double rho0, double dA,
                           const float *resid, const float *Gs, const float *Gsx,

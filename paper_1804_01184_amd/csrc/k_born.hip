@@ -476,6 +476,144 @@ __global__ __launch_bounds__(kGradBlock) void k_born_grad(int F, int S, int R, i
     }
 }
 
+// Wt[f][r][s] = conj(resid[f][s][r]) spec[f]: the weights of the gradient
+// sums, sources contiguous for the matrix-core kernel.
+__global__ __launch_bounds__(256) void k_born_wt(int F, int S, int R, const float2 *spec,
+                                                 const float2 *resid, float2 *Wt)
+{
+    const long long n = (long long)F * S * R;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int s = (int)(i % S);
+        const long long fr = i / S;
+        const int r = (int)(fr % R);
+        const int f = (int)(fr / R);
+        const float2 q = resid[((long long)f * S + s) * R + r];
+        const float2 sp = spec[f];
+        Wt[i] = make_float2(q.x * sp.x + q.y * sp.y, q.x * sp.y - q.y * sp.x);
+    }
+}
+
+// Receivers staged per step of the matrix-core gradient kernel.
+constexpr int kGRC = 32;
+
+// The gradient sums on the matrix cores.  Per frequency and table,
+// U[s][c] = sum_r W[s][r] A[c][r] is a complex product with k over
+// (receiver pair, re/im part), laid out as in k_born_data_mfma: D[s][c] with
+// the weights as the first operand (rows: 16 sources) and the receiver
+// table as the second (columns: 16 cells).  A block stages the receiver
+// rows of its 64 cells (four waves of 16 cells) and the weights of 32
+// receivers in LDS; the epilogue adds Re sum_s Gs[c][s] U[s][c] per lane
+// and the four lane groups holding one cell are summed at the end.
+// grid: x = blocks of 64 cells, y = frequency ranges.
+template <int NS>
+__global__ __launch_bounds__(256) void k_born_grad_mfma(
+    int F, int S, int R, int C, int freqs_per_split, int sgroups, const float *omega,
+    const float2 *Wt, const float2 *Gs, const float2 *Gsx, const float2 *Gsz, const float2 *Gr,
+    const float2 *Grx, const float2 *Grz, float *partK, float *partR)
+{
+    constexpr int SW = 16 * NS;
+    __shared__ float2 sA[64][kGRC + 1];
+    __shared__ float2 sW[kGRC][SW];
+    const int wave = (int)(threadIdx.x >> 6), l = (int)(threadIdx.x & 63);
+    const int li = l & 15, kk = l >> 4, rpar = kk & 1;
+    const bool second = kk >= 2;
+    const int cb0 = blockIdx.x * 64;
+    const int cw = wave * 16 + li;
+    const int c = cb0 + cw;
+    const bool live = c < C;
+    const int cl = live ? c : C - 1;
+    const int f_begin = blockIdx.y * freqs_per_split;
+    const int f_end = min(F, f_begin + freqs_per_split);
+    float accK = 0.f, accR = 0.f;
+
+    for (int f = f_begin; f < f_end; ++f) {
+        const long long fC = (long long)f * C;
+        const float2 *W = Wt + (long long)f * R * S;
+#pragma unroll 1
+        for (int t = 0; t < 3; ++t) {
+            const float2 *A = t == 0 ? Gr : (t == 1 ? Grx : Grz);
+            const float2 *B = t == 0 ? Gs : (t == 1 ? Gsx : Gsz);
+            float acc_t = 0.f;
+            for (int sg = 0; sg < sgroups; ++sg) {
+                const int s0 = sg * SW;
+                v4f dre[NS], dim[NS];
+#pragma unroll
+                for (int b = 0; b < NS; ++b) {
+                    dre[b] = v4f{0.f, 0.f, 0.f, 0.f};
+                    dim[b] = v4f{0.f, 0.f, 0.f, 0.f};
+                }
+                for (int r0 = 0; r0 < R; r0 += kGRC) {
+                    const int nr = min(kGRC, R - r0);
+                    __syncthreads();
+                    for (int e = threadIdx.x; e < 64 * kGRC; e += 256) {
+                        const int row = e / kGRC, j = e % kGRC;
+                        const int cc = cb0 + row;
+                        float2 v = make_float2(0.f, 0.f);
+                        if (cc < C && j < nr)
+                            v = A[(fC + cc) * R + r0 + j];
+                        sA[row][j] = v;
+                    }
+                    for (int e = threadIdx.x; e < kGRC * SW; e += 256) {
+                        const int j = e / SW, s = e % SW;
+                        float2 v = make_float2(0.f, 0.f);
+                        if (j < nr && s0 + s < S)
+                            v = W[(long long)(r0 + j) * S + s0 + s];
+                        sW[j][s] = v;
+                    }
+                    __syncthreads();
+#pragma unroll 4
+                    for (int p = 0; p < kGRC / 2; ++p) {
+                        const int j = 2 * p + rpar;
+                        const float2 a = sA[cw][j];
+                        const float bre = second ? a.y : a.x;
+                        const float bim = second ? a.x : a.y;
+#pragma unroll
+                        for (int b = 0; b < NS; ++b) {
+                            const float2 w = sW[j][16 * b + li];
+                            const float are = second ? -w.y : w.x;
+                            const float aim = second ? w.y : w.x;
+                            dre[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(are, bre, dre[b], 0, 0,
+                                                                          0);
+                            dim[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(aim, bim, dim[b], 0, 0,
+                                                                          0);
+                        }
+                    }
+                }
+                if (live) {
+                    const float2 *brow = B + (fC + cl) * S;
+#pragma unroll
+                    for (int b = 0; b < NS; ++b)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int s = s0 + 16 * b + 4 * kk + v;
+                            if (s < S) {
+                                const float2 g = brow[s];
+                                acc_t = fmaf(g.x, dre[b][v], acc_t);
+                                acc_t = fmaf(-g.y, dim[b][v], acc_t);
+                            }
+                        }
+                }
+            }
+            if (t == 0) {
+                const float w = omega[f];
+                accK = fmaf(w * w, acc_t, accK);
+            } else {
+                accR += acc_t;
+            }
+        }
+    }
+    // lanes li, li + 16, li + 32, li + 48 hold the same cell
+    accK += __shfl_xor(accK, 16);
+    accK += __shfl_xor(accK, 32);
+    accR += __shfl_xor(accR, 16);
+    accR += __shfl_xor(accR, 32);
+    if (kk == 0 && live) {
+        partK[(long long)blockIdx.y * C + c] = accK;
+        partR[(long long)blockIdx.y * C + c] = accR;
+    }
+}
+
 // gK[c] = dA/K0 sum_split partK, gR[c] = -dA/rho0 sum_split partR.
 __global__ __launch_bounds__(256) void k_born_grad_finish(int C, int nsplit, float dA_K0,
                                                           float cR, const float *partK,
@@ -678,15 +816,15 @@ void launch_born_green(int F, int C, int P, const float *omega, const float *cel
                        (float2 *)Gz);
 }
 
-// Source chunk width of the data and gradient kernels: the smallest
-// instantiated width covering min(S, 64).
+// Source chunk width of the vector-FMA data and gradient kernels (used
+// below 12 sources): the smallest instantiated width covering S.
 static int born_ts(int S)
 {
-    const int opts[] = {1, 2, 4, 8, 16, 24, 32, 40, 48, 64};
+    const int opts[] = {1, 2, 4, 8, 16};
     for (int t : opts)
         if (t >= S)
             return t;
-    return 64;
+    return 16;
 }
 
 BornSplit born_data_split(int F, int S, int R, int C)
@@ -732,14 +870,21 @@ BornSplit born_data_split(int F, int S, int R, int C)
     b.cells_per_split = per;
     if (per > 0)
         b.nsplit = (C + per - 1) / per;
-    // gradient: cell blocks x frequency splits
-    b.cblocks = (C + kGradBlock - 1) / kGradBlock;
-    const long long gw = b.cblocks > 0 ? (2048 + b.cblocks - 1) / b.cblocks : 1;
+    // gradient: cell blocks x frequency splits (matrix cores: blocks of 64
+    // cells, about 8 rounds of 4 resident blocks per CU)
+    b.cblocks = b.ns ? (C + 63) / 64 : (C + kGradBlock - 1) / kGradBlock;
+    const long long gtarget = b.ns ? 8192 : 2048;
+    const long long gw = b.cblocks > 0 ? (gtarget + b.cblocks - 1) / b.cblocks : 1;
     b.fsplit = (int)std::max(1LL, std::min<long long>(gw, std::max(F, 1)));
     b.freqs_per_split = F > 0 ? (F + b.fsplit - 1) / b.fsplit : 0;
     if (F > 0)
         b.fsplit = (F + b.freqs_per_split - 1) / b.freqs_per_split;
     return b;
+}
+
+size_t born_grad_wt_offset(const BornSplit &b, int C)
+{
+    return ((size_t)2 * std::max(b.fsplit, 1) * C * sizeof(float) + 255) / 256 * 256;
 }
 
 template <int NS>
@@ -792,8 +937,7 @@ void launch_born_data(const BornSplit &b, int F, int S, int R, int C, const floa
                    g2(Gr), g2(Grx), g2(Grz), (float2 *)part, st);                          \
         break;
         switch (b.ts) {
-            BORN_DATA(1) BORN_DATA(2) BORN_DATA(4) BORN_DATA(8) BORN_DATA(16) BORN_DATA(24)
-            BORN_DATA(32) BORN_DATA(40) BORN_DATA(48) BORN_DATA(64)
+            BORN_DATA(1) BORN_DATA(2) BORN_DATA(4) BORN_DATA(8) BORN_DATA(16)
         }
 #undef BORN_DATA
     }
@@ -828,14 +972,30 @@ void launch_born_gradient(const BornSplit &b, int F, int S, int R, int C, const 
         return;
     }
     auto g2 = [](const float *p) { return (const float2 *)p; };
+    if (b.ns > 0) {
+        float2 *Wt = (float2 *)((char *)part + born_grad_wt_offset(b, C));
+        const long long n = (long long)F * S * R;
+        hipLaunchKernelGGL(k_born_wt, dim3(grid_for(n, 256)), dim3(256), 0, st, F, S, R,
+                           g2(spec), g2(resid), Wt);
+#define BORN_GMFMA(N)                                                                      \
+    case N:                                                                                \
+        hipLaunchKernelGGL(k_born_grad_mfma<N>, dim3(b.cblocks, b.fsplit), dim3(256), 0, st, \
+                           F, S, R, C, b.freqs_per_split, b.sgroups, omega, Wt, g2(Gs),      \
+                           g2(Gsx), g2(Gsz), g2(Gr), g2(Grx), g2(Grz), partK, partR);        \
+        break;
+        switch (b.ns) { BORN_GMFMA(1) BORN_GMFMA(2) BORN_GMFMA(3) BORN_GMFMA(4) }
+#undef BORN_GMFMA
+        hipLaunchKernelGGL(k_born_grad_finish, dim3((C + 255) / 256), dim3(256), 0, st, C,
+                           b.fsplit, dA_K0, cR, partK, partR, gK, gR);
+        return;
+    }
 #define BORN_GRAD(T)                                                                       \
     case T:                                                                                \
         grad_ts<T>(b, F, S, R, C, omega, g2(spec), g2(resid), g2(Gs), g2(Gsx), g2(Gsz),    \
                    g2(Gr), g2(Grx), g2(Grz), partK, partR, st);                            \
         break;
     switch (b.ts) {
-        BORN_GRAD(1) BORN_GRAD(2) BORN_GRAD(4) BORN_GRAD(8) BORN_GRAD(16) BORN_GRAD(24)
-        BORN_GRAD(32) BORN_GRAD(40) BORN_GRAD(48) BORN_GRAD(64)
+        BORN_GRAD(1) BORN_GRAD(2) BORN_GRAD(4) BORN_GRAD(8) BORN_GRAD(16)
     }
 #undef BORN_GRAD
     hipLaunchKernelGGL(k_born_grad_finish, dim3((C + 255) / 256), dim3(256), 0, st, C, b.fsplit,

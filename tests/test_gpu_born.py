@@ -6,8 +6,9 @@ for the Green tables (FP64 Hankel functions rounded to FP32), 1e-4 for data,
 gradients and the reduced Hessian (FP32 sums over cells, sources and
 receivers), 1e-5 for the elementwise maps.  The oracle takes the same
 FP32-rounded inputs (positions, frequencies, spectrum, contrasts, residual)
-in FP64.  Shapes cover every source-chunk width of the kernels, ragged
-receiver tiles, cell chunks and cell blocks, more than 64 sources, and the
+in FP64.  Shapes cover every source-chunk width of the vector kernels and
+every tile count of the matrix-core kernels, ragged receiver tiles and
+groups, cell chunks, pairs and blocks, more than 64 sources, and the
 full frequency-domain config-2 problem on sampled outputs plus the adjoint
 dot product."""
 import math
@@ -95,8 +96,10 @@ def test_green_tables_match_oracle(env):
     assert maxrel(prob.Gd.cpu().numpy(), gd) <= 1e-5
 
 
+# vector path: 1, 3, 8, 11 sources (chunk widths 1, 4, 8, 16); matrix-core
+# path: 17, 41, 70 sources (2, 3, 4 source tiles; 70 needs two groups)
 SHAPES = [(3, 1, 70, 300), (2, 3, 37, 529), (2, 17, 64, 1000), (1, 41, 130, 777),
-          (2, 70, 20, 400), (5, 8, 200, 33)]
+          (2, 70, 20, 400), (5, 8, 200, 33), (2, 11, 45, 250)]
 
 
 @pytest.mark.parametrize("F,S,R,C", SHAPES)
