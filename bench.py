@@ -36,7 +36,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c5"])
+    ap.add_argument("--shots", type=int, default=0,
+                    help="evenly spaced subset of the shots (default: all; c5: 32, one GPU's "
+                         "share of 256 shots over 8)")
     ap.add_argument("--band-rows", type=int, default=0)
     ap.add_argument("--shots-per-group", type=int, default=0)
     ap.add_argument("--lane-cols", type=int, default=0)
@@ -63,11 +66,14 @@ def parse():
     return ap.parse_args()
 
 
-def workload(name):
+def workload(name, shots=0):
     from paper_1804_01184_amd import workloads as W
-    if name == "c2":
-        return W.config2()
-    w = W.config3()
+    w = {"c2": W.config2, "c3": W.config3, "c5": W.config5}[name]()
+    if name == "c5" and not shots:
+        shots = 32
+    if shots and shots < w.nshots:
+        idx = np.linspace(0, w.nshots - 1, shots).round().astype(int)
+        w = w.subset(shots=idx, name=f"{w.name}-{shots}of{w.nshots}")
     return w
 
 
@@ -249,7 +255,7 @@ def main():
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
-    w = workload(args.workload)
+    w = workload(args.workload, args.shots)
     if args.time_steps:
         w = w.subset(nt=args.time_steps)
     grid = api.Grid.of(w)
@@ -266,9 +272,14 @@ def main():
         t = time.perf_counter()
         decomp = autotune.tune(grid, w.src_xz, w.rec_xz)
         tuned = {"seconds": round(time.perf_counter() - t, 2)}
+        print(f"bench: decomposition {decomp} ({tuned['seconds']} s)", file=sys.stderr,
+              flush=True)
     plan = api.Plan(grid, w.src_xz, w.rec_xz, ckpt_every=args.ckpt_every, **decomp)
     info = plan.info
     obs = plan.forward("vp-rho", w.vp_true, w.rho_true, f)
+    torch.cuda.synchronize()
+    print(f"bench: {w.name}, observed data modelled; {info['segments']} segment(s)",
+          file=sys.stderr, flush=True)
     K0, r0 = api.model_convert("vp-rho", "k-rho", vp0, rho0)
     Jb = torch.empty(1, dtype=torch.float32, device=dev)
     gK, gr = torch.empty_like(K0), torch.empty_like(K0)
