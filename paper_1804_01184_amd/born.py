@@ -30,6 +30,8 @@ import torch
 from . import _lib as L
 from .api import _ptr, _stream, param_id
 
+PARAMS = ("vp-rho", "ip-rho", "vp-ip", "k-rho", "invk-invrho")
+
 
 def _f32(x, dev):
     return torch.as_tensor(np.ascontiguousarray(np.asarray(x, np.float32)), device=dev)
@@ -202,6 +204,122 @@ def descent(prob, scheme, param, observed, iters, mask=None, direct=True, **kw):
                              start=(zero, zero), **kw)
 
 
+def amplitude_descent(prob, scheme, param, profile, observed, iters, direct=False, **kw):
+    """Steepest descent when the scatterer's shape s is known (section
+    "Almost Well-posed Example", scatterers (i), (ii), (iv), (v)): the
+    unknowns are the two amplitudes (a, b), the contrasts a s and b s, and
+    dJ/da = sum_c s dJ/dxa.  Same loop and step rule as descent(); returns
+    its DescentResult with m1, m2 the amplitudes ([1] tensors)."""
+    from . import inversion
+    dev = prob.device
+    s = _cell_tensor(profile, prob)
+    one = torch.ones(1, dtype=torch.float32, device=dev)
+    zero = torch.zeros_like(one)
+    q = observed.contiguous()
+    d = torch.empty((prob.F, prob.S, prob.R), dtype=torch.complex64, device=dev)
+
+    def model(a, b):
+        return contrasts(scheme, param, (a * s).contiguous(), (b * s).contiguous())
+
+    def grad_fn(a, b):
+        xa, xb = (a * s).contiguous(), (b * s).contiguous()
+        prob.data(*contrasts(scheme, param, xa, xb), direct=direct, out=d)
+        J, r = prob.misfit(d, q)
+        ga, gb = chain(scheme, param, xa, xb, *prob.gradient(r))
+        return J, (s * ga).sum().reshape(1), (s * gb).sum().reshape(1)
+
+    def value_fn(a, b):
+        prob.data(*model(a, b), direct=direct, out=d)
+        return prob.misfit(d, q, residual=False)[0]
+
+    return inversion.descend(grad_fn, value_fn, one, one, iters, start=(zero, zero), **kw)
+
+
+def _cell_tensor(x, prob):
+    t = x if isinstance(x, torch.Tensor) else torch.as_tensor(np.asarray(x, np.float32))
+    return t.to(device=prob.device, dtype=torch.float32).reshape(-1).contiguous()
+
+
+def bowl(prob, scheme, param, profile, observed, xa, xb, direct=False):
+    """J on the grid xa x xb of amplitudes of the known shape (the error
+    bowls of section "Error-bowl Analysis" under schemes I and II)."""
+    s = _cell_tensor(profile, prob)
+    q = observed.contiguous()
+    d = torch.empty((prob.F, prob.S, prob.R), dtype=torch.complex64, device=prob.device)
+    J = np.empty((len(xa), len(xb)))
+    for i, a in enumerate(xa):
+        for j, b in enumerate(xb):
+            ca, cb = (float(a) * s).contiguous(), (float(b) * s).contiguous()
+            prob.data(*contrasts(scheme, param, ca, cb), direct=direct, out=d)
+            J[i, j] = float(prob.misfit(d, q, residual=False)[0].item())
+    return J
+
+
+CASES = ("i", "ii", "iii", "iv", "v", "vi", "vii")
+
+
+def scatterer_study(w, iters, cases=CASES, schemes=(1, 2), params=PARAMS, device=None,
+                    bowl_points=9):
+    """Schemes I and II for the scatterers of the paper's scatterer table in
+    its almost well-posed geometry: misfit per iteration in each
+    parameterization (shape known: amplitude descent; shape unknown:
+    descent over every cell), and for the point scatterers the error bowl's
+    axis ratio and long-axis angle.  Observed data: the true contrasts
+    through the exact map (both schemes), scattered part only."""
+    from . import bowls, workloads as W
+    dev = torch.device(device) if device is not None else torch.device(
+        "cuda", torch.cuda.current_device())
+    prob = BornProblem.of(w, dev)
+    out = {"workload": w.name, "iters": iters, "sizes": w.sizes()}
+    for case in cases:
+        ta, tb, prof, known = W.paper_scatterer(case, w)
+        q = prob.data(*contrasts(2, "vp-rho", _f32(ta.ravel(), dev), _f32(tb.ravel(), dev)),
+                      direct=False)
+        rec = {"shape_known": known}
+        for scheme in schemes:
+            rs = {}
+            for p in params:
+                if known:
+                    r = amplitude_descent(prob, scheme, p, prof, q, iters)
+                else:
+                    r = descent(prob, scheme, p, q, iters, direct=False)
+                rs[p] = {"J": [float(x) for x in r.J],
+                         "J_final_over_J0": float(r.J[-1] / r.J[0]), "steps": len(r.alpha)}
+                if known:
+                    rs[p]["amplitudes"] = [float(r.m1[0]), float(r.m2[0])]
+                if known and case in ("i", "iv") and bowl_points:
+                    # true amplitudes in this parameterization: the scheme-II
+                    # map of the Vp-rho truth, read back at the scatterer
+                    c = int(np.argmax(prof.ravel()))
+                    tk, tr = (float(v[c]) for v in contrasts(
+                        2, "vp-rho", _f32(ta.ravel(), dev), _f32(tb.ravel(), dev)))
+                    xt = _true_amplitudes(p, tk, tr)
+                    half = 0.5 * max(abs(xt[0]), abs(xt[1]))
+                    ga = np.linspace(xt[0] - half, xt[0] + half, bowl_points)
+                    gb = np.linspace(xt[1] - half, xt[1] + half, bowl_points)
+                    Jb = bowl(prob, scheme, p, prof, q, ga, gb)
+                    ratio, ang = bowls.bowl_shape(bowls.fit_quadratic(ga, gb, Jb, xt)[0])
+                    rs[p]["bowl"] = {"true_amplitudes": list(xt), "axis_ratio": ratio,
+                                     "long_axis_deg": ang}
+            rec[f"scheme_{scheme}"] = rs
+            order = sorted(params, key=lambda p: rs[p]["J_final_over_J0"])
+            print(f"({case}) scheme {scheme}: fastest to slowest " +
+                  ", ".join(f"{p} {rs[p]['J_final_over_J0']:.1e}" for p in order),
+                  file=sys.stderr, flush=True)
+        out[f"({case})"] = rec
+    return out
+
+
+def _true_amplitudes(param, xk, xr):
+    """Contrasts (xa, xb) of `param` whose exact inverse contrasts are
+    (xk, xr) = (K0/K - 1, rho0/rho - 1) (host arithmetic on two scalars)."""
+    k, r = 1.0 / (1.0 + xk), 1.0 / (1.0 + xr)          # K/K0, rho/rho0
+    return {"k-rho": (k - 1, r - 1), "vp-rho": (math.sqrt(k / r) - 1, r - 1),
+            "ip-rho": (math.sqrt(k * r) - 1, r - 1),
+            "vp-ip": (math.sqrt(k / r) - 1, math.sqrt(k * r) - 1),
+            "invk-invrho": (1 / k - 1, 1 / r - 1)}[param]
+
+
 def hessian_summary(H):
     """Eigen-analysis of the Gauss-Newton Hessian Re H: eigenvalues,
     condition number, angle of the principal eigenvector (degrees in
@@ -218,7 +336,6 @@ def hessian_summary(H):
 # data and gradient sums run on v_mfma_f32_16x16x4f32 from 12 sources up.
 PEAK_FP32_TFLOPS = 157.3
 
-PARAMS = ("vp-rho", "ip-rho", "vp-ip", "k-rho", "invk-invrho")
 
 
 def _events_ms(fn, reps):
@@ -322,10 +439,17 @@ def main(argv=None):
     ap.add_argument("--workload", default="c2", choices=["c1", "c2"])
     ap.add_argument("--freqs", type=int, default=32)
     ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--scatterers", type=int, default=0, metavar="ITERS",
+                    help="instead: schemes I and II for the seven scatterers of the paper's "
+                         "scatterer table in its 10-source, 100-receiver ring geometry")
     ap.add_argument("--invert", type=int, default=0, metavar="ITERS",
                     help="instead: schemes I and II steepest descent on scatterer (i) "
                          "(frequency-domain config 1, shape known) for ITERS iterations")
     a = ap.parse_args(argv)
+    if a.scatterers:
+        torch.cuda.set_device(0)
+        print(json.dumps(scatterer_study(W.born_paper(), a.scatterers)), flush=True)
+        return
     if a.invert:
         torch.cuda.set_device(0)
         print(json.dumps(invert_point(W.born_config1(a.freqs), a.invert)), flush=True)

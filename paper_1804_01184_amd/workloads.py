@@ -295,6 +295,7 @@ class BornWorkload:
     param: str
     xa: np.ndarray             # [nz][nx]
     xb: np.ndarray
+    origin: tuple = (0.0, 0.0)  # (x, z) of cell [0][0]
 
     @property
     def omega(self):
@@ -303,7 +304,8 @@ class BornWorkload:
     @property
     def cells(self):
         z, x = np.mgrid[0:self.nz, 0:self.nx]
-        return np.stack([x.ravel() * self.dx, z.ravel() * self.dz], axis=1)
+        return np.stack([x.ravel() * self.dx + self.origin[0],
+                         z.ravel() * self.dz + self.origin[1]], axis=1)
 
     @property
     def dA(self):
@@ -346,3 +348,46 @@ def point_ring(n_src, n_rec, radius, x0=(0.0, 0.0)):
     """Sources and receivers evenly on a circle around x0 (the circular
     acquisition of the point-scatterer analysis)."""
     return ring(n_src, radius, x0[0], x0[1]), ring(n_rec, radius, x0[0], x0[1], offset=0.5)
+
+
+def born_paper(nf=15, n=121, dx=5.0):
+    """The paper's almost well-posed example in the frequency domain: 10
+    sources and 100 receivers evenly on a 490 m circle around x0 = (0, 0),
+    background 2000 m/s and 2000 kg/m^3, a 5 Hz Ricker wavelet (frequencies
+    1, 2, ..., nf Hz), and n x n cells of dx metres centred on x0 (600 m
+    square by default: every cell inside the ring).  The contrasts are left
+    at zero; paper_scatterer sets them."""
+    freqs = np.arange(1, nf + 1, dtype=float)
+    _, rec = point_ring(10, 100, 490.0)
+    src = ring(10, 490.0, 0.0, 0.0, offset=0.25)
+    z = np.zeros((n, n))
+    h = -0.5 * (n - 1) * dx
+    return BornWorkload("born-paper-ring-490", n, n, dx, dx, 2000.0 * 2000.0 ** 2, 2000.0, freqs,
+                        ricker_spectrum(freqs, 5.0), src, rec, "vp-rho", z, z.copy(), (h, h))
+
+
+def paper_scatterer(case, w, contrast=0.1, sigma=50.0):
+    """Scatterer `case` ('i' ... 'vii') of the paper's scatterer table at the
+    centre cell of a born_paper workload, as Vp-rho contrasts: (i) point,
+    Vp only; (ii), (iii) Gaussian (sigma metres), Vp only; (iv) point, rho
+    only; (v), (vi) Gaussian, rho only; (vii) Gaussian with no bulk-modulus
+    contrast (rho (1 + c s), Vp (1 + c s)^-1/2).  Returns (xa, xb, profile,
+    shape_known): the profile s (peak 1) and whether the inversion knows it."""
+    n = w.nz
+    i0 = n // 2
+    z, x = np.mgrid[0:n, 0:n]
+    r2 = ((x - i0) * w.dx) ** 2 + ((z - i0) * w.dz) ** 2
+    point = np.zeros((n, n))
+    point[i0, i0] = 1.0
+    gauss = np.exp(-r2 / (2.0 * sigma * sigma))
+    s = point if case in ("i", "iv") else gauss
+    zero = np.zeros((n, n))
+    if case in ("i", "ii", "iii"):
+        xa, xb = contrast * s, zero
+    elif case in ("iv", "v", "vi"):
+        xa, xb = zero, contrast * s
+    elif case == "vii":
+        xa, xb = (1.0 + contrast * s) ** -0.5 - 1.0, contrast * s
+    else:
+        raise ValueError(case)
+    return xa, xb, s, case in ("i", "ii", "iv", "v")
