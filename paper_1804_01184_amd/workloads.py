@@ -373,10 +373,14 @@ def paper_scatterer(case, w, contrast=0.1, sigma=50.0):
     only; (v), (vi) Gaussian, rho only; (vii) Gaussian with no bulk-modulus
     contrast (rho (1 + c s), Vp (1 + c s)^-1/2).  Returns (xa, xb, profile,
     shape_known): the profile s (peak 1) and whether the inversion knows it."""
-    n = w.nz
-    i0 = n // 2
+    return _scatterer_fields(case, w.nz, w.dx, w.nz // 2, contrast, sigma)
+
+
+def _scatterer_fields(case, n, dx, i0, contrast, sigma):
+    """Vp-rho contrasts (xa, xb), profile s and shape_known of scatterer
+    `case` at node (i0, i0) of an n x n grid of spacing dx."""
     z, x = np.mgrid[0:n, 0:n]
-    r2 = ((x - i0) * w.dx) ** 2 + ((z - i0) * w.dz) ** 2
+    r2 = ((x - i0) * dx) ** 2 + ((z - i0) * dx) ** 2
     point = np.zeros((n, n))
     point[i0, i0] = 1.0
     gauss = np.exp(-r2 / (2.0 * sigma * sigma))
@@ -391,3 +395,26 @@ def paper_scatterer(case, w, contrast=0.1, sigma=50.0):
     else:
         raise ValueError(case)
     return xa, xb, s, case in ("i", "ii", "iv", "v")
+
+
+def paper_fd(case, n=121, dx=10.0, npml=20, contrast=0.1, sigma=50.0, duration=1.4):
+    """Time-domain (scheme III) form of the paper's almost well-posed
+    example: n x n nodes of dx metres with the scatterer at the centre node
+    x0, 10 sources and 100 receivers evenly on a 490 m circle around it,
+    background 2000 m/s and 2000 kg/m^3, a 5 Hz Ricker wavelet, CFL 0.5 on
+    the true vmax, `duration` seconds.  Returns (Workload, profile,
+    shape_known)."""
+    i0 = n // 2
+    c = i0 * dx
+    xa, xb, s, known = _scatterer_fields(case, n, dx, i0, contrast, sigma)
+    vp0 = np.full((n, n), 2000.0)
+    rho0 = np.full((n, n), 2000.0)
+    vp, rho = vp0 * (1.0 + xa), rho0 * (1.0 + xb)
+    vmax = float(vp.max())
+    dt = _dt(vmax, dx, dx)
+    src = ring(10, 490.0, c, c, offset=0.25)
+    rec = ring(100, 490.0, c, c, offset=0.5)
+    w = Workload(f"paper-ring-490-{case}", n, n, dx, dx, npml, int(round(duration / dt)), dt,
+                 vmax, 5.0, src, np.ascontiguousarray(np.broadcast_to(rec, (10, 100, 2))), vp,
+                 rho, vp0, rho0)
+    return w, s, known

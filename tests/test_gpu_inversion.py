@@ -102,3 +102,40 @@ def test_masked_loop_moves_only_the_support(env):
     np.testing.assert_array_equal(res.m1.cpu().numpy()[frozen], m1.cpu().numpy()[frozen])
     np.testing.assert_array_equal(res.m2.cpu().numpy()[frozen], m2.cpu().numpy()[frozen])
     assert res.J[-1] < res.J[0]
+
+
+@pytest.mark.parametrize("param", ["vp-rho", "ip-rho", "k-rho"])
+def test_amplitude_loop_matches_oracle_loop(env, param):
+    # known shape (a Gaussian at the centre): the unknowns are the two
+    # amplitudes; three iterations against the oracle's loop over the same
+    # amplitudes
+    api, inv, torch = env
+    w = _tiny()
+    g = O.Grid(w.nz, w.nx, w.dz, w.dx, w.npml, w.nt, w.dt, w.vmax, w.pml_r)
+    f = w.wavelet()
+    obs = O.forward_krho(g, w.src_xz, w.rec_xz, w.rho_true * w.vp_true ** 2, w.rho_true, f)
+    m1, m2 = O.krho_to_model(O.PARAMS[param], w.rho_start * w.vp_start ** 2, w.rho_start)
+    c = (w.nz - 1) / 2 * w.dx
+    s = W.gaussian_bump(w.nz, w.nx, w.dz, w.dx, c, c, 20.0)
+    res = inv.amplitude_descent(api.Plan(api.Grid.of(w), w.src_xz, w.rec_xz), param, m1, m2, s,
+                                f, obs.astype(np.float32), 3)
+    s32 = s.astype(np.float32).astype(np.float64)
+    m1f, m2f = (m.astype(np.float32).astype(np.float64) for m in (m1, m2))
+
+    def model(u1, u2):
+        return m1f * (1.0 + (u1[0] - 1.0) * s32), m2f * (1.0 + (u2[0] - 1.0) * s32)
+
+    def grad_fn(u1, u2):
+        J, g1, g2, _ = O.gradient(g, O.PARAMS[param], *model(u1, u2), w.src_xz, w.rec_xz, f, obs)
+        return J, np.array([np.sum(s32 * m1f * g1)]), np.array([np.sum(s32 * m2f * g2)])
+
+    def value_fn(u1, u2):
+        return O.misfit(O.forward(g, O.PARAMS[param], *model(u1, u2), w.src_xz, w.rec_xz, f),
+                        obs)[0]
+
+    ref = OI.descend(grad_fn, value_fn, np.ones(1), np.ones(1), 3)
+    assert len(res.alpha) == len(ref["alpha"]) == 3
+    np.testing.assert_allclose(res.J, ref["J"], rtol=TOL)
+    np.testing.assert_allclose(res.alpha, ref["alpha"], rtol=TOL)
+    np.testing.assert_allclose([float(res.m1[0]), float(res.m2[0])],
+                               [ref["m1"][0] - 1.0, ref["m2"][0] - 1.0], rtol=TOL, atol=1e-6)
