@@ -287,18 +287,22 @@ fwi_status fwi_born_green(int32_t F, const float *omega, int32_t C, const float 
                           float *Gx, float *Gz, void *stream);
 
 /* Workspace bytes (256-byte aligned) that fwi_born_data, fwi_born_gradient
- * and fwi_born_misfit need for these sizes (partial sums of the split
- * launches).  The workspace is only used during the call's kernels; calls
- * on one workspace must be ordered (same stream). */
+ * and fwi_born_misfit need for these sizes: the partial sums of the split
+ * launches and, for the gradient with 12 sources or more, the residual
+ * weights transposed for the matrix cores.  The workspace is only used
+ * during the call's kernels; calls on one workspace must be ordered (same
+ * stream).  0 for sizes the calls reject. */
 size_t fwi_born_workspace_bytes(int32_t F, int32_t S, int32_t R, int32_t C);
 
 /* Born data d [F][S][R] (formula above) from the contrasts xiK, xiR [C], the
  * source tables Gs, Gsx, Gsz [F][C][S], the receiver tables Gr, Grx, Grz
  * [F][C][R] and the direct wave Gd [F][S][R] (NULL: scattered data only).
- * spec [F] complex.  FP32 arithmetic with FP32 accumulation: per frequency
- * the cells are cut into ranges summed in a fixed order (bitwise
- * repeatable).  FWI_EWORKSPACE if work is NULL, misaligned or smaller than
- * fwi_born_workspace_bytes. */
+ * spec [F] complex.  FP32 arithmetic with FP32 accumulation, on the FP32
+ * matrix cores from 12 sources up: per frequency the cells are cut into
+ * ranges summed in a fixed order (bitwise repeatable).  FWI_EINVAL for
+ * sizes out of range (F > 65535, S > 4194240, S R >= 2^31) or a NULL
+ * required array; FWI_EWORKSPACE if work is NULL, misaligned or smaller
+ * than fwi_born_workspace_bytes. */
 fwi_status fwi_born_data(int32_t F, const float *omega, const float *spec, int32_t S,
                          int32_t R, int32_t C, double K0, double rho0, double dA,
                          const float *xiK, const float *xiR, const float *Gs, const float *Gsx,
