@@ -41,10 +41,22 @@ def _c64(x, dev):
     return torch.as_tensor(np.ascontiguousarray(np.asarray(x, np.complex64)), device=dev)
 
 
+def _need(t, shape, dtype, what):
+    """The library reads and writes whole arrays through plain pointers: a
+    tensor of another size, type or layout is refused here."""
+    if (tuple(t.shape) != tuple(shape) or t.dtype != dtype or not t.is_contiguous()
+            or not t.is_cuda):
+        raise ValueError(f"{what}: expected a contiguous device {dtype} tensor of shape "
+                         f"{tuple(shape)}, got {t.dtype} {tuple(t.shape)} on {t.device}")
+
+
 def green(omega, cells, pts, K0, rho0, grad=True, stream=None):
     """Tables (G, Gx, Gz) [F][C][P] complex64 on the device of `omega` (a
     float32 device tensor); cells, pts [n][2] device float32."""
     F, C, P = omega.numel(), cells.shape[0], pts.shape[0]
+    _need(omega, (F,), torch.float32, "omega")
+    _need(cells, (C, 2), torch.float32, "cells")
+    _need(pts, (P, 2), torch.float32, "pts")
     dev = omega.device
     G = torch.empty((F, C, P), dtype=torch.complex64, device=dev)
     Gx = torch.empty_like(G) if grad else None
@@ -97,6 +109,7 @@ class BornProblem:
         xiK, xiR = self._cell(xiK), self._cell(xiR)
         d = torch.empty((self.F, self.S, self.R), dtype=torch.complex64,
                         device=self.device) if out is None else out
+        _need(d, (self.F, self.S, self.R), torch.complex64, "out")
         L.check(L.lib().fwi_born_data(
             self.F, _ptr(self.omega), _ptr(self.spec), self.S, self.R, self.C, self.K0,
             self.rho0, self.dA, _ptr(xiK), _ptr(xiR), *(_ptr(t) for t in self.Gs),
@@ -107,6 +120,8 @@ class BornProblem:
     def misfit(self, d, q, residual=True, stream=None):
         """(J [1] device float32, resid = d - q or None)."""
         d, q = d.contiguous(), q.contiguous()
+        _need(d, (self.F, self.S, self.R), torch.complex64, "d")
+        _need(q, (self.F, self.S, self.R), torch.complex64, "q")
         J = torch.empty(1, dtype=torch.float32, device=self.device)
         r = torch.empty_like(d) if residual else None
         L.check(L.lib().fwi_born_misfit(d.numel(), _ptr(d), _ptr(q), _ptr(r), _ptr(J),
@@ -116,6 +131,7 @@ class BornProblem:
     def gradient(self, resid, stream=None):
         """(dJ/dxi_{1/K}, dJ/dxi_{1/rho}) [C] for resid = d - q."""
         resid = resid.contiguous()
+        _need(resid, (self.F, self.S, self.R), torch.complex64, "resid")
         gK = torch.empty(self.C, dtype=torch.float32, device=self.device)
         gR = torch.empty_like(gK)
         L.check(L.lib().fwi_born_gradient(
@@ -133,6 +149,8 @@ def contrasts(scheme, param, xa, xb, stream=None):
     """(xi_{1/K}, xi_{1/rho}) of the contrasts (xa, xb) of `param`: scheme 2
     exact, scheme 1 linearised."""
     xa, xb = xa.contiguous(), xb.contiguous()
+    _need(xa, xb.shape, torch.float32, "xa")
+    _need(xb, xa.shape, torch.float32, "xb")
     k, r = torch.empty_like(xa), torch.empty_like(xa)
     L.check(L.lib().fwi_born_contrasts(int(scheme), param_id(param), xa.numel(), _ptr(xa),
                                        _ptr(xb), _ptr(k), _ptr(r), _stream(stream)))
@@ -142,6 +160,9 @@ def contrasts(scheme, param, xa, xb, stream=None):
 def chain(scheme, param, xa, xb, gK, gR, stream=None):
     """(dJ/dxa, dJ/dxb) from (dJ/dxi_{1/K}, dJ/dxi_{1/rho})."""
     xa, xb, gK, gR = (x.contiguous() for x in (xa, xb, gK, gR))
+    for t, name in ((xa, "xa"), (xb, "xb"), (gR, "gR")):
+        _need(t, gK.shape, torch.float32, name)
+    _need(gK, gK.shape, torch.float32, "gK")
     ga, gb = torch.empty_like(gK), torch.empty_like(gK)
     L.check(L.lib().fwi_born_chain(int(scheme), param_id(param), gK.numel(), _ptr(xa),
                                    _ptr(xb), _ptr(gK), _ptr(gR), _ptr(ga), _ptr(gb),

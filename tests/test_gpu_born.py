@@ -334,3 +334,16 @@ def test_point_scatterer_amplitudes_are_recovered(env):
     r1 = born.amplitude_descent(prob, 1, "invk-invrho", prof, q, 10)
     r2 = born.amplitude_descent(prob, 2, "invk-invrho", prof, q, 10)
     assert r1.J == r2.J
+
+
+def test_binding_refuses_mismatched_tensors(env):
+    torch, born = env
+    p = problem(8, 2, 3, 10, 20)
+    prob = gpu_problem(born, p)
+    x = torch.zeros(20, device="cuda")
+    with pytest.raises(ValueError):
+        prob.data(x, x, out=torch.empty((2, 3, 9), dtype=torch.complex64, device="cuda"))
+    with pytest.raises(ValueError):
+        prob.gradient(torch.zeros((2, 3, 10), dtype=torch.float32, device="cuda"))
+    with pytest.raises(ValueError):
+        born.contrasts(2, "vp-rho", x, torch.zeros(19, device="cuda"))
