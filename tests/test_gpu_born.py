@@ -16,7 +16,6 @@ import math
 import numpy as np
 import pytest
 
-import oracle as O
 from oracle import born as OB
 from paper_1804_01184_amd import workloads as W
 
