@@ -587,7 +587,6 @@ __global__ void __launch_bounds__(NTHR)
     cfloat *zahz = zbz + g.Nz, *zbhz = zahz + g.Nz;
     const unsigned FB = 4u * (unsigned)g.N;
     const rsrc_t rM = res(model, 3u * FB);
-    const unsigned rowN = 4u * (unsigned)g.Nx;
     const rsrc_t rPin = grp_res(a.pin, w.s0, SPG), rVin = grp_res(a.vin, w.s0, SPG);
     const rsrc_t rPmid = grp_res(a.pmid, w.s0, SPG);
     const rsrc_t rPout = grp_res(a.pout, w.s0, SPG), rVout = grp_res(a.vout, w.s0, SPG);
