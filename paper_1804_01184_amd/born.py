@@ -341,6 +341,32 @@ def _true_amplitudes(param, xk, xr):
             "invk-invrho": (1 / k - 1, 1 / r - 1)}[param]
 
 
+LINEAR_MAP = {"k-rho": ((-1.0, 0.0), (0.0, -1.0)), "vp-rho": ((-2.0, -1.0), (0.0, -1.0)),
+              "ip-rho": ((-2.0, 1.0), (0.0, -1.0)), "vp-ip": ((-1.0, -1.0), (1.0, -1.0)),
+              "invk-invrho": ((1.0, 0.0), (0.0, 1.0))}
+
+
+def contrast_table(xk, xr, device=None):
+    """The contrasts of every parameterization for inverse contrasts
+    (xk, xr) = (xi_{1/K}, xi_{1/rho}): exact (Table 2; the library's model
+    conversion of K0/(1 + xk), rho0/(1 + xr)) and linearised (Table 3, as
+    the inverse of the derivative of Table 2 at zero contrast)."""
+    from . import api
+    dev = torch.device(device) if device is not None else torch.device(
+        "cuda", torch.cuda.current_device())
+    K0, r0 = 2000.0 * 2000.0 ** 2, 2000.0
+    K = torch.tensor([K0, K0 / (1.0 + xk)], dtype=torch.float64).float().to(dev)
+    rho = torch.tensor([r0, r0 / (1.0 + xr)], dtype=torch.float64).float().to(dev)
+    out = {}
+    for p in PARAMS:
+        a, b = (t.double().cpu().numpy() for t in api.model_convert("k-rho", p, K, rho))
+        A = np.array(LINEAR_MAP[p])
+        la, lb = np.linalg.solve(A, np.array([xk, xr]))
+        out[p] = {"exact": [float(a[1] / a[0] - 1.0), float(b[1] / b[0] - 1.0)],
+                  "linear": [float(la), float(lb)]}
+    return out
+
+
 def hessian_summary(H):
     """Eigen-analysis of the Gauss-Newton Hessian Re H: eigenvalues,
     condition number, angle of the principal eigenvector (degrees in
@@ -460,6 +486,9 @@ def main(argv=None):
     ap.add_argument("--workload", default="c2", choices=["c1", "c2"])
     ap.add_argument("--freqs", type=int, default=32)
     ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--contrast-table", action="store_true",
+                    help="instead: exact and linearised contrasts of every parameterization "
+                         "for the point scatterers (i), (iv) and a no-K-contrast scatterer")
     ap.add_argument("--scatterers", type=int, default=0, metavar="ITERS",
                     help="instead: schemes I and II for the seven scatterers of the paper's "
                          "scatterer table in its 10-source, 100-receiver ring geometry")
@@ -467,6 +496,12 @@ def main(argv=None):
                     help="instead: schemes I and II steepest descent on scatterer (i) "
                          "(frequency-domain config 1, shape known) for ITERS iterations")
     a = ap.parse_args(argv)
+    if a.contrast_table:
+        torch.cuda.set_device(0)
+        rows = {"(i) Vp +10 %": (1 / 1.21 - 1, 0.0), "(iv) rho +10 %": (1 / 1.1 - 1, 1 / 1.1 - 1),
+                "(vii) rho +10 %, K fixed": (0.0, 1 / 1.1 - 1)}
+        print(json.dumps({k: contrast_table(*v) for k, v in rows.items()}), flush=True)
+        return
     if a.scatterers:
         torch.cuda.set_device(0)
         print(json.dumps(scatterer_study(W.born_paper(), a.scatterers)), flush=True)

@@ -346,3 +346,20 @@ def test_binding_refuses_mismatched_tensors(env):
         prob.gradient(torch.zeros((2, 3, 10), dtype=torch.float32, device="cuda"))
     with pytest.raises(ValueError):
         born.contrasts(2, "vp-rho", x, torch.zeros(19, device="cuda"))
+
+
+def test_contrast_table(env):
+    # exact contrasts (Table 2) against the oracle's conversions; the
+    # linearised ones (Table 3) mapped back by the oracle's linear map
+    import oracle as O
+    torch, born = env
+    xk, xr = 1 / 1.21 - 1, 1 / 1.1 - 1
+    tab = born.contrast_table(xk, xr)
+    K0, r0 = 2000.0 * 2000.0 ** 2, 2000.0
+    for p, pid in O.PARAMS.items():
+        a0, b0 = O.krho_to_model(pid, np.array([K0]), np.array([r0]))
+        a1, b1 = O.krho_to_model(pid, np.array([K0 / (1 + xk)]), np.array([r0 / (1 + xr)]))
+        np.testing.assert_allclose(tab[p]["exact"], [a1[0] / a0[0] - 1, b1[0] / b0[0] - 1],
+                                   rtol=1e-5, atol=1e-6)
+        np.testing.assert_allclose(OB.linear_map(pid) @ np.array(tab[p]["linear"]), [xk, xr],
+                                   rtol=1e-12)
