@@ -479,6 +479,35 @@ def invert_point(w, iters, device=None):
     return out
 
 
+def invert_field(w, iters, schemes=(1, 2), params=PARAMS, device=None):
+    """Steepest descent over every cell (shape unknown) at the workload's
+    full size: misfit per iteration in each parameterization and the
+    wall time per iteration (one gradient and the line-search data
+    evaluations)."""
+    import time
+    dev = torch.device(device) if device is not None else torch.device(
+        "cuda", torch.cuda.current_device())
+    prob = BornProblem.of(w, dev)
+    q = prob.data(*contrasts(2, w.param, _f32(w.xa.ravel(), dev), _f32(w.xb.ravel(), dev)),
+                  direct=False)
+    out = {"workload": w.name, "sizes": w.sizes(), "iters": iters}
+    for scheme in schemes:
+        rec = {}
+        for p in params:
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            r = descent(prob, scheme, p, q, iters, direct=False)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t
+            rec[p] = {"J": [float(x) for x in r.J], "J_final_over_J0": float(r.J[-1] / r.J[0]),
+                      "gradients": r.gradients, "data_evaluations": r.forwards,
+                      "seconds": round(dt, 3)}
+            print(f"scheme {scheme} {p}: J/J0 {rec[p]['J_final_over_J0']:.2e} after "
+                  f"{len(r.alpha)} steps, {dt:.2f} s", file=sys.stderr, flush=True)
+        out[f"scheme_{scheme}"] = rec
+    return out
+
+
 def main(argv=None):
     import argparse
     from . import workloads as W
@@ -486,6 +515,9 @@ def main(argv=None):
     ap.add_argument("--workload", default="c2", choices=["c1", "c2"])
     ap.add_argument("--freqs", type=int, default=32)
     ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--invert-c2", type=int, default=0, metavar="ITERS",
+                    help="instead: scheme II steepest descent over every cell of the "
+                         "frequency-domain config 2 (Gaussian Vp anomaly, shape unknown)")
     ap.add_argument("--contrast-table", action="store_true",
                     help="instead: exact and linearised contrasts of every parameterization "
                          "for the point scatterers (i), (iv) and a no-K-contrast scatterer")
@@ -496,6 +528,10 @@ def main(argv=None):
                     help="instead: schemes I and II steepest descent on scatterer (i) "
                          "(frequency-domain config 1, shape known) for ITERS iterations")
     a = ap.parse_args(argv)
+    if a.invert_c2:
+        torch.cuda.set_device(0)
+        print(json.dumps(invert_field(W.born_config2(a.freqs), a.invert_c2)), flush=True)
+        return
     if a.contrast_table:
         torch.cuda.set_device(0)
         rows = {"(i) Vp +10 %": (1 / 1.21 - 1, 0.0), "(iv) rho +10 %": (1 / 1.1 - 1, 1 / 1.1 - 1),
