@@ -89,37 +89,72 @@ __device__ inline void hankel01(double z, double2 &h0, double2 &h1)
     h1 = make_double2(amp * (P1 * s + Q1 * c), -amp * (P1 * c - Q1 * s));
 }
 
+// One entry: G0 and its gradient between point (px, pz) and cell (cx, cz).
+__device__ inline void green_entry(double cx, double cz, double px, double pz, double k,
+                                   double rho0, float2 &g, float2 &gx, float2 &gz)
+{
+    const double dx = cx - px, dz = cz - pz;
+    const double r = sqrt(dx * dx + dz * dz);
+    g = gx = gz = make_float2(0.f, 0.f);
+    if (r > 0.0) {
+        double2 h0, h1;
+        hankel01(k * r, h0, h1);
+        // G = (i rho0/4)(J0 + i Y0); grad = (rho0 k/4)(Y1 - i J1) (x - y)/r
+        const double a = 0.25 * rho0;
+        g = make_float2((float)(-a * h0.y), (float)(a * h0.x));
+        const double b = a * k / r;
+        gx = make_float2((float)(b * h1.y * dx), (float)(-b * h1.x * dx));
+        gz = make_float2((float)(b * h1.y * dz), (float)(-b * h1.x * dz));
+    }
+}
+
+// Tiles of 64 cells x 32 points for one frequency.  The 64 lanes of a
+// wave take 64 neighbouring cells at one point, so that k r, and with it
+// the branch of the Hankel evaluation, varies little across a wave; the
+// tile goes out through LDS, one table at a time, with the points of a
+// cell contiguous.  grid: x = cell tiles, y = point tiles, z = frequency.
+constexpr int kGTC = 64, kGTP = 32;
+
 __global__ __launch_bounds__(256) void k_born_green(int F, int C, int P, const float *omega,
                                                     const float *cells, const float *pts,
                                                     double slow, double rho0, float2 *G,
                                                     float2 *Gx, float2 *Gz)
 {
-    const long long n = (long long)F * C * P;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (long long)gridDim.x * blockDim.x) {
-        const int p = (int)(i % P);
-        const long long fc = i / P;
-        const int c = (int)(fc % C);
-        const int f = (int)(fc / C);
-        const double dx = (double)cells[2 * c] - (double)pts[2 * p];
-        const double dz = (double)cells[2 * c + 1] - (double)pts[2 * p + 1];
-        const double r = sqrt(dx * dx + dz * dz);
-        float2 g = make_float2(0.f, 0.f), gx = g, gz = g;
-        if (r > 0.0) {
-            const double k = (double)omega[f] * slow;
-            double2 h0, h1;
-            hankel01(k * r, h0, h1);
-            // G = (i rho0/4)(J0 + i Y0); grad = (rho0 k/4)(Y1 - i J1) (x - y)/r
-            const double a = 0.25 * rho0;
-            g = make_float2((float)(-a * h0.y), (float)(a * h0.x));
-            const double b = a * k / r;
-            gx = make_float2((float)(b * h1.y * dx), (float)(-b * h1.x * dx));
-            gz = make_float2((float)(b * h1.y * dz), (float)(-b * h1.x * dz));
-        }
-        G[i] = g;
-        if (Gx) {
-            Gx[i] = gx;
-            Gz[i] = gz;
+    constexpr int PER = kGTP / 4;   // points per thread
+    __shared__ float2 tile[kGTC][kGTP + 1];
+    const int f = blockIdx.z;
+    const int c0 = blockIdx.x * kGTC, p0 = blockIdx.y * kGTP;
+    const int lc = (int)(threadIdx.x & 63), w = (int)(threadIdx.x >> 6);
+    const int c = c0 + lc;
+    const bool live = c < C;
+    const double cx = live ? (double)cells[2 * c] : 0.0;
+    const double cz = live ? (double)cells[2 * c + 1] : 0.0;
+    const double k = (double)omega[f] * slow;
+    float2 g[PER], gx[PER], gz[PER];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int p = p0 + w * PER + j;
+        g[j] = gx[j] = gz[j] = make_float2(0.f, 0.f);
+        if (live && p < P)
+            green_entry(cx, cz, (double)pts[2 * p], (double)pts[2 * p + 1], k, rho0, g[j],
+                        gx[j], gz[j]);
+    }
+    const long long base = (long long)f * C;
+    const int np = min(kGTP, P - p0);
+#pragma unroll 1
+    for (int t = 0; t < 3; ++t) {
+        float2 *out = t == 0 ? G : (t == 1 ? Gx : Gz);
+        if (!out)
+            break;
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < PER; ++j)
+            tile[lc][w * PER + j] = t == 0 ? g[j] : (t == 1 ? gx[j] : gz[j]);
+        __syncthreads();
+        for (int e = (int)threadIdx.x; e < kGTC * kGTP; e += 256) {
+            const int rc = e / kGTP, jp = e % kGTP;
+            if (c0 + rc < C && jp < np)
+                out[(base + c0 + rc) * P + p0 + jp] = tile[rc][jp];
         }
     }
 }
@@ -811,9 +846,10 @@ void launch_born_green(int F, int C, int P, const float *omega, const float *cel
     const long long n = (long long)F * C * P;
     if (n <= 0)
         return;
-    hipLaunchKernelGGL(k_born_green, dim3(grid_for(n, 256)), dim3(256), 0, st, F, C, P, omega,
-                       cells, pts, std::sqrt(rho0 / K0), rho0, (float2 *)G, (float2 *)Gx,
-                       (float2 *)Gz);
+    const dim3 grid((unsigned)((C + kGTC - 1) / kGTC), (unsigned)((P + kGTP - 1) / kGTP),
+                    (unsigned)F);
+    hipLaunchKernelGGL(k_born_green, grid, dim3(256), 0, st, F, C, P, omega, cells, pts,
+                       std::sqrt(rho0 / K0), rho0, (float2 *)G, (float2 *)Gx, (float2 *)Gz);
 }
 
 // Source chunk width of the vector-FMA data and gradient kernels (used
