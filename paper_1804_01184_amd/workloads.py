@@ -267,12 +267,13 @@ def serving_requests(n_requests=200, seed=None, side=(201, 1201), shots=(8, 64),
 
 def ricker_spectrum(freqs, fpeak, t0=None):
     """Fourier transform, int f(t) exp(i w t) dt, of the unit-peak Ricker
-    wavelet delayed by t0 = 1.5 / fpeak, at frequencies `freqs` (Hz):
-    (2 w^2 / (sqrt(pi) wp^3)) exp(-w^2 / wp^2) exp(i w t0), wp = 2 pi fpeak."""
+    wavelet delayed by t0 = 1.5 / fpeak (the wavelet of `ricker`), at
+    frequencies `freqs` (Hz): (4 sqrt(pi) w^2 / wp^3) exp(-w^2 / wp^2)
+    exp(i w t0), wp = 2 pi fpeak."""
     t0 = 1.5 / fpeak if t0 is None else t0
     w = 2.0 * math.pi * np.asarray(freqs, float)
     wp = 2.0 * math.pi * fpeak
-    return 2.0 * w * w / (math.sqrt(math.pi) * wp ** 3) * np.exp(-(w / wp) ** 2) * \
+    return 4.0 * math.sqrt(math.pi) * w * w / wp ** 3 * np.exp(-(w / wp) ** 2) * \
         np.exp(1j * w * t0)
 
 

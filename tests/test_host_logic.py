@@ -92,3 +92,38 @@ def test_scattering_angles_and_aperture_weights():
     np.testing.assert_array_equal(w, [[1, 1, 0, 1], [1, 1, 1, 0]])
     assert w.dtype == np.float32
     np.testing.assert_array_equal(P.angle_weights(th, 135.0, 180.0), [[0, 0, 1, 0], [0, 0, 0, 1]])
+
+
+def test_ricker_spectrum_is_the_transform_of_the_wavelet():
+    # the source spectrum of the Born forms against a quadrature of the
+    # time-domain wavelet the finite-difference path injects
+    dt, nt, fp = 1e-4, 20000, 25.0
+    t = np.arange(nt) * dt
+    f = W.ricker(nt, dt, fp)
+    freqs = np.array([2.0, 10.0, 25.0, 40.0, 64.0])
+    quad = (f[None, :] * np.exp(1j * 2 * np.pi * freqs[:, None] * t[None, :])).sum(1) * dt
+    np.testing.assert_allclose(W.ricker_spectrum(freqs, fp), quad, rtol=1e-6,
+                               atol=1e-9 * np.abs(quad).max())
+
+
+def test_paper_example_geometry_and_scatterers():
+    w = W.born_paper()
+    assert w.sizes() == {"F": 15, "S": 10, "R": 100, "C": 121 * 121}
+    # every cell inside the 490 m ring; sources and receivers on it
+    assert np.hypot(*w.cells.T).max() < 490.0
+    np.testing.assert_allclose(np.hypot(*w.src_xz.T), 490.0)
+    np.testing.assert_allclose(np.hypot(*w.rec_xz.T), 490.0)
+    for case in ("i", "ii", "iii", "iv", "v", "vi", "vii"):
+        xa, xb, s, known = W.paper_scatterer(case, w)
+        assert known == (case in ("i", "ii", "iv", "v"))
+        assert s.max() == 1.0 and s[60, 60] == 1.0
+        if case in ("i", "ii", "iii"):
+            assert not xb.any() and abs(xa.max() - 0.1) < 1e-12
+        if case in ("iv", "v", "vi"):
+            assert not xa.any() and abs(xb.max() - 0.1) < 1e-12
+    # (vii) carries no bulk-modulus contrast: K = rho Vp^2 unchanged
+    xa, xb, _, _ = W.paper_scatterer("vii", w)
+    np.testing.assert_allclose((1 + xa) ** 2 * (1 + xb), 1.0, atol=1e-12)
+    wf, s, known = W.paper_fd("v")
+    assert wf.padded == (161, 161) and wf.nshots == 10 and wf.nrec == 100
+    assert known and s[60, 60] == 1.0 and wf.rho_true.max() == pytest.approx(2200.0)
