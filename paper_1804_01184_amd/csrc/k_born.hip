@@ -35,10 +35,12 @@ __device__ inline void cmac(float2 &acc, float2 a, float2 b)
 }
 
 // H0 and H1 of the first kind at z > 0, FP64.  For z <= 12 the ascending
-// series of J0, J1, Y0 and Y1 (Abramowitz & Stegun 9.1.10-9.1.13), 34
-// terms; beyond, Hankel's asymptotic expansion (A&S 9.2.5-9.2.10) truncated
-// after 24 terms, below the smallest term at z = 12.  Relative error below
-// 1e-11 against library Hankel functions over (0, 600].
+// series of J0, J1, Y0 and Y1 (Abramowitz & Stegun 9.1.10-9.1.13), up to
+// 34 terms; beyond, Hankel's asymptotic expansion (A&S 9.2.5-9.2.10), up to
+// 24 terms (below the smallest term at z = 12).  Both stop once the terms
+// fall below 1e-18 of the sums (series) or 1e-18 absolute (expansion, whose
+// sums are near 1).  Relative error below 1e-11 against library Hankel
+// functions over (0, 600].
 __device__ inline void hankel01(double z, double2 &h0, double2 &h1)
 {
     if (z <= 12.0) {
@@ -55,6 +57,8 @@ __device__ inline void hankel01(double z, double2 &h0, double2 &h1)
             j1 += t1;
             ps += 1.0 / k + 1.0 / (k + 1);
             s1 += ps * t1;
+            if (fabs(t0) + fabs(t1) < 1e-18 * (fabs(j0) + fabs(j1)))
+                break;
         }
         const double L = log(0.5 * z);
         const double y0 = (2.0 / kPi) * ((L + kEulerGamma) * j0 + s0);
@@ -79,6 +83,8 @@ __device__ inline void hankel01(double z, double2 &h0, double2 &h1)
             P0 += sg * a0;
             P1 += sg * a1;
         }
+        if (fabs(a0) + fabs(a1) < 1e-18)
+            break;
     }
     const double amp = sqrt(2.0 / (kPi * z));
     double s, c;
