@@ -536,25 +536,26 @@ __global__ __launch_bounds__(256) void k_born_wt(int F, int S, int R, const floa
 }
 
 // Receivers staged per step of the matrix-core gradient kernel.
-constexpr int kGRC = 32;
+constexpr int kGRC = 16;
 
 // The gradient sums on the matrix cores.  Per frequency and table,
-// U[s][c] = sum_r W[s][r] A[c][r] is a complex product with k over
+// U_t[s][c] = sum_r W[s][r] A_t[c][r] is a complex product with k over
 // (receiver pair, re/im part), laid out as in k_born_data_mfma: D[s][c] with
 // the weights as the first operand (rows: 16 sources) and the receiver
-// table as the second (columns: 16 cells).  A block stages the receiver
-// rows of its 64 cells (four waves of 16 cells) and the weights of 32
-// receivers in LDS; the epilogue adds Re sum_s Gs[c][s] U[s][c] per lane
-// and the four lane groups holding one cell are summed at the end.
+// table as the second (columns: 16 cells).  A block stages, per chunk of 16
+// receivers, the rows of its 64 cells (four waves of 16 cells) in the three
+// tables and the weights once, in LDS; the three tables' products share the
+// weights.  The epilogue adds Re sum_s Gs_t[c][s] U_t[s][c] per lane and
+// the four lane groups holding one cell are summed at the end.
 // grid: x = blocks of 64 cells, y = frequency ranges.
 template <int NS>
-__global__ __launch_bounds__(256) void k_born_grad_mfma(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_born_grad_mfma(
     int F, int S, int R, int C, int freqs_per_split, int sgroups, const float *omega,
     const float2 *Wt, const float2 *Gs, const float2 *Gsx, const float2 *Gsz, const float2 *Gr,
     const float2 *Grx, const float2 *Grz, float *partK, float *partR)
 {
     constexpr int SW = 16 * NS;
-    __shared__ float2 sA[64][kGRC + 1];
+    __shared__ float2 sA[3][64][kGRC + 1];
     __shared__ float2 sW[kGRC][SW];
     const int wave = (int)(threadIdx.x >> 6), l = (int)(threadIdx.x & 63);
     const int li = l & 15, kk = l >> 4, rpar = kk & 1;
@@ -571,58 +572,71 @@ __global__ __launch_bounds__(256) void k_born_grad_mfma(
     for (int f = f_begin; f < f_end; ++f) {
         const long long fC = (long long)f * C;
         const float2 *W = Wt + (long long)f * R * S;
-#pragma unroll 1
-        for (int t = 0; t < 3; ++t) {
-            const float2 *A = t == 0 ? Gr : (t == 1 ? Grx : Grz);
-            const float2 *B = t == 0 ? Gs : (t == 1 ? Gsx : Gsz);
-            float acc_t = 0.f;
-            for (int sg = 0; sg < sgroups; ++sg) {
-                const int s0 = sg * SW;
-                v4f dre[NS], dim[NS];
+        float acc[3] = {0.f, 0.f, 0.f};
+        for (int sg = 0; sg < sgroups; ++sg) {
+            const int s0 = sg * SW;
+            v4f dre[3][NS], dim[3][NS];
+#pragma unroll
+            for (int t = 0; t < 3; ++t)
 #pragma unroll
                 for (int b = 0; b < NS; ++b) {
-                    dre[b] = v4f{0.f, 0.f, 0.f, 0.f};
-                    dim[b] = v4f{0.f, 0.f, 0.f, 0.f};
+                    dre[t][b] = v4f{0.f, 0.f, 0.f, 0.f};
+                    dim[t][b] = v4f{0.f, 0.f, 0.f, 0.f};
                 }
-                for (int r0 = 0; r0 < R; r0 += kGRC) {
-                    const int nr = min(kGRC, R - r0);
-                    __syncthreads();
-                    for (int e = threadIdx.x; e < 64 * kGRC; e += 256) {
-                        const int row = e / kGRC, j = e % kGRC;
-                        const int cc = cb0 + row;
-                        float2 v = make_float2(0.f, 0.f);
-                        if (cc < C && j < nr)
-                            v = A[(fC + cc) * R + r0 + j];
-                        sA[row][j] = v;
+            for (int r0 = 0; r0 < R; r0 += kGRC) {
+                const int nr = min(kGRC, R - r0);
+                __syncthreads();
+                for (int e = threadIdx.x; e < 64 * kGRC; e += 256) {
+                    const int row = e / kGRC, j = e % kGRC;
+                    const int cc = cb0 + row;
+                    float2 v0 = make_float2(0.f, 0.f), v1 = v0, v2 = v0;
+                    if (cc < C && j < nr) {
+                        const long long o = (fC + cc) * R + r0 + j;
+                        v0 = Gr[o];
+                        v1 = Grx[o];
+                        v2 = Grz[o];
                     }
-                    for (int e = threadIdx.x; e < kGRC * SW; e += 256) {
-                        const int j = e / SW, s = e % SW;
-                        float2 v = make_float2(0.f, 0.f);
-                        if (j < nr && s0 + s < S)
-                            v = W[(long long)(r0 + j) * S + s0 + s];
-                        sW[j][s] = v;
+                    sA[0][row][j] = v0;
+                    sA[1][row][j] = v1;
+                    sA[2][row][j] = v2;
+                }
+                for (int e = threadIdx.x; e < kGRC * SW; e += 256) {
+                    const int j = e / SW, s = e % SW;
+                    float2 v = make_float2(0.f, 0.f);
+                    if (j < nr && s0 + s < S)
+                        v = W[(long long)(r0 + j) * S + s0 + s];
+                    sW[j][s] = v;
+                }
+                __syncthreads();
+#pragma unroll 2
+                for (int p = 0; p < kGRC / 2; ++p) {
+                    const int j = 2 * p + rpar;
+                    float are[NS], aim[NS];
+#pragma unroll
+                    for (int b = 0; b < NS; ++b) {
+                        const float2 w = sW[j][16 * b + li];
+                        are[b] = second ? -w.y : w.x;
+                        aim[b] = second ? w.y : w.x;
                     }
-                    __syncthreads();
-#pragma unroll 4
-                    for (int p = 0; p < kGRC / 2; ++p) {
-                        const int j = 2 * p + rpar;
-                        const float2 a = sA[cw][j];
+#pragma unroll
+                    for (int t = 0; t < 3; ++t) {
+                        const float2 a = sA[t][cw][j];
                         const float bre = second ? a.y : a.x;
                         const float bim = second ? a.x : a.y;
 #pragma unroll
                         for (int b = 0; b < NS; ++b) {
-                            const float2 w = sW[j][16 * b + li];
-                            const float are = second ? -w.y : w.x;
-                            const float aim = second ? w.y : w.x;
-                            dre[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(are, bre, dre[b], 0, 0,
-                                                                          0);
-                            dim[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(aim, bim, dim[b], 0, 0,
-                                                                          0);
+                            dre[t][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(are[b], bre,
+                                                                             dre[t][b], 0, 0, 0);
+                            dim[t][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(aim[b], bim,
+                                                                             dim[t][b], 0, 0, 0);
                         }
                     }
                 }
-                if (live) {
-                    const float2 *brow = B + (fC + cl) * S;
+            }
+            if (live) {
+#pragma unroll
+                for (int t = 0; t < 3; ++t) {
+                    const float2 *brow = (t == 0 ? Gs : (t == 1 ? Gsx : Gsz)) + (fC + cl) * S;
 #pragma unroll
                     for (int b = 0; b < NS; ++b)
 #pragma unroll
@@ -630,19 +644,16 @@ __global__ __launch_bounds__(256) void k_born_grad_mfma(
                             const int s = s0 + 16 * b + 4 * kk + v;
                             if (s < S) {
                                 const float2 g = brow[s];
-                                acc_t = fmaf(g.x, dre[b][v], acc_t);
-                                acc_t = fmaf(-g.y, dim[b][v], acc_t);
+                                acc[t] = fmaf(g.x, dre[t][b][v], acc[t]);
+                                acc[t] = fmaf(-g.y, dim[t][b][v], acc[t]);
                             }
                         }
                 }
             }
-            if (t == 0) {
-                const float w = omega[f];
-                accK = fmaf(w * w, acc_t, accK);
-            } else {
-                accR += acc_t;
-            }
         }
+        const float w = omega[f];
+        accK = fmaf(w * w, acc[0], accK);
+        accR += acc[1] + acc[2];
     }
     // lanes li, li + 16, li + 32, li + 48 hold the same cell
     accK += __shfl_xor(accK, 16);
