@@ -261,8 +261,13 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 // parts, so that Re D = sum ar br - ai bi and Im D = sum ar bi + ai br.
 // A wave computes 32 receivers x 16 NS sources; the four waves of a block
 // take consecutive receiver groups of one (frequency, cell range, source
-// group), and blocks are remapped so that those of one cell range run on
-// one XCD (its L2 serves the shared source tables).
+// group) and share, per chunk of 8 cells, the source tables and cell
+// coefficients staged in LDS; each lane loads its receiver-table parts for
+// the chunk before the staging.  Blocks are remapped so that those of one
+// cell range run on one XCD.
+// Cells per chunk of the matrix-core data kernel.
+constexpr int kDCH = 8;
+
 template <int NS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_born_data_mfma(
     int F, int S, int R, int C, int nsplit, int cells_per_split, int sgroups, int nrg,
@@ -270,6 +275,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     const float *xiR, const float2 *Gs, const float2 *Gsx, const float2 *Gsz, const float2 *Gr,
     const float2 *Grx, const float2 *Grz, float2 *part)
 {
+    constexpr int SW = 16 * NS;
+    __shared__ float2 sB[3][kDCH][SW];
+    __shared__ float sq[2][kDCH];
     const long long per = (nblocks + 7) / 8;
     const long long w = (long long)(blockIdx.x % 8) * per + blockIdx.x / 8;
     if (w >= nblocks)
@@ -282,23 +290,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     const int split = (int)(fsg % nsplit);
     const int f = (int)(fsg / nsplit);
     const int rg = rb * 4 + (int)(threadIdx.x >> 6);
-    if (rg >= nrg)
-        return;
+    // a wave past the last receiver group still stages and waits with the
+    // others; it computes and stores nothing
+    const bool active = rg < nrg;
     const int l = threadIdx.x & 63;
     const int li = l & 15, kk = l >> 4, cpar = kk & 1;
     const bool second = kk >= 2;
-    const int r0 = rg * 32, s0 = sg * 16 * NS;
-    int rA[2], sB[NS];
+    const int r0 = (active ? rg : 0) * 32, s0 = sg * SW;
+    int rA[2];
 #pragma unroll
     for (int t = 0; t < 2; ++t)
         rA[t] = min(r0 + 16 * t + li, R - 1);
-#pragma unroll
-    for (int t = 0; t < NS; ++t)
-        sB[t] = min(s0 + 16 * t + li, S - 1);
     const int c_begin = split * cells_per_split;
     const int c_end = min(C, c_begin + cells_per_split);
     const float wf = omega[f];
     const float aK = wf * wf * dA_K0;
+    const long long fC = (long long)f * C;
+    const int part_off = second ? 1 : 0;
+    const float *Gr1 = (const float *)Gr, *Grx1 = (const float *)Grx, *Grz1 = (const float *)Grz;
     v4f dre[2][NS], dim[2][NS];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -307,82 +316,75 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
             dre[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
             dim[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
         }
-    // operands of one cell pair: the receiver-table part this lane needs
-    // (real part in lanes 0-31, imaginary part in lanes 32-63) and the full
-    // source-table value; two pairs in flight, loaded one pair ahead of the
-    // products.  A pair past the range loads the last cell and weighs 0.
-    struct Pair {
-        float a[3][2];
-        float2 b[3][NS];
-        float xk, xr;
-        bool ok;
-    };
-    const int part_off = second ? 1 : 0;
-    const float *Gr1 = (const float *)Gr, *Grx1 = (const float *)Grx, *Grz1 = (const float *)Grz;
-    auto load = [&](int c0, Pair &P) {
-        P.ok = c0 + cpar < c_end;
-        const int c = P.ok ? c0 + cpar : c_end - 1;
-        P.xk = xiK[c];
-        P.xr = xiR[c];
-        const long long oA = ((long long)f * C + c) * R, oB = ((long long)f * C + c) * S;
+
+    for (int c0 = c_begin; c0 < c_end; c0 += kDCH) {
+        const int nc = min(kDCH, c_end - c0);
+        // this lane's receiver-table parts for the chunk's cell pairs (real
+        // parts in lanes 0-31, imaginary in 32-63), loaded before the
+        // staging so that both are in flight together
+        float av[kDCH / 2][3][2];
 #pragma unroll
-        for (int a = 0; a < 2; ++a) {
-            const long long o = 2 * (oA + rA[a]) + part_off;
-            P.a[0][a] = Gr1[o];
-            P.a[1][a] = Grx1[o];
-            P.a[2][a] = Grz1[o];
-        }
-#pragma unroll
-        for (int b = 0; b < NS; ++b) {
-            P.b[0][b] = Gs[oB + sB[b]];
-            P.b[1][b] = Gsx[oB + sB[b]];
-            P.b[2][b] = Gsz[oB + sB[b]];
-        }
-    };
-    auto product = [&](const Pair &P) {
-        const float qK = P.ok ? aK * P.xk : 0.f;
-        const float qR = P.ok ? cR * P.xr : 0.f;
-#pragma unroll
-        for (int t = 0; t < 3; ++t) {
-            const float q = t == 0 ? qK : qR;
-            float aRe[2], aIm[2], bRe[NS], bIm[NS];
+        for (int p = 0; p < kDCH / 2; ++p) {
+            const int c = c0 + min(2 * p + cpar, nc - 1);
 #pragma unroll
             for (int a = 0; a < 2; ++a) {
-                const float v = q * P.a[t][a];
-                aRe[a] = second ? -v : v;
-                aIm[a] = v;
+                const long long o = 2 * (((fC + c) * R) + rA[a]) + part_off;
+                av[p][0][a] = active ? Gr1[o] : 0.f;
+                av[p][1][a] = active ? Grx1[o] : 0.f;
+                av[p][2][a] = active ? Grz1[o] : 0.f;
             }
-#pragma unroll
-            for (int b = 0; b < NS; ++b) {
-                bRe[b] = second ? P.b[t][b].y : P.b[t][b].x;
-                bIm[b] = second ? P.b[t][b].x : P.b[t][b].y;
-            }
-#pragma unroll
-            for (int a = 0; a < 2; ++a)
-#pragma unroll
-                for (int b = 0; b < NS; ++b) {
-                    dre[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(aRe[a], bRe[b], dre[a][b],
-                                                                     0, 0, 0);
-                    dim[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(aIm[a], bIm[b], dim[a][b],
-                                                                     0, 0, 0);
-                }
         }
-    };
-    Pair P0, P1;
-    load(c_begin, P0);
-    // the scheduling barriers keep each pair's loads ahead of the other
-    // pair's products (left alone, the scheduler sinks them next to their
-    // uses and the products wait on fresh loads)
-    for (int c0 = c_begin; c0 < c_end; c0 += 4) {
-        load(c0 + 2, P1);
-        __builtin_amdgcn_sched_barrier(0);
-        product(P0);
-        __builtin_amdgcn_sched_barrier(0);
-        load(c0 + 4, P0);
-        __builtin_amdgcn_sched_barrier(0);
-        product(P1);
-        __builtin_amdgcn_sched_barrier(0);
+        __syncthreads();
+        for (int e = threadIdx.x; e < 3 * kDCH * SW; e += 256) {
+            const int t = e / (kDCH * SW), rem = e % (kDCH * SW);
+            const int cc = rem / SW, sc = rem % SW;
+            const float2 *B = t == 0 ? Gs : (t == 1 ? Gsx : Gsz);
+            float2 v = make_float2(0.f, 0.f);
+            if (cc < nc && s0 + sc < S)
+                v = B[(fC + c0 + cc) * S + s0 + sc];
+            sB[t][cc][sc] = v;
+        }
+        if (threadIdx.x < kDCH) {
+            const int cc = threadIdx.x;
+            sq[0][cc] = cc < nc ? aK * xiK[c0 + cc] : 0.f;
+            sq[1][cc] = cc < nc ? cR * xiR[c0 + cc] : 0.f;
+        }
+        __syncthreads();
+        if (active) {
+#pragma unroll
+            for (int p = 0; p < kDCH / 2; ++p) {
+                const int cc = 2 * p + cpar;
+#pragma unroll
+                for (int t = 0; t < 3; ++t) {
+                    const float q = sq[t == 0 ? 0 : 1][cc];
+                    float aRe[2], aIm[2], bRe[NS], bIm[NS];
+#pragma unroll
+                    for (int a = 0; a < 2; ++a) {
+                        const float v = q * av[p][t][a];
+                        aRe[a] = second ? -v : v;
+                        aIm[a] = v;
+                    }
+#pragma unroll
+                    for (int b = 0; b < NS; ++b) {
+                        const float2 v = sB[t][cc][16 * b + li];
+                        bRe[b] = second ? v.y : v.x;
+                        bIm[b] = second ? v.x : v.y;
+                    }
+#pragma unroll
+                    for (int a = 0; a < 2; ++a)
+#pragma unroll
+                        for (int b = 0; b < NS; ++b) {
+                            dre[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(aRe[a], bRe[b],
+                                                                             dre[a][b], 0, 0, 0);
+                            dim[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(aIm[a], bIm[b],
+                                                                             dim[a][b], 0, 0, 0);
+                        }
+                }
+            }
+        }
     }
+    if (!active)
+        return;
     float2 *out = part + ((long long)split * F + f) * S * R;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
