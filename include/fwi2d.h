@@ -288,7 +288,7 @@ fwi_status fwi_born_green(int32_t F, const float *omega, int32_t C, const float 
 
 /* Workspace bytes (256-byte aligned) that fwi_born_data, fwi_born_gradient
  * and fwi_born_misfit need for these sizes: the partial sums of the split
- * launches and, for the gradient with 12 sources or more, the residual
+ * launches and, for the gradient with 2 sources or more, the residual
  * weights transposed for the matrix cores.  The workspace is only used
  * during the call's kernels; calls on one workspace must be ordered (same
  * stream).  0 for sizes the calls reject. */
@@ -298,7 +298,7 @@ size_t fwi_born_workspace_bytes(int32_t F, int32_t S, int32_t R, int32_t C);
  * source tables Gs, Gsx, Gsz [F][C][S], the receiver tables Gr, Grx, Grz
  * [F][C][R] and the direct wave Gd [F][S][R] (NULL: scattered data only).
  * spec [F] complex.  FP32 arithmetic with FP32 accumulation, on the FP32
- * matrix cores from 12 sources up: per frequency the cells are cut into
+ * matrix cores from 9 sources up: per frequency the cells are cut into
  * ranges summed in a fixed order (bitwise repeatable).  FWI_EINVAL for
  * sizes out of range (F > 65535, S > 4194240, S R >= 2^31) or a NULL
  * required array; FWI_EWORKSPACE if work is NULL, misaligned or smaller

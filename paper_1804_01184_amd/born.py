@@ -380,7 +380,8 @@ def hessian_summary(H):
 
 
 # Dense FP32 matrix-core rate of the chip (256 CUs x 2.4 GHz): the Born
-# data and gradient sums run on v_mfma_f32_16x16x4f32 from 12 sources up.
+# data sum runs on v_mfma_f32_16x16x4f32 from 9 sources up, the gradient sum
+# from 2.
 PEAK_FP32_TFLOPS = 157.3
 
 

@@ -1272,7 +1272,7 @@ BornWs born_ws(int F, int S, int R, int C)
     BornWs w;
     w.data = align_up((size_t)b.nsplit * F * S * R * 2 * sizeof(float), kAlign);
     w.grad = born_grad_wt_offset(b, C) +
-             (b.ns ? align_up((size_t)F * S * R * 2 * sizeof(float), kAlign) : 0);
+             (b.gns ? align_up((size_t)F * S * R * 2 * sizeof(float), kAlign) : 0);
     w.misfit = align_up((size_t)misfit_blocks(2LL * F * S * R) * sizeof(float), kAlign);
     w.total = std::max(w.data, std::max(w.grad, w.misfit));
     return w;

@@ -228,6 +228,8 @@ struct BornSplit {
     int ts;               // source chunk width (template instance)
     int ns;               // data on the matrix cores: 16-wide source tiles per wave (0: off)
     int nrg, sgroups;     // matrix-core data: 32-receiver groups, source groups
+    int gns, gsgroups;    // gradient on the matrix cores: source tiles per wave (0: off),
+                          // source groups
     int block, rtiles;    // data: receivers per block, receiver tiles
     int schunks;          // source chunks
     int nsplit;           // data: cell ranges summed by the finishing kernel

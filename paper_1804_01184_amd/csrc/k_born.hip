@@ -871,23 +871,28 @@ void launch_born_green(int F, int C, int P, const float *omega, const float *cel
                        std::sqrt(rho0 / K0), rho0, (float2 *)G, (float2 *)Gx, (float2 *)Gz);
 }
 
-// Source chunk width of the vector-FMA data and gradient kernels (used
-// below 12 sources): the smallest instantiated width covering S.
+// Source chunk width of the vector-FMA data kernel (below 9 sources): the
+// smallest instantiated width covering S.
 static int born_ts(int S)
 {
-    const int opts[] = {1, 2, 4, 8, 16};
+    const int opts[] = {1, 2, 4, 8};
     for (int t : opts)
         if (t >= S)
             return t;
-    return 16;
+    return 8;
 }
 
 BornSplit born_data_split(int F, int S, int R, int C)
 {
     BornSplit b;
     b.ts = born_ts(S);
-    // matrix-core path from 12 sources: 16-wide source tiles
-    b.ns = S >= 12 ? std::min(4, (S + 15) / 16) : 0;
+    // matrix cores for the data from 9 sources (below, the vector kernel's
+    // chunk of 8 wastes less than a 16-wide tile) and for the gradient from
+    // 2 (measured on the config-2 geometry: the vector gradient takes
+    // 18-21 ms at 4-11 sources, the matrix-core one 11 ms)
+    b.ns = S >= 9 ? std::min(4, (S + 15) / 16) : 0;
+    b.gns = S >= 2 ? std::min(4, (S + 15) / 16) : 0;
+    b.gsgroups = b.gns ? (S + 16 * b.gns - 1) / (16 * b.gns) : 0;
     int step = kCB;
     long long base;
     long long target;
@@ -927,8 +932,8 @@ BornSplit born_data_split(int F, int S, int R, int C)
         b.nsplit = (C + per - 1) / per;
     // gradient: cell blocks x frequency splits (matrix cores: blocks of 64
     // cells, about 8 rounds of 4 resident blocks per CU)
-    b.cblocks = b.ns ? (C + 63) / 64 : (C + kGradBlock - 1) / kGradBlock;
-    const long long gtarget = b.ns ? 8192 : 2048;
+    b.cblocks = b.gns ? (C + 63) / 64 : (C + kGradBlock - 1) / kGradBlock;
+    const long long gtarget = b.gns ? 8192 : 2048;
     const long long gw = b.cblocks > 0 ? (gtarget + b.cblocks - 1) / b.cblocks : 1;
     b.fsplit = (int)std::max(1LL, std::min<long long>(gw, std::max(F, 1)));
     b.freqs_per_split = F > 0 ? (F + b.fsplit - 1) / b.fsplit : 0;
@@ -992,7 +997,7 @@ void launch_born_data(const BornSplit &b, int F, int S, int R, int C, const floa
                    g2(Gr), g2(Grx), g2(Grz), (float2 *)part, st);                          \
         break;
         switch (b.ts) {
-            BORN_DATA(1) BORN_DATA(2) BORN_DATA(4) BORN_DATA(8) BORN_DATA(16)
+            BORN_DATA(1) BORN_DATA(2) BORN_DATA(4) BORN_DATA(8)
         }
 #undef BORN_DATA
     }
@@ -1027,7 +1032,7 @@ void launch_born_gradient(const BornSplit &b, int F, int S, int R, int C, const 
         return;
     }
     auto g2 = [](const float *p) { return (const float2 *)p; };
-    if (b.ns > 0) {
+    if (b.gns > 0) {
         float2 *Wt = (float2 *)((char *)part + born_grad_wt_offset(b, C));
         const long long n = (long long)F * S * R;
         hipLaunchKernelGGL(k_born_wt, dim3(grid_for(n, 256)), dim3(256), 0, st, F, S, R,
@@ -1035,24 +1040,18 @@ void launch_born_gradient(const BornSplit &b, int F, int S, int R, int C, const 
 #define BORN_GMFMA(N)                                                                      \
     case N:                                                                                \
         hipLaunchKernelGGL(k_born_grad_mfma<N>, dim3(b.cblocks, b.fsplit), dim3(256), 0, st, \
-                           F, S, R, C, b.freqs_per_split, b.sgroups, omega, Wt, g2(Gs),      \
+                           F, S, R, C, b.freqs_per_split, b.gsgroups, omega, Wt, g2(Gs),     \
                            g2(Gsx), g2(Gsz), g2(Gr), g2(Grx), g2(Grz), partK, partR);        \
         break;
-        switch (b.ns) { BORN_GMFMA(1) BORN_GMFMA(2) BORN_GMFMA(3) BORN_GMFMA(4) }
+        switch (b.gns) { BORN_GMFMA(1) BORN_GMFMA(2) BORN_GMFMA(3) BORN_GMFMA(4) }
 #undef BORN_GMFMA
         hipLaunchKernelGGL(k_born_grad_finish, dim3((C + 255) / 256), dim3(256), 0, st, C,
                            b.fsplit, dA_K0, cR, partK, partR, gK, gR);
         return;
     }
-#define BORN_GRAD(T)                                                                       \
-    case T:                                                                                \
-        grad_ts<T>(b, F, S, R, C, omega, g2(spec), g2(resid), g2(Gs), g2(Gsx), g2(Gsz),    \
-                   g2(Gr), g2(Grx), g2(Grz), partK, partR, st);                            \
-        break;
-    switch (b.ts) {
-        BORN_GRAD(1) BORN_GRAD(2) BORN_GRAD(4) BORN_GRAD(8) BORN_GRAD(16)
-    }
-#undef BORN_GRAD
+    // one source (gns == 0 only for S == 1)
+    grad_ts<1>(b, F, S, R, C, omega, g2(spec), g2(resid), g2(Gs), g2(Gsx), g2(Gsz), g2(Gr),
+               g2(Grx), g2(Grz), partK, partR, st);
     hipLaunchKernelGGL(k_born_grad_finish, dim3((C + 255) / 256), dim3(256), 0, st, C, b.fsplit,
                        dA_K0, cR, partK, partR, gK, gR);
 }

@@ -95,10 +95,11 @@ def test_green_tables_match_oracle(env):
     assert maxrel(prob.Gd.cpu().numpy(), gd) <= 1e-5
 
 
-# vector path: 1, 3, 8, 11 sources (chunk widths 1, 4, 8, 16); matrix-core
-# path: 17, 41, 70 sources (2, 3, 4 source tiles; 70 needs two groups)
-SHAPES = [(3, 1, 70, 300), (2, 3, 37, 529), (2, 17, 64, 1000), (1, 41, 130, 777),
-          (2, 70, 20, 400), (5, 8, 200, 33), (2, 11, 45, 250)]
+# vector data: 1, 2, 3, 8 sources (chunk widths 1, 2, 4, 8); vector gradient:
+# 1 source.  Matrix-core data: 11, 17, 41, 70 sources (1, 2, 3, 4 source
+# tiles; 70 needs two groups); matrix-core gradient: the same and 2, 3, 8.
+SHAPES = [(3, 1, 70, 300), (4, 2, 90, 211), (2, 3, 37, 529), (2, 17, 64, 1000),
+          (1, 41, 130, 777), (2, 70, 20, 400), (5, 8, 200, 33), (2, 11, 45, 250)]
 
 
 @pytest.mark.parametrize("F,S,R,C", SHAPES)
