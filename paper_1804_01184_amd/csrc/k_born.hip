@@ -262,9 +262,11 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 // A wave computes 32 receivers x 16 NS sources; the four waves of a block
 // take consecutive receiver groups of one (frequency, cell range, source
 // group) and share, per chunk of 8 cells, the source tables and cell
-// coefficients staged in LDS; each lane loads its receiver-table parts for
-// the chunk before the staging.  Blocks are remapped so that those of one
-// cell range run on one XCD.
+// coefficients staged in LDS (two buffers).  The next chunk is loaded while
+// one is computed: its source side into registers, stored to the other
+// buffer after the computation, and each lane's receiver-table parts of a
+// cell pair as soon as the current chunk's pair has been consumed.  Blocks
+// are remapped so that those of one cell range run on one XCD.
 // Cells per chunk of the matrix-core data kernel.
 constexpr int kDCH = 8;
 
@@ -276,8 +278,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     const float2 *Grx, const float2 *Grz, float2 *part)
 {
     constexpr int SW = 16 * NS;
-    __shared__ float2 sB[3][kDCH][SW];
-    __shared__ float sq[2][kDCH];
+    constexpr int NST = (3 * kDCH * SW + 255) / 256;
+    __shared__ float2 sB[2][3][kDCH][SW];
+    __shared__ float sq[2][2][kDCH];
     const long long per = (nblocks + 7) / 8;
     const long long w = (long long)(blockIdx.x % 8) * per + blockIdx.x / 8;
     if (w >= nblocks)
@@ -316,57 +319,94 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
             dre[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
             dim[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
         }
-
+    float av[kDCH / 2][3][2];
+    float2 stg[NST];
+    float sqv = 0.f;
+    const int qc = threadIdx.x % kDCH;
+    const bool isK = (threadIdx.x / kDCH) % 2 == 0;
+    const float *xq = isK ? xiK : xiR;
+    const float qcoef = threadIdx.x < 2 * kDCH ? (isK ? aK : cR) : 0.f;
+    // receiver-table parts of cell pair P of the chunk at CN
+#define LOAD_PAIR(CN, P)                                                                   \
+    {                                                                                      \
+        const int nc_ = min(kDCH, c_end - (CN));                                           \
+        const int c_ = (CN) + min(2 * (P) + cpar, nc_ - 1);                                \
+        _Pragma("unroll") for (int a = 0; a < 2; ++a)                                      \
+        {                                                                                  \
+            const long long o = 2 * (((fC + c_) * R) + rA[a]) + part_off;                  \
+            av[P][0][a] = Gr1[o];                                                          \
+            av[P][1][a] = Grx1[o];                                                         \
+            av[P][2][a] = Grz1[o];                                                         \
+        }                                                                                  \
+    }
+    // this thread's share of the chunk's source tables and coefficients
+#define LOAD_STAGE(CN)                                                                     \
+    {                                                                                      \
+        const int nc_ = min(kDCH, c_end - (CN));                                           \
+        _Pragma("unroll") for (int j = 0; j < NST; ++j)                                    \
+        {                                                                                  \
+            const int e = (int)threadIdx.x + 256 * j;                                      \
+            const int t = e / (kDCH * SW), rem = e % (kDCH * SW);                          \
+            const int cc = rem / SW, sc = rem % SW;                                        \
+            const float2 *B = t == 0 ? Gs : (t == 1 ? Gsx : Gsz);                          \
+            const bool ok = e < 3 * kDCH * SW && cc < nc_ && s0 + sc < S;                  \
+            const float2 v = B[ok ? (fC + (CN) + cc) * S + s0 + sc : 0];                   \
+            stg[j] = ok ? v : make_float2(0.f, 0.f);                                       \
+        }                                                                                  \
+        const float x_ = xq[(CN) + min(qc, nc_ - 1)];                                      \
+        sqv = qc < nc_ ? qcoef * x_ : 0.f;                                                 \
+    }
+#define STORE_STAGE(BUF)                                                                   \
+    {                                                                                      \
+        _Pragma("unroll") for (int j = 0; j < NST; ++j)                                    \
+        {                                                                                  \
+            const int e = (int)threadIdx.x + 256 * j;                                      \
+            if (e < 3 * kDCH * SW) {                                                       \
+                const int t = e / (kDCH * SW), rem = e % (kDCH * SW);                      \
+                sB[BUF][t][rem / SW][rem % SW] = stg[j];                                   \
+            }                                                                              \
+        }                                                                                  \
+        if (threadIdx.x < 2 * kDCH)                                                        \
+            sq[BUF][threadIdx.x / kDCH][threadIdx.x % kDCH] = sqv;                         \
+    }
+    if (c_begin < c_end) {
+#pragma unroll
+        for (int p = 0; p < kDCH / 2; ++p)
+            LOAD_PAIR(c_begin, p)
+        LOAD_STAGE(c_begin)
+        STORE_STAGE(0)
+    }
+    __syncthreads();
+    int buf = 0;
     for (int c0 = c_begin; c0 < c_end; c0 += kDCH) {
-        const int nc = min(kDCH, c_end - c0);
-        // this lane's receiver-table parts for the chunk's cell pairs (real
-        // parts in lanes 0-31, imaginary in 32-63), loaded before the
-        // staging so that both are in flight together
-        float av[kDCH / 2][3][2];
+        // the next chunk (this one again after the last) is loaded while
+        // this one is computed: its source side into registers for the next
+        // LDS buffer, each cell pair's receiver side once this chunk's pair
+        // has been consumed
+        const int cn = c0 + kDCH < c_end ? c0 + kDCH : c0;
+        LOAD_STAGE(cn)
 #pragma unroll
         for (int p = 0; p < kDCH / 2; ++p) {
-            const int c = c0 + min(2 * p + cpar, nc - 1);
+            const int cc = 2 * p + cpar;
+            float aRe[3][2], aIm[3][2];
 #pragma unroll
-            for (int a = 0; a < 2; ++a) {
-                const long long o = 2 * (((fC + c) * R) + rA[a]) + part_off;
-                av[p][0][a] = active ? Gr1[o] : 0.f;
-                av[p][1][a] = active ? Grx1[o] : 0.f;
-                av[p][2][a] = active ? Grz1[o] : 0.f;
+            for (int t = 0; t < 3; ++t) {
+                const float q = sq[buf][t == 0 ? 0 : 1][cc];
+#pragma unroll
+                for (int a = 0; a < 2; ++a) {
+                    const float v = q * av[p][t][a];
+                    aRe[t][a] = second ? -v : v;
+                    aIm[t][a] = v;
+                }
             }
-        }
-        __syncthreads();
-        for (int e = threadIdx.x; e < 3 * kDCH * SW; e += 256) {
-            const int t = e / (kDCH * SW), rem = e % (kDCH * SW);
-            const int cc = rem / SW, sc = rem % SW;
-            const float2 *B = t == 0 ? Gs : (t == 1 ? Gsx : Gsz);
-            float2 v = make_float2(0.f, 0.f);
-            if (cc < nc && s0 + sc < S)
-                v = B[(fC + c0 + cc) * S + s0 + sc];
-            sB[t][cc][sc] = v;
-        }
-        if (threadIdx.x < kDCH) {
-            const int cc = threadIdx.x;
-            sq[0][cc] = cc < nc ? aK * xiK[c0 + cc] : 0.f;
-            sq[1][cc] = cc < nc ? cR * xiR[c0 + cc] : 0.f;
-        }
-        __syncthreads();
-        if (active) {
-#pragma unroll
-            for (int p = 0; p < kDCH / 2; ++p) {
-                const int cc = 2 * p + cpar;
+            LOAD_PAIR(cn, p)
+            if (active) {
 #pragma unroll
                 for (int t = 0; t < 3; ++t) {
-                    const float q = sq[t == 0 ? 0 : 1][cc];
-                    float aRe[2], aIm[2], bRe[NS], bIm[NS];
-#pragma unroll
-                    for (int a = 0; a < 2; ++a) {
-                        const float v = q * av[p][t][a];
-                        aRe[a] = second ? -v : v;
-                        aIm[a] = v;
-                    }
+                    float bRe[NS], bIm[NS];
 #pragma unroll
                     for (int b = 0; b < NS; ++b) {
-                        const float2 v = sB[t][cc][16 * b + li];
+                        const float2 v = sB[buf][t][cc][16 * b + li];
                         bRe[b] = second ? v.y : v.x;
                         bIm[b] = second ? v.x : v.y;
                     }
@@ -374,15 +414,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                     for (int a = 0; a < 2; ++a)
 #pragma unroll
                         for (int b = 0; b < NS; ++b) {
-                            dre[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(aRe[a], bRe[b],
-                                                                             dre[a][b], 0, 0, 0);
-                            dim[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(aIm[a], bIm[b],
-                                                                             dim[a][b], 0, 0, 0);
+                            dre[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                                aRe[t][a], bRe[b], dre[a][b], 0, 0, 0);
+                            dim[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                                aIm[t][a], bIm[b], dim[a][b], 0, 0, 0);
                         }
                 }
             }
         }
+        STORE_STAGE(buf ^ 1)
+        __syncthreads();
+        buf ^= 1;
     }
+#undef LOAD_PAIR
+#undef LOAD_STAGE
+#undef STORE_STAGE
     if (!active)
         return;
     float2 *out = part + ((long long)split * F + f) * S * R;
@@ -538,25 +584,30 @@ __global__ __launch_bounds__(256) void k_born_wt(int F, int S, int R, const floa
 }
 
 // Receivers staged per step of the matrix-core gradient kernel.
-constexpr int kGRC = 16;
+constexpr int kGRC = 8;
 
 // The gradient sums on the matrix cores.  Per frequency and table,
 // U_t[s][c] = sum_r W[s][r] A_t[c][r] is a complex product with k over
 // (receiver pair, re/im part), laid out as in k_born_data_mfma: D[s][c] with
 // the weights as the first operand (rows: 16 sources) and the receiver
-// table as the second (columns: 16 cells).  A block stages, per chunk of 16
+// table as the second (columns: 16 cells).  A block stages, per chunk of 8
 // receivers, the rows of its 64 cells (four waves of 16 cells) in the three
 // tables and the weights once, in LDS; the three tables' products share the
-// weights.  The epilogue adds Re sum_s Gs_t[c][s] U_t[s][c] per lane and
-// the four lane groups holding one cell are summed at the end.
+// weights.  The next chunk is loaded into registers while one is computed
+// (three waves per SIMD; two for four source tiles, whose accumulators take
+// 96 registers).  The epilogue adds Re sum_s Gs_t[c][s] U_t[s][c] per lane
+// and the four lane groups holding one cell are summed at the end.
 // grid: x = blocks of 64 cells, y = frequency ranges.
 template <int NS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_born_grad_mfma(
-    int F, int S, int R, int C, int freqs_per_split, int sgroups, const float *omega,
-    const float2 *Wt, const float2 *Gs, const float2 *Gsx, const float2 *Gsz, const float2 *Gr,
-    const float2 *Grx, const float2 *Grz, float *partK, float *partR)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NS >= 4 ? 2 : 3))) void
+k_born_grad_mfma(int F, int S, int R, int C, int freqs_per_split, int sgroups,
+                 const float *omega, const float2 *Wt, const float2 *Gs, const float2 *Gsx,
+                 const float2 *Gsz, const float2 *Gr, const float2 *Grx, const float2 *Grz,
+                 float *partK, float *partR)
 {
     constexpr int SW = 16 * NS;
+    constexpr int kGA = 64 * kGRC / 256, kGW = (kGRC * SW + 255) / 256;
+    static_assert(64 * kGRC % 256 == 0, "receiver rows split evenly over the block");
     __shared__ float2 sA[3][64][kGRC + 1];
     __shared__ float2 sW[kGRC][SW];
     const int wave = (int)(threadIdx.x >> 6), l = (int)(threadIdx.x & 63);
@@ -585,31 +636,53 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                     dre[t][b] = v4f{0.f, 0.f, 0.f, 0.f};
                     dim[t][b] = v4f{0.f, 0.f, 0.f, 0.f};
                 }
+            // a chunk's receiver rows of the block's cells (three tables) and
+            // weights, loaded into registers one chunk ahead
+            float2 ra[kGA][3], rw[kGW];
+#define GRAD_LOAD(R0)                                                                      \
+    {                                                                                      \
+        const int nr_ = min(kGRC, R - (R0));                                               \
+        _Pragma("unroll") for (int k = 0; k < kGA; ++k)                                    \
+        {                                                                                  \
+            const int e = (int)threadIdx.x + 256 * k;                                      \
+            const int row = e / kGRC, j = e % kGRC;                                        \
+            const bool ok = cb0 + row < C && j < nr_;                                      \
+            const long long o = ok ? (fC + cb0 + row) * R + (R0) + j : 0;                  \
+            const float2 v0 = Gr[o], v1 = Grx[o], v2 = Grz[o];                             \
+            ra[k][0] = make_float2(ok ? v0.x : 0.f, ok ? v0.y : 0.f);                      \
+            ra[k][1] = make_float2(ok ? v1.x : 0.f, ok ? v1.y : 0.f);                      \
+            ra[k][2] = make_float2(ok ? v2.x : 0.f, ok ? v2.y : 0.f);                      \
+        }                                                                                  \
+        _Pragma("unroll") for (int k = 0; k < kGW; ++k)                                    \
+        {                                                                                  \
+            const int e = (int)threadIdx.x + 256 * k;                                      \
+            const int j = e / SW, s = e % SW;                                              \
+            const bool ok = e < kGRC * SW && j < nr_ && s0 + s < S;                        \
+            const float2 v = W[ok ? (long long)((R0) + j) * S + s0 + s : 0];               \
+            rw[k] = make_float2(ok ? v.x : 0.f, ok ? v.y : 0.f);                           \
+        }                                                                                  \
+    }
+            GRAD_LOAD(0)
             for (int r0 = 0; r0 < R; r0 += kGRC) {
-                const int nr = min(kGRC, R - r0);
                 __syncthreads();
-                for (int e = threadIdx.x; e < 64 * kGRC; e += 256) {
-                    const int row = e / kGRC, j = e % kGRC;
-                    const int cc = cb0 + row;
-                    float2 v0 = make_float2(0.f, 0.f), v1 = v0, v2 = v0;
-                    if (cc < C && j < nr) {
-                        const long long o = (fC + cc) * R + r0 + j;
-                        v0 = Gr[o];
-                        v1 = Grx[o];
-                        v2 = Grz[o];
-                    }
-                    sA[0][row][j] = v0;
-                    sA[1][row][j] = v1;
-                    sA[2][row][j] = v2;
+#pragma unroll
+                for (int k = 0; k < kGA; ++k) {
+                    const int e = (int)threadIdx.x + 256 * k;
+#pragma unroll
+                    for (int t = 0; t < 3; ++t)
+                        sA[t][e / kGRC][e % kGRC] = ra[k][t];
                 }
-                for (int e = threadIdx.x; e < kGRC * SW; e += 256) {
-                    const int j = e / SW, s = e % SW;
-                    float2 v = make_float2(0.f, 0.f);
-                    if (j < nr && s0 + s < S)
-                        v = W[(long long)(r0 + j) * S + s0 + s];
-                    sW[j][s] = v;
+#pragma unroll
+                for (int k = 0; k < kGW; ++k) {
+                    const int e = (int)threadIdx.x + 256 * k;
+                    if (e < kGRC * SW)
+                        sW[e / SW][e % SW] = rw[k];
                 }
                 __syncthreads();
+                // the next chunk (this one again after the last) is in
+                // flight while this one is computed
+                const int rn = r0 + kGRC < R ? r0 + kGRC : r0;
+                GRAD_LOAD(rn)
 #pragma unroll 2
                 for (int p = 0; p < kGRC / 2; ++p) {
                     const int j = 2 * p + rpar;
@@ -635,6 +708,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                     }
                 }
             }
+#undef GRAD_LOAD
             if (live) {
 #pragma unroll
                 for (int t = 0; t < 3; ++t) {
