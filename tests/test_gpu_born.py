@@ -98,8 +98,12 @@ def test_green_tables_match_oracle(env):
 # vector data: 1, 2, 3, 8 sources (chunk widths 1, 2, 4, 8); vector gradient:
 # 1 source.  Matrix-core data: 11, 17, 41, 70 sources (1, 2, 3, 4 source
 # tiles; 70 needs two groups); matrix-core gradient: the same and 2, 3, 8.
+# Switch points and small sizes: 9 sources (the first matrix-core data
+# count) with a single receiver, 5 sources with fewer receivers than one
+# gradient chunk, and exactly one 16-wide tile with a ragged receiver group.
 SHAPES = [(3, 1, 70, 300), (4, 2, 90, 211), (2, 3, 37, 529), (2, 17, 64, 1000),
-          (1, 41, 130, 777), (2, 70, 20, 400), (5, 8, 200, 33), (2, 11, 45, 250)]
+          (1, 41, 130, 777), (2, 70, 20, 400), (5, 8, 200, 33), (2, 11, 45, 250),
+          (2, 9, 1, 70), (3, 5, 3, 90), (1, 16, 33, 17)]
 
 
 @pytest.mark.parametrize("F,S,R,C", SHAPES)
