@@ -4,7 +4,7 @@ One step = one complete gradient of the least-squares misfit for every shot
 of the workload (forward sweep keeping the pressure history, misfit, adjoint
 sweep with imaging, finalization), chain-ruled into the K-rho, Vp-rho, Ip-rho
 and Vp-Ip parameterizations.  The library keeps the whole history when it
-fits in half the HBM (config 2: 97 GB), else sqrt(nt) checkpoints with
+fits in half the HBM (97 GB for the 401² Gaussian benchmark), else sqrt(nt) checkpoints with
 segment recompute; the checkpointed form is timed beside it.  value = padded cells x time steps x shots /
 seconds per step (Gcell-updates/s; each cell-step counted once although the
 forward, recompute and adjoint sweeps all touch it).
@@ -36,9 +36,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c5"])
+    ap.add_argument("--workload", default="gauss401", choices=["gauss401", "smooth1001", "layered2001"])
     ap.add_argument("--shots", type=int, default=0,
-                    help="evenly spaced subset of the shots (default: all; c5: 32, one GPU's "
+                    help="evenly spaced subset of the shots (default: all; layered2001: 32, one GPU's "
                          "share of 256 shots over 8)")
     ap.add_argument("--band-rows", type=int, default=0)
     ap.add_argument("--shots-per-group", type=int, default=0)
@@ -59,7 +59,7 @@ def parse():
                          "roofline entry is then omitted")
     ap.add_argument("--born", action="store_true",
                     help="schemes I/II instead: one Born gradient per step (frequency-domain "
-                         "config 2), one JSON line")
+                         "form of the 401² Gaussian benchmark), one JSON line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB elementwise kernel (reads 1 GiB, writes 1 GiB) and "
                          "exit: the reference for the HBM traffic counters")
@@ -68,8 +68,8 @@ def parse():
 
 def workload(name, shots=0):
     from paper_1804_01184_amd import workloads as W
-    w = {"c2": W.config2, "c3": W.config3, "c5": W.config5}[name]()
-    if name == "c5" and not shots:
+    w = {"gauss401": W.gauss401, "smooth1001": W.smooth1001, "layered2001": W.layered2001}[name]()
+    if name == "layered2001" and not shots:
         shots = 32
     if shots and shots < w.nshots:
         idx = np.linspace(0, w.nshots - 1, shots).round().astype(int)
@@ -184,7 +184,7 @@ def born_main(args):
     from paper_1804_01184_amd import born, workloads as W
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
-    w = W.born_config2()
+    w = W.born_gauss401()
     sz = w.sizes()
     m = born.measure(w, reps=max(args.steps, 1), device=dev)
     prob = born.BornProblem.of(w, dev)

@@ -15,7 +15,8 @@ change during an inversion), and evaluates
 
 and reduced_hessian() gives the 2x2 Hessian of a point scatterer in any
 parameterization.  ``python -m paper_1804_01184_amd.born`` measures the
-kernels on the frequency-domain form of config 2 and prints the reduced
+kernels on the frequency-domain form of the 401² Gaussian benchmark and
+prints the reduced
 Hessians of the circular acquisition, as one JSON line.
 """
 from __future__ import annotations
@@ -513,12 +514,12 @@ def main(argv=None):
     import argparse
     from . import workloads as W
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2"])
+    ap.add_argument("--workload", default="gauss401", choices=["point101", "gauss401"])
     ap.add_argument("--freqs", type=int, default=32)
     ap.add_argument("--reps", type=int, default=5)
-    ap.add_argument("--invert-c2", type=int, default=0, metavar="ITERS",
+    ap.add_argument("--invert-gauss401", type=int, default=0, metavar="ITERS",
                     help="instead: scheme II steepest descent over every cell of the "
-                         "frequency-domain config 2 (Gaussian Vp anomaly, shape unknown)")
+                         "frequency-domain 401² Gaussian benchmark (Vp anomaly, shape unknown)")
     ap.add_argument("--contrast-table", action="store_true",
                     help="instead: exact and linearised contrasts of every parameterization "
                          "for the point scatterers (i), (iv) and a no-K-contrast scatterer")
@@ -527,11 +528,11 @@ def main(argv=None):
                          "scatterer table in its 10-source, 100-receiver ring geometry")
     ap.add_argument("--invert", type=int, default=0, metavar="ITERS",
                     help="instead: schemes I and II steepest descent on scatterer (i) "
-                         "(frequency-domain config 1, shape known) for ITERS iterations")
+                         "(frequency-domain 101² point benchmark, shape known) for ITERS iterations")
     a = ap.parse_args(argv)
-    if a.invert_c2:
+    if a.invert_gauss401:
         torch.cuda.set_device(0)
-        print(json.dumps(invert_field(W.born_config2(a.freqs), a.invert_c2)), flush=True)
+        print(json.dumps(invert_field(W.born_gauss401(a.freqs), a.invert_gauss401)), flush=True)
         return
     if a.contrast_table:
         torch.cuda.set_device(0)
@@ -545,10 +546,10 @@ def main(argv=None):
         return
     if a.invert:
         torch.cuda.set_device(0)
-        print(json.dumps(invert_point(W.born_config1(a.freqs), a.invert)), flush=True)
+        print(json.dumps(invert_point(W.born_point101(a.freqs), a.invert)), flush=True)
         return
     torch.cuda.set_device(0)
-    w = W.born_config2(a.freqs) if a.workload == "c2" else W.born_config1(a.freqs)
+    w = W.born_gauss401(a.freqs) if a.workload == "gauss401" else W.born_point101(a.freqs)
     out = measure(w, a.reps)
     out.pop("contrasts")
     for k in ("data", "gradient"):

@@ -15,7 +15,7 @@ the angle of the long axis (0 or 90 degrees: uncorrelated parameters, 45 or
 
 Every misfit is one forward and one misfit launch of the library; the 2x2
 fit is host arithmetic on the grid of scalars.  ``python -m
-paper_1804_01184_amd.bowls`` prints the bowls of config 1 (scatterer (i))
+paper_1804_01184_amd.bowls`` prints the bowls of the 101² point benchmark (scatterer (i))
 in the five parameterizations as one JSON line.
 """
 from __future__ import annotations
@@ -85,7 +85,7 @@ def main(argv=None):
     a = ap.parse_args(argv)
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
-    w = W.config1()
+    w = W.point101()
     plan = api.Plan(api.Grid.of(w), w.src_xz, w.rec_xz, device=dev)
     f = torch.tensor(w.wavelet(), dtype=torch.float32, device=dev)
     Kt = torch.tensor(w.rho_true * w.vp_true ** 2, dtype=torch.float32, device=dev)
@@ -95,7 +95,7 @@ def main(argv=None):
     obs = plan.forward("k-rho", Kt, rt, f)
     prof = (Kt != K0).float()            # the point scatterer's support
     i0, j0 = (int(x) for x in torch.nonzero(prof)[0])
-    out = {"workload": "c1 point scatterer (i), Vp-only, shape known", "points": a.points}
+    out = {"workload": "point-101 scatterer (i), Vp-only, shape known", "points": a.points}
     for p in PARAMS:
         m0a, m0b = api.model_convert("k-rho", p, K0, r0)
         ta, tb = api.model_convert("k-rho", p, Kt, rt)

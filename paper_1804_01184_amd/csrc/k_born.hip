@@ -962,8 +962,9 @@ BornSplit born_data_split(int F, int S, int R, int C)
     b.ts = born_ts(S);
     // matrix cores for the data from 9 sources (below, the vector kernel's
     // chunk of 8 wastes less than a 16-wide tile) and for the gradient from
-    // 2 (measured on the config-2 geometry: the vector gradient takes
-    // 18-21 ms at 4-11 sources, the matrix-core one 11 ms)
+    // 2 (measured with 360 receivers, 401^2 cells and 32 frequencies: the
+    // vector gradient takes 18-21 ms at 4-11 sources, the matrix-core one
+    // 11 ms)
     b.ns = S >= 9 ? std::min(4, (S + 15) / 16) : 0;
     b.gns = S >= 2 ? std::min(4, (S + 15) / 16) : 0;
     b.gsgroups = b.gns ? (S + 16 * b.gns - 1) / (16 * b.gns) : 0;

@@ -1,6 +1,6 @@
 """Central-difference check of the autograd gradient at full size.
 
-``python -m paper_1804_01184_amd.fdcheck`` builds config 3 (1001² + 40 PML,
+``python -m paper_1804_01184_amd.fdcheck`` builds the 1001² smooth benchmark (1001² + 40 PML,
 64 shots, 4000 steps, smooth random Vp with Gardner density and 8 Gaussian
 anomalies), takes the gradient of J = ½‖d(m) − d_obs‖² through
 FWIFunction (forward with checkpoints every ⌈√nt⌉ steps, backward with
@@ -24,7 +24,7 @@ from . import api, autograd, workloads as W
 
 # central differences converge as h^2 until FP32 rounding of the traces
 # takes over; the scan reaches below 1e-3, where the truncation error of the
-# smoothest directions is still above 1e-3 on config 3
+# smoothest directions is still above 1e-3 on the 1001² smooth benchmark
 HS = (1e-2, 3e-3, 1e-3, 3e-4, 1e-4)
 
 
@@ -43,13 +43,13 @@ def directions(w, n, seed=1804 + 30):
 def main(argv=None):
     import argparse
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="c3", choices=["c2", "c3"])
+    ap.add_argument("--workload", default="smooth1001", choices=["gauss401", "smooth1001"])
     ap.add_argument("--directions", type=int, default=16)
     ap.add_argument("--param", default="vp-rho")
     a = ap.parse_args(argv)
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
-    w = W.config3() if a.workload == "c3" else W.config2()
+    w = W.smooth1001() if a.workload == "smooth1001" else W.gauss401()
     k = int(np.ceil(np.sqrt(w.nt)))
     plan = api.Plan(api.Grid.of(w), w.src_xz, w.rec_xz, ckpt_every=k)
     f = torch.tensor(w.wavelet(), dtype=torch.float32, device=dev)

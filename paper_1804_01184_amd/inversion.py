@@ -27,9 +27,9 @@ Every array operation runs in the library's kernels (gradient, forward,
 misfit, fwi_descent_direction / fwi_descent_apply / fwi_descent_norms); the
 step-length arithmetic on the handful of scalars runs on the host in FP64.
 
-``python -m paper_1804_01184_amd.inversion`` runs the loop on config 1
-(point velocity-only scatterer, shape known) and config 2 (Gaussian
-velocity-only scatterer, shape unknown) in all five parameterizations and
+``python -m paper_1804_01184_amd.inversion`` runs the loop on the 101² point
+benchmark (velocity-only scatterer, shape known) and the 401² Gaussian
+benchmark (velocity-only anomaly, shape unknown) in all five parameterizations and
 prints one JSON line: misfit per iteration and the loop's throughput.
 """
 from __future__ import annotations
@@ -257,9 +257,9 @@ def main(argv=None):
     import argparse
     from . import workloads as W
     ap = argparse.ArgumentParser()
-    ap.add_argument("--iters-c1", type=int, default=15)
-    ap.add_argument("--iters-c2", type=int, default=4)
-    ap.add_argument("--no-c2", action="store_true")
+    ap.add_argument("--iters-point101", type=int, default=15)
+    ap.add_argument("--iters-gauss401", type=int, default=4)
+    ap.add_argument("--no-gauss401", action="store_true")
     ap.add_argument("--table5", type=int, default=0, metavar="ITERS",
                     help="instead: the seven scatterers of the paper's scatterer table in its "
                          "10-source, 100-receiver ring geometry")
@@ -270,12 +270,12 @@ def main(argv=None):
         print(json.dumps(table5(a.table5, dev=dev)), flush=True)
         return
     rec = {"loop": "steepest descent in the contrasts, parabolic line search"}
-    w1 = W.config1()
+    w1 = W.point101()
     ci, cj = np.argwhere(w1.rho_true * w1.vp_true ** 2 != w1.rho_start * w1.vp_start ** 2)[0]
-    rec["c1_point_vp_only_shape_known"] = _run(w1, a.iters_c1, mask_cells=[(int(ci), int(cj))],
+    rec["point101_vp_only_shape_known"] = _run(w1, a.iters_point101, mask_cells=[(int(ci), int(cj))],
                                                dev=dev)
-    if not a.no_c2:
-        rec["c2_gaussian_vp_only_shape_unknown"] = _run(W.config2(), a.iters_c2, dev=dev)
+    if not a.no_gauss401:
+        rec["gauss401_vp_only_shape_unknown"] = _run(W.gauss401(), a.iters_gauss401, dev=dev)
     print(json.dumps(rec), flush=True)
 
 

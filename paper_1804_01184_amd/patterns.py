@@ -139,9 +139,9 @@ def main(argv=None):
               file=sys.stderr, flush=True)
     out["patterns"] = pats
 
-    # error bowls of scatterer (i) (config 1) with all the data and in the
+    # error bowls of scatterer (i) (101² point benchmark) with all the data and in the
     # two limited-aperture regimes
-    w = W.config1()
+    w = W.point101()
     plan1 = api.Plan(api.Grid.of(w), w.src_xz, w.rec_xz, device=dev)
     f1 = torch.tensor(w.wavelet(), dtype=torch.float32, device=dev)
     Kt = torch.tensor(w.rho_true * w.vp_true ** 2, dtype=torch.float32, device=dev)
@@ -172,7 +172,7 @@ def main(argv=None):
                             else int(th1.size)}
             print(f"{p} {name}: axis ratio {ratio:.2f}, long axis {ang:.1f} deg",
                   file=sys.stderr, flush=True)
-    out["limited_aperture_bowls_c1"] = res
+    out["limited_aperture_bowls_point101"] = res
     print(json.dumps(out), flush=True)
 
 

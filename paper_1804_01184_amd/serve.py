@@ -16,7 +16,7 @@ large request does not hold the memory the others need to run alongside.
 
 Reports per-request latency (completion - arrival), p50/p99, and aggregate
 Gcell-updates/s over the makespan.  ``python -m paper_1804_01184_amd.serve``
-serves a seeded Poisson stream of config-4 requests and prints one JSON
+serves a seeded Poisson stream of mixed-size requests and prints one JSON
 line.
 """
 from __future__ import annotations
@@ -218,8 +218,8 @@ def summary(results, makespan):
 
 
 def make_requests(specs, device=None, param="vp-rho", nrec=360, npml=40):
-    """Requests for serving_requests()-style specs: a config-2-style problem
-    per spec (Gaussian anomaly), with observed data modelled from the true
+    """Requests for serving_requests()-style specs: a problem shaped like the
+    401² Gaussian benchmark per spec (Gaussian anomaly), with observed data modelled from the true
     model on the GPU and kept in pinned host memory."""
     from . import workloads as W
     dev = torch.device(device if device is not None else "cuda")
@@ -244,7 +244,7 @@ def make_requests(specs, device=None, param="vp-rho", nrec=360, npml=40):
 
 
 def main(argv=None):
-    """Serves a seeded Poisson stream of config-4 gradient requests (sides
+    """Serves a seeded Poisson stream of mixed-size gradient requests (sides
     201..1201 + 40 PML, 8-64 shots, 1000-4000 steps) and prints one JSON
     line: latency percentiles, aggregate rate, and the same requests run one
     after another for comparison."""

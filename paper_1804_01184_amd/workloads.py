@@ -117,7 +117,7 @@ def _rings(S, nrec, radius, cx, cz):
     return src, np.ascontiguousarray(np.broadcast_to(rec, (S, nrec, 2)))
 
 
-def config1():
+def point101():
     """Plain method: 101x101 at 5 m + 20 PML, homogeneous 2000/2000, one node
     with +10 % bulk modulus at the centre, one 25 Hz source 150 m above it,
     180 receivers on a 200 m ring, CFL 0.5, 600 steps."""
@@ -131,11 +131,11 @@ def config1():
     cx = cz = 250.0
     src = np.array([[cx, cz - 150.0]])
     rec = ring(180, 200.0, cx, cz)[None]
-    return Workload("c1-point-101", nz, nx, dz, dx, 20, 600, _dt(vmax, dx, dz), vmax, 25.0,
+    return Workload("point-101", nz, nx, dz, dx, 20, 600, _dt(vmax, dx, dz), vmax, 25.0,
                     src, rec, vp_true, rho.copy(), vp, rho)
 
 
-def config2(seed=None):
+def gauss401(seed=None):
     """401x401 at 5 m + 40 PML, Gaussian Vp anomaly (sigma = 0.2 dominant
     wavelength, contrast +-U[0.05, 0.40]), 2000 steps, 40 sources and 360
     receivers on an 800 m ring."""
@@ -151,7 +151,7 @@ def config2(seed=None):
     rho = np.full((nz, nx), 2000.0)
     vmax = float(vp_true.max())
     src, rec = _rings(40, 360, 800.0, cx, cz)
-    return Workload("c2-gauss-401", nz, nx, dz, dx, 40, 2000, _dt(vmax, dx, dz), vmax, fpeak,
+    return Workload("gauss-401", nz, nx, dz, dx, 40, 2000, _dt(vmax, dx, dz), vmax, fpeak,
                     src, rec, vp_true, rho.copy(), np.full((nz, nx), 2000.0), rho,
                     meta={"contrast": c})
 
@@ -175,7 +175,7 @@ def _anomalies(rng, vp, dz, dx, n, xc, zc, radius, sigma, min_sep):
     return out, pos
 
 
-def config3(seed=None):
+def smooth1001(seed=None):
     """1001x1001 at 5 m + 40 PML, smooth random Vp in [1500, 3500], Gardner
     density, 8 Gaussian anomalies, 4000 steps, 64 sources, 360 receivers on a
     2000 m ring."""
@@ -188,11 +188,11 @@ def config3(seed=None):
     vp_true, _ = _anomalies(rng, bg, dz, dx, 8, cx, cz, 1800.0, 0.2 * 2000.0 / fpeak, 200.0)
     vmax = float(vp_true.max())
     src, rec = _rings(64, 360, 2000.0, cx, cz)
-    return Workload("c3-smooth-1001", nz, nx, dz, dx, 40, 4000, _dt(vmax, dx, dz), vmax,
+    return Workload("smooth-1001", nz, nx, dz, dx, 40, 4000, _dt(vmax, dx, dz), vmax,
                     fpeak, src, rec, vp_true, gardner(vp_true), bg, gardner(bg))
 
 
-def config5(seed=None):
+def layered2001(seed=None):
     """2001x2001 at 5 m + 40 PML, seeded layers in [1500, 3500] with Gardner
     density and 16 Gaussian anomalies, 8000 steps, 256 sources and 720
     receivers on a 4000 m ring."""
@@ -210,13 +210,13 @@ def config5(seed=None):
                             float(bg.mean()) / fpeak / 8.0, 300.0)
     vmax = float(vp_true.max())
     src, rec = _rings(256, 720, 4000.0, cx, cz)
-    return Workload("c5-layered-2001", nz, nx, dz, dx, 40, 8000, _dt(vmax, dx, dz), vmax,
+    return Workload("layered-2001", nz, nx, dz, dx, 40, 8000, _dt(vmax, dx, dz), vmax,
                     fpeak, src, rec, vp_true, gardner(vp_true), bg, gardner(bg))
 
 
 def gauss_problem(n, nshots, nrec, nt, npml=20, dx=5.0, fpeak=25.0, contrast=0.2,
                   rho_contrast=0.0, radius_frac=0.8, seed=0, name=None):
-    """A config-2-style problem at any size (for tests and serving requests):
+    """A problem shaped like the 401² Gaussian benchmark, at any size (for tests and serving requests):
     n x n grid, one Gaussian anomaly in Vp (and optionally rho) at the centre,
     sources and receivers on a ring of radius radius_frac * half width."""
     rng = np.random.default_rng(np.random.SeedSequence(seed))
@@ -317,8 +317,8 @@ class BornWorkload:
                     C=self.nz * self.nx)
 
 
-def born_config1(nf=32):
-    """Frequency-domain form of config 1: 101 x 101 cells at 5 m,
+def born_point101(nf=32):
+    """Frequency-domain form of the 101² point benchmark: 101 x 101 cells at 5 m,
     background 2000 m/s and 2000 kg/m^3, +10 % K at the centre cell, one
     source 150 m above it, 180 receivers on a 200 m ring, nf frequencies
     2, 4, ... Hz of a 25 Hz Ricker wavelet."""
@@ -326,20 +326,20 @@ def born_config1(nf=32):
     xa = np.zeros((nz, nx))
     xa[50, 50] = 0.1
     freqs = 2.0 * np.arange(1, nf + 1)
-    return BornWorkload("born-c1-point-101", nz, nx, 5.0, 5.0, 2000.0 * 2000.0 ** 2, 2000.0,
+    return BornWorkload("born-point-101", nz, nx, 5.0, 5.0, 2000.0 * 2000.0 ** 2, 2000.0,
                         freqs, ricker_spectrum(freqs, 25.0), np.array([[250.0, 100.0]]),
                         ring(180, 200.0, 250.0, 250.0), "k-rho", xa, np.zeros((nz, nx)))
 
 
-def born_config2(nf=32, seed=None):
-    """Frequency-domain form of config 2: 401 x 401 cells at 5 m, the same
+def born_gauss401(nf=32, seed=None):
+    """Frequency-domain form of the 401² Gaussian benchmark: 401 x 401 cells at 5 m, the same
     seeded Gaussian Vp contrast at fixed density, 40 sources and 360
     receivers on an 800 m ring, nf frequencies 2, 4, ... Hz of a 25 Hz
     Ricker wavelet."""
-    w = config2(seed)
+    w = gauss401(seed)
     xa = w.vp_true / w.vp_start - 1.0
     freqs = 2.0 * np.arange(1, nf + 1)
-    return BornWorkload("born-c2-gauss-401", w.nz, w.nx, w.dz, w.dx, 2000.0 * 2000.0 ** 2,
+    return BornWorkload("born-gauss-401", w.nz, w.nx, w.dz, w.dx, 2000.0 * 2000.0 ** 2,
                         2000.0, freqs, ricker_spectrum(freqs, 25.0), w.src_xz,
                         np.ascontiguousarray(w.rec_xz[0]), "vp-rho", xa,
                         np.zeros((w.nz, w.nx)))

@@ -19,7 +19,7 @@ def env():
 
 
 def _problem(n=121, shots=5, nt=400, seed=7):
-    """A small config-3-style problem: smooth random background (Gardner
+    """A small problem shaped like the 1001² smooth benchmark: smooth random background (Gardner
     density) with Gaussian anomalies, sources and receivers on a ring."""
     rng = np.random.default_rng(np.random.SeedSequence(seed))
     w = W.gauss_problem(n, shots, 48, nt, npml=15, contrast=0.25, rho_contrast=0.1, seed=seed)

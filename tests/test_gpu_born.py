@@ -9,7 +9,7 @@ FP32-rounded inputs (positions, frequencies, spectrum, contrasts, residual)
 in FP64.  Shapes cover every source-chunk width of the vector kernels and
 every tile count of the matrix-core kernels, ragged receiver tiles and
 groups, cell chunks, pairs and blocks, more than 64 sources, and the
-full frequency-domain config-2 problem on sampled outputs plus the adjoint
+full frequency-domain 401² Gaussian problem on sampled outputs plus the adjoint
 dot product."""
 import math
 
@@ -193,16 +193,16 @@ def test_reduced_hessian_matches_oracle(env, param):
 
 
 @pytest.fixture(scope="module")
-def config2(env):
+def gauss401(env):
     torch, born = env
-    w = W.born_config2()
+    w = W.born_gauss401()
     prob = born.BornProblem.of(w)
     return w, prob
 
 
-def test_full_size_sampled_outputs_and_dot_product(env, config2):
+def test_full_size_sampled_outputs_and_dot_product(env, gauss401):
     torch, born = env
-    w, prob = config2
+    w, prob = gauss401
     sz = w.sizes()
     F, S, R, C = sz["F"], sz["S"], sz["R"], sz["C"]
     xa = torch.tensor(w.xa.ravel(), dtype=torch.float32, device="cuda")

@@ -1,4 +1,4 @@
-"""Error bowls on the GPU against the FP64 oracle (config 1, point
+"""Error bowls on the GPU against the FP64 oracle (101² point benchmark, point
 scatterer (i), a 3 x 3 grid of contrasts around the true ones, all five
 parameterizations).
 
@@ -22,7 +22,7 @@ def env():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_1804_01184_amd import api, bowls
-    w = W.config1()
+    w = W.point101()
     g = O.Grid(w.nz, w.nx, w.dz, w.dx, w.npml, w.nt, w.dt, w.vmax, w.pml_r)
     f = w.wavelet()
     Kt = w.rho_true * w.vp_true ** 2

@@ -69,7 +69,7 @@ class Case:
 
 @pytest.fixture(scope="module")
 def c1():
-    return Case(W.config1())
+    return Case(W.point101())
 
 
 def _small(n=149, shots=6, nrec=40, nt=300, npml=12, seed=3, rho_contrast=0.15):
@@ -92,7 +92,7 @@ def small():
 # ------------------------------------------------------------------ forward
 
 @pytest.mark.parametrize("mode", ["plain", "batched"])
-def test_forward_config1(api, c1, mode):
+def test_forward_point101(api, c1, mode):
     w = c1.w
     p = api.Plan(agrid(api, w), w.src_xz, w.rec_xz, mode=mode)
     tr = p.forward("k-rho", c1.K0, c1.r0, c1.f).cpu().numpy()
@@ -141,7 +141,7 @@ def test_forward_wavelet_per_shot(api, small):
 
 @pytest.mark.parametrize("mode", ["plain", "batched"])
 @pytest.mark.parametrize("param", [0, 1, 2, 3, 4])
-def test_adjoint_config1(api, c1, mode, param):
+def test_adjoint_point101(api, c1, mode, param):
     w = c1.w
     m1, m2 = O.krho_to_model(param, c1.K0, c1.r0)
     e1, e2 = O.chain_rule(param, c1.K0, c1.r0, c1.gK, c1.gr)

@@ -56,7 +56,7 @@ def test_weighted_misfit_definition(env):
 
 def test_limited_aperture_bowl_matches_oracle(env):
     torch, api, bowls, patterns = env
-    w = W.config1()
+    w = W.point101()
     g = O.Grid(w.nz, w.nx, w.dz, w.dx, w.npml, w.nt, w.dt, w.vmax, w.pml_r)
     f = w.wavelet()
     K0 = w.rho_start * w.vp_start ** 2

@@ -27,12 +27,12 @@ def test_candidates_cover_rows_shot_groups_and_lane_widths():
 
 
 def test_workloads_seeded_and_shaped():
-    a, b = W.config2(), W.config2()
+    a, b = W.gauss401(), W.gauss401()
     np.testing.assert_array_equal(a.vp_true, b.vp_true)
     assert a.padded == (481, 481) and a.nshots == 40 and a.nrec == 360 and a.nt == 2000
     assert 0.05 <= abs(a.meta["contrast"]) <= 0.40
     assert abs(a.vmax * a.dt / a.dx - 0.5) < 1e-12
-    c1 = W.config1()
+    c1 = W.point101()
     assert c1.padded == (141, 141) and c1.nt == 600 and c1.nrec == 180
     K = c1.rho_true * c1.vp_true ** 2
     K0 = c1.rho_start * c1.vp_start ** 2

@@ -253,9 +253,9 @@ def test_analytic_green_function_and_refinement():
 
 
 def test_pml_reflection_bound():
-    """Config-1 grid (101^2 at 5 m + 20 cells): traces match a domain so large
+    """The 101² point benchmark grid (101^2 at 5 m + 20 cells): traces match a domain so large
     that nothing returns from its edges, to 1e-2 of the direct arrival."""
-    w = W.config1()
+    w = W.point101()
     rho = w.rho_start
     K = rho * w.vp_start ** 2
     g = O.Grid(w.nz, w.nx, w.dz, w.dx, w.npml, w.nt, w.dt, w.vmax)
