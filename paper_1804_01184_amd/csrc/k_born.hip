@@ -956,6 +956,28 @@ static int born_ts(int S)
     return 8;
 }
 
+// Resident 256-thread blocks per CU of the matrix-core data kernel with NS
+// source tiles (set by its register count), from the runtime's occupancy
+// calculator; 4 if the query fails.
+static int data_mfma_blocks_per_cu(int ns)
+{
+    static int cache[5] = {0, 0, 0, 0, 0};
+    if (ns < 1 || ns > 4)
+        return 4;
+    if (cache[ns] == 0) {
+        int n = 0;
+        hipError_t e = hipErrorInvalidValue;
+        switch (ns) {
+        case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_born_data_mfma<1>, 256, 0); break;
+        case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_born_data_mfma<2>, 256, 0); break;
+        case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_born_data_mfma<3>, 256, 0); break;
+        case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_born_data_mfma<4>, 256, 0); break;
+        }
+        cache[ns] = (e == hipSuccess && n > 0) ? n : 4;
+    }
+    return cache[ns];
+}
+
 BornSplit born_data_split(int F, int S, int R, int C)
 {
     BornSplit b;
@@ -991,10 +1013,12 @@ BornSplit born_data_split(int F, int S, int R, int C)
     const int max_split = std::max(1, (C + step - 1) / step);
     long long want = base > 0 ? (target + base - 1) / base : 1;
     if (b.ns && base > 0) {
-        // whole rounds of resident blocks: 256 CUs x 4 blocks of 4 waves
-        // (4 waves per SIMD); 8 rounds, rounded down so that the last round
-        // is full rather than nearly empty
-        const long long cap = 256LL * 4 * 8, blocks_per_range = base / b.nrg * ((b.nrg + 3) / 4);
+        // whole rounds of resident blocks (256 CUs x the blocks of 4 waves
+        // that fit one CU at this kernel's register count); 8 rounds,
+        // rounded down so that the last round is full rather than nearly
+        // empty
+        const long long cap = 256LL * data_mfma_blocks_per_cu(b.ns) * 8;
+        const long long blocks_per_range = base / b.nrg * ((b.nrg + 3) / 4);
         want = std::max(1LL, cap / std::max(1LL, blocks_per_range));
     }
     b.nsplit = (int)std::max(1LL, std::min<long long>(want, max_split));
@@ -1006,7 +1030,8 @@ BornSplit born_data_split(int F, int S, int R, int C)
     if (per > 0)
         b.nsplit = (C + per - 1) / per;
     // gradient: cell blocks x frequency splits (matrix cores: blocks of 64
-    // cells, about 8 rounds of 4 resident blocks per CU)
+    // cells, about 8192 in all, 10 or more rounds of the 3 blocks that fit
+    // one CU; each block's frequencies are summed in registers)
     b.cblocks = b.gns ? (C + 63) / 64 : (C + kGradBlock - 1) / kGradBlock;
     const long long gtarget = b.gns ? 8192 : 2048;
     const long long gw = b.cblocks > 0 ? (gtarget + b.cblocks - 1) / b.cblocks : 1;
