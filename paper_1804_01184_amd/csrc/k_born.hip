@@ -18,6 +18,7 @@
 #include "fwi2d_internal.h"
 
 #include <algorithm>
+#include <atomic>
 
 namespace fwi {
 
@@ -961,10 +962,10 @@ static int born_ts(int S)
 // calculator; 4 if the query fails.
 static int data_mfma_blocks_per_cu(int ns)
 {
-    static int cache[5] = {0, 0, 0, 0, 0};
+    static std::atomic<int> cache[5] = {0, 0, 0, 0, 0};
     if (ns < 1 || ns > 4)
         return 4;
-    if (cache[ns] == 0) {
+    if (cache[ns].load(std::memory_order_relaxed) == 0) {
         int n = 0;
         hipError_t e = hipErrorInvalidValue;
         switch (ns) {
@@ -973,9 +974,9 @@ static int data_mfma_blocks_per_cu(int ns)
         case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_born_data_mfma<3>, 256, 0); break;
         case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_born_data_mfma<4>, 256, 0); break;
         }
-        cache[ns] = (e == hipSuccess && n > 0) ? n : 4;
+        cache[ns].store((e == hipSuccess && n > 0) ? n : 4, std::memory_order_relaxed);
     }
-    return cache[ns];
+    return cache[ns].load(std::memory_order_relaxed);
 }
 
 BornSplit born_data_split(int F, int S, int R, int C)
