@@ -35,6 +35,7 @@
 #include "fwi2d_oracle.h"
 
 #include <math.h>
+#include <xmmintrin.h>
 #include <stdlib.h>
 #include <string.h>
 #ifdef _OPENMP
@@ -45,9 +46,16 @@
 static const double C1 = 9.0 / 8.0;
 static const double C2 = -1.0 / 24.0;
 
+/* Grid arrays are stored with two ghost cells on every side of the padded
+ * grid: row pitch P = Nx + 4, node (i, j) at index (i + 2) P + (j + 2), for
+ * i in -2..Nz+1 and j in -2..Nx+1.  Ghost cells are zero-initialised and
+ * never written, so they hold the zero field the scheme assumes outside the
+ * padded grid, and the difference operators read them without bounds
+ * checks.  Loops over the grid visit the Nz x Nx nodes only. */
 typedef struct {
     int Nz, Nx;
-    long N;
+    long N;               /* Nz * Nx nodes                                */
+    long P, NG;           /* row pitch Nx + 4; stored cells (Nz + 4) P     */
     double *K, *rho;      /* padded model                        [Nz][Nx] */
     double *bx, *bz;      /* buoyancy at (i, j+1/2) and (i+1/2, j)        */
     double *ax, *btx;     /* PML alpha, beta at integer x nodes   [Nx]    */
@@ -55,6 +63,10 @@ typedef struct {
     double *ahx, *bthx;   /* at half x nodes j+1/2                [Nx]    */
     double *ahz, *bthz;   /* at half z nodes i+1/2                [Nz]    */
 } model_t;
+
+/* Stored index of node (i, j) (ghost cells: i or j in -2..-1 or past the
+ * last node by one or two). */
+static long IX(const model_t *m, int i, int j) { return (long)(i + 2) * m->P + (j + 2); }
 
 typedef struct {
     long idx[4];
@@ -70,6 +82,22 @@ static const long kInnerMinCells = 65536;
 typedef struct {
     double *vx, *vz, *px, *pz;
 } state_t;
+
+/* Subnormal numbers are flushed to zero while the wavefield calls run (on
+ * every OpenMP thread, and on the calling thread until they return, when its
+ * own mode is restored).  Ahead of every wavefront the scheme produces values
+ * that decay below 2.2e-308; they carry no weight at the precision of any
+ * result, and subnormal arithmetic runs about a hundred times slower on
+ * x86-64. */
+static unsigned ftz_enter(void)
+{
+    const unsigned old = _mm_getcsr();
+#pragma omp parallel
+    _mm_setcsr(_mm_getcsr() | 0x8040u);
+    _mm_setcsr(old | 0x8040u);
+    return old;
+}
+static void ftz_leave(unsigned old) { _mm_setcsr(old); }
 
 int ora_padded_nz(const ora_grid *g) { return g->nz + 2 * g->npml; }
 int ora_padded_nx(const ora_grid *g) { return g->nx + 2 * g->npml; }
@@ -197,10 +225,12 @@ static int model_build(const ora_grid *g, const double *K, const double *rho, mo
     m->Nz = Nz;
     m->Nx = Nx;
     m->N = (long)Nz * Nx;
-    m->K = malloc(sizeof(double) * m->N);
-    m->rho = malloc(sizeof(double) * m->N);
-    m->bx = malloc(sizeof(double) * m->N);
-    m->bz = malloc(sizeof(double) * m->N);
+    m->P = Nx + 4;
+    m->NG = (long)(Nz + 4) * m->P;
+    m->K = calloc(m->NG, sizeof(double));
+    m->rho = calloc(m->NG, sizeof(double));
+    m->bx = calloc(m->NG, sizeof(double));
+    m->bz = calloc(m->NG, sizeof(double));
     m->ax = malloc(sizeof(double) * Nx);  m->btx = malloc(sizeof(double) * Nx);
     m->ahx = malloc(sizeof(double) * Nx); m->bthx = malloc(sizeof(double) * Nx);
     m->az = malloc(sizeof(double) * Nz);  m->btz = malloc(sizeof(double) * Nz);
@@ -215,16 +245,16 @@ static int model_build(const ora_grid *g, const double *K, const double *rho, mo
         for (int j = 0; j < Nx; ++j) {
             int pi = clampi(i - g->npml, 0, g->nz - 1);
             int pj = clampi(j - g->npml, 0, g->nx - 1);
-            m->K[(long)i * Nx + j] = K[(long)pi * g->nx + pj];
-            m->rho[(long)i * Nx + j] = rho[(long)pi * g->nx + pj];
+            m->K[IX(m, i, j)] = K[(long)pi * g->nx + pj];
+            m->rho[IX(m, i, j)] = rho[(long)pi * g->nx + pj];
         }
     /* buoyancy between a node and its +x / +z neighbour; beyond the last
      * node the density continues by replication */
     for (int i = 0; i < Nz; ++i)
         for (int j = 0; j < Nx; ++j) {
-            long c = (long)i * Nx + j;
-            double rx = m->rho[(long)i * Nx + (j + 1 < Nx ? j + 1 : j)];
-            double rz = m->rho[(long)(i + 1 < Nz ? i + 1 : i) * Nx + j];
+            long c = IX(m, i, j);
+            double rx = m->rho[IX(m, i, j + 1 < Nx ? j + 1 : j)];
+            double rz = m->rho[IX(m, i + 1 < Nz ? i + 1 : i, j)];
             m->bx[c] = 2.0 / (m->rho[c] + rx);
             m->bz[c] = 2.0 / (m->rho[c] + rz);
         }
@@ -244,12 +274,12 @@ static int bilinear(const ora_grid *g, double x, double z, stencil4 *st)
     double tx = fx - j, tz = fz - i;
     if (i < 0 || j < 0 || i > g->nz - 2 || j > g->nx - 2)
         return -1;
-    int Nx = g->nx + 2 * g->npml;
-    long I = i + g->npml, J = j + g->npml;
-    st->idx[0] = I * Nx + J;           st->w[0] = (1.0 - tx) * (1.0 - tz);
-    st->idx[1] = I * Nx + J + 1;       st->w[1] = tx * (1.0 - tz);
-    st->idx[2] = (I + 1) * Nx + J;     st->w[2] = (1.0 - tx) * tz;
-    st->idx[3] = (I + 1) * Nx + J + 1; st->w[3] = tx * tz;
+    long P = g->nx + 2 * g->npml + 4;   /* stored row pitch (see model_t) */
+    long I = i + g->npml + 2, J = j + g->npml + 2;
+    st->idx[0] = I * P + J;           st->w[0] = (1.0 - tx) * (1.0 - tz);
+    st->idx[1] = I * P + J + 1;       st->w[1] = tx * (1.0 - tz);
+    st->idx[2] = (I + 1) * P + J;     st->w[2] = (1.0 - tx) * tz;
+    st->idx[3] = (I + 1) * P + J + 1; st->w[3] = tx * tz;
     return 0;
 }
 
@@ -264,37 +294,36 @@ static int check_grid(const ora_grid *g)
 }
 
 /* ------------------------------------------------------------------------ */
-/* Difference operators.  Values outside the padded grid are zero.           */
+/* Difference operators.  Values outside the padded grid are zero (they   */
+/* are read from the ghost cells).                                          */
 /* ------------------------------------------------------------------------ */
 
-static double at(const double *f, int Nz, int Nx, int i, int j)
+static double at(const double *f, const model_t *m, int i, int j)
 {
-    if (i < 0 || j < 0 || i >= Nz || j >= Nx)
-        return 0.0;
-    return f[(long)i * Nx + j];
+    return f[IX(m, i, j)];
 }
 
 /* D+ : from nodes to the staggered point after (i, j). */
-static double dxp(const double *f, int Nz, int Nx, int i, int j, double h)
+static double dxp(const double *f, const model_t *m, int i, int j, double h)
 {
-    return (C1 * (at(f, Nz, Nx, i, j + 1) - at(f, Nz, Nx, i, j)) +
-            C2 * (at(f, Nz, Nx, i, j + 2) - at(f, Nz, Nx, i, j - 1))) / h;
+    return (C1 * (at(f, m, i, j + 1) - at(f, m, i, j)) +
+            C2 * (at(f, m, i, j + 2) - at(f, m, i, j - 1))) / h;
 }
-static double dzp(const double *f, int Nz, int Nx, int i, int j, double h)
+static double dzp(const double *f, const model_t *m, int i, int j, double h)
 {
-    return (C1 * (at(f, Nz, Nx, i + 1, j) - at(f, Nz, Nx, i, j)) +
-            C2 * (at(f, Nz, Nx, i + 2, j) - at(f, Nz, Nx, i - 1, j))) / h;
+    return (C1 * (at(f, m, i + 1, j) - at(f, m, i, j)) +
+            C2 * (at(f, m, i + 2, j) - at(f, m, i - 1, j))) / h;
 }
 /* D- : from staggered points to the node (i, j); D- = -(D+)^T. */
-static double dxm(const double *f, int Nz, int Nx, int i, int j, double h)
+static double dxm(const double *f, const model_t *m, int i, int j, double h)
 {
-    return (C1 * (at(f, Nz, Nx, i, j) - at(f, Nz, Nx, i, j - 1)) +
-            C2 * (at(f, Nz, Nx, i, j + 1) - at(f, Nz, Nx, i, j - 2))) / h;
+    return (C1 * (at(f, m, i, j) - at(f, m, i, j - 1)) +
+            C2 * (at(f, m, i, j + 1) - at(f, m, i, j - 2))) / h;
 }
-static double dzm(const double *f, int Nz, int Nx, int i, int j, double h)
+static double dzm(const double *f, const model_t *m, int i, int j, double h)
 {
-    return (C1 * (at(f, Nz, Nx, i, j) - at(f, Nz, Nx, i - 1, j)) +
-            C2 * (at(f, Nz, Nx, i + 1, j) - at(f, Nz, Nx, i - 2, j))) / h;
+    return (C1 * (at(f, m, i, j) - at(f, m, i - 1, j)) +
+            C2 * (at(f, m, i + 1, j) - at(f, m, i - 2, j))) / h;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -310,21 +339,21 @@ static void step_forward(const ora_grid *g, const model_t *m, state_t *u,
 {
     int Nz = m->Nz, Nx = m->Nx;
 #pragma omp parallel for if (inner_parallel)
-    for (long c = 0; c < m->N; ++c)
+    for (long c = 0; c < m->NG; ++c)
         p[c] = u->px[c] + u->pz[c];
 #pragma omp parallel for if (inner_parallel)
     for (int i = 0; i < Nz; ++i)
         for (int j = 0; j < Nx; ++j) {
-            long c = (long)i * Nx + j;
-            u->vx[c] = m->ahx[j] * u->vx[c] - m->bthx[j] * m->bx[c] * dxp(p, Nz, Nx, i, j, g->dx);
-            u->vz[c] = m->ahz[i] * u->vz[c] - m->bthz[i] * m->bz[c] * dzp(p, Nz, Nx, i, j, g->dz);
+            long c = IX(m, i, j);
+            u->vx[c] = m->ahx[j] * u->vx[c] - m->bthx[j] * m->bx[c] * dxp(p, m, i, j, g->dx);
+            u->vz[c] = m->ahz[i] * u->vz[c] - m->bthz[i] * m->bz[c] * dzp(p, m, i, j, g->dz);
         }
 #pragma omp parallel for if (inner_parallel)
     for (int i = 0; i < Nz; ++i)
         for (int j = 0; j < Nx; ++j) {
-            long c = (long)i * Nx + j;
-            u->px[c] = m->ax[j] * u->px[c] - m->btx[j] * m->K[c] * dxm(u->vx, Nz, Nx, i, j, g->dx);
-            u->pz[c] = m->az[i] * u->pz[c] - m->btz[i] * m->K[c] * dzm(u->vz, Nz, Nx, i, j, g->dz);
+            long c = IX(m, i, j);
+            u->px[c] = m->ax[j] * u->px[c] - m->btx[j] * m->K[c] * dxm(u->vx, m, i, j, g->dx);
+            u->pz[c] = m->az[i] * u->pz[c] - m->btz[i] * m->K[c] * dzm(u->vz, m, i, j, g->dz);
         }
     for (int k = 0; k < 4; ++k) {
         long c = src->idx[k];
@@ -393,8 +422,28 @@ static int geometry(const ora_grid *g, const ora_acq *a, stencil4 **src, stencil
 /* Forward modelling.                                                        */
 /* ------------------------------------------------------------------------ */
 
-int ora_forward(const ora_grid *g, const ora_acq *a, const double *K,
-                const double *rho, const double *wavelet, double *traces)
+/* Traces [nrec][nt] of one shot. */
+static void shot_forward(const ora_grid *g, const model_t *m, const stencil4 *src,
+                         const stencil4 *rec, int nrec, const double *f, double *traces)
+{
+    state_t u;
+    double *p = calloc(m->NG, sizeof(double));
+    double *Q = malloc(sizeof(double) * g->nt);
+    if (state_alloc(&u, m->NG) == 0 && p && Q) {
+        cumulative_wavelet(g, f, Q);
+        for (int n = 0; n < g->nt; ++n) {
+            step_forward(g, m, &u, p, src, Q[n]);
+            for (int r = 0; r < nrec; ++r)
+                traces[(size_t)r * g->nt + n] = sample(&rec[r], &u);
+        }
+    }
+    state_free(&u);
+    free(p);
+    free(Q);
+}
+
+static int forward_impl(const ora_grid *g, const ora_acq *a, const double *K,
+                        const double *rho, const double *wavelet, double *traces)
 {
     if (check_grid(g) || a->nshots < 1 || a->nrec < 0)
         return -1;
@@ -404,25 +453,22 @@ int ora_forward(const ora_grid *g, const ora_acq *a, const double *K,
     stencil4 *src = NULL, *rec = NULL;
     int rc = geometry(g, a, &src, &rec);
     if (rc == 0) {
+        /* threads over grid rows (shots one after another) or over shots;
+         * the two loops run the same per-shot code */
         inner_parallel = a->nshots < ora_num_threads() && m.N >= kInnerMinCells;
-#pragma omp parallel for schedule(dynamic, 1) if (!inner_parallel)
-        for (int s = 0; s < a->nshots; ++s) {
-            state_t u;
-            double *p = malloc(sizeof(double) * m.N);
-            double *Q = malloc(sizeof(double) * g->nt);
-            if (state_alloc(&u, m.N) == 0 && p && Q) {
-                cumulative_wavelet(g, wavelet + (a->wavelet_per_shot ? (size_t)s * g->nt : 0), Q);
-                for (int n = 0; n < g->nt; ++n) {
-                    step_forward(g, &m, &u, p, &src[s], Q[n]);
-                    for (int r = 0; r < a->nrec; ++r)
-                        traces[((size_t)s * a->nrec + r) * g->nt + n] =
-                            sample(&rec[(size_t)s * a->nrec + r], &u);
-                }
-            }
-            state_free(&u);
-            free(p);
-            free(Q);
+#define FWD_SHOT(s)                                                                  \
+        shot_forward(g, &m, &src[s], rec + (size_t)(s) * a->nrec, a->nrec,            \
+                     wavelet + (a->wavelet_per_shot ? (size_t)(s) * g->nt : 0),       \
+                     traces + (size_t)(s) * a->nrec * g->nt)
+        if (inner_parallel) {
+            for (int s = 0; s < a->nshots; ++s)
+                FWD_SHOT(s);
+        } else {
+#pragma omp parallel for schedule(dynamic, 1)
+            for (int s = 0; s < a->nshots; ++s)
+                FWD_SHOT(s);
         }
+#undef FWD_SHOT
     }
     free(src);
     free(rec);
@@ -430,9 +476,18 @@ int ora_forward(const ora_grid *g, const ora_acq *a, const double *K,
     return rc;
 }
 
-int ora_forward_states(const ora_grid *g, const ora_acq *a, const double *K,
-                       const double *rho, const double *wavelet, int shot,
-                       int nsteps, const int *steps, double *states)
+int ora_forward(const ora_grid *g, const ora_acq *a, const double *K,
+                const double *rho, const double *wavelet, double *traces)
+{
+    unsigned mode = ftz_enter();
+    int rc = forward_impl(g, a, K, rho, wavelet, traces);
+    ftz_leave(mode);
+    return rc;
+}
+
+static int forward_states_impl(const ora_grid *g, const ora_acq *a, const double *K,
+                               const double *rho, const double *wavelet, int shot,
+                               int nsteps, const int *steps, double *states)
 {
     if (check_grid(g) || shot < 0 || shot >= a->nshots)
         return -1;
@@ -448,9 +503,9 @@ int ora_forward_states(const ora_grid *g, const ora_acq *a, const double *K,
         return -1;
     }
     state_t u;
-    double *p = malloc(sizeof(double) * m.N);
+    double *p = calloc(m.NG, sizeof(double));
     double *Q = malloc(sizeof(double) * g->nt);
-    int rc = (state_alloc(&u, m.N) == 0 && p && Q) ? 0 : -2;
+    int rc = (state_alloc(&u, m.NG) == 0 && p && Q) ? 0 : -2;
     inner_parallel = m.N >= kInnerMinCells;
     if (rc == 0) {
         cumulative_wavelet(g, wavelet + (a->wavelet_per_shot ? (size_t)shot * g->nt : 0), Q);
@@ -458,10 +513,11 @@ int ora_forward_states(const ora_grid *g, const ora_acq *a, const double *K,
         for (int n = 0; n <= g->nt && k < nsteps; ++n) {
             if (n == steps[k]) {
                 double *o = states + (size_t)k * 4 * m.N;
-                memcpy(o, u.vx, sizeof(double) * m.N);
-                memcpy(o + m.N, u.vz, sizeof(double) * m.N);
-                memcpy(o + 2 * m.N, u.px, sizeof(double) * m.N);
-                memcpy(o + 3 * m.N, u.pz, sizeof(double) * m.N);
+                const double *fld[4] = {u.vx, u.vz, u.px, u.pz};
+                for (int q = 0; q < 4; ++q)
+                    for (int i = 0; i < m.Nz; ++i)
+                        memcpy(o + q * m.N + (long)i * m.Nx, fld[q] + IX(&m, i, 0),
+                               sizeof(double) * m.Nx);
                 ++k;
             }
             if (n < g->nt)
@@ -472,6 +528,16 @@ int ora_forward_states(const ora_grid *g, const ora_acq *a, const double *K,
     free(p);
     free(Q);
     model_free(&m);
+    return rc;
+}
+
+int ora_forward_states(const ora_grid *g, const ora_acq *a, const double *K,
+                       const double *rho, const double *wavelet, int shot,
+                       int nsteps, const int *steps, double *states)
+{
+    unsigned mode = ftz_enter();
+    int rc = forward_states_impl(g, a, K, rho, wavelet, shot, nsteps, steps, states);
+    ftz_leave(mode);
     return rc;
 }
 
@@ -522,9 +588,9 @@ static void step_adjoint(const ora_grid *g, const model_t *m, state_t *lam,
 #pragma omp parallel for if (inner_parallel)
     for (int i = 0; i < Nz; ++i)
         for (int j = 0; j < Nx; ++j) {
-            long c = (long)i * Nx + j;
-            double dpx = -m->btx[j] * dxm(un1->vx, Nz, Nx, i, j, g->dx);
-            double dpz = -m->btz[i] * dzm(un1->vz, Nz, Nx, i, j, g->dz);
+            long c = IX(m, i, j);
+            double dpx = -m->btx[j] * dxm(un1->vx, m, i, j, g->dx);
+            double dpz = -m->btz[i] * dzm(un1->vz, m, i, j, g->dz);
             sens->gK[c] += lam->px[c] * dpx + lam->pz[c] * dpz;
         }
     double gq = 0.0;
@@ -539,30 +605,30 @@ static void step_adjoint(const ora_grid *g, const model_t *m, state_t *lam,
 #pragma omp parallel for if (inner_parallel)
     for (int i = 0; i < Nz; ++i)
         for (int j = 0; j < Nx; ++j) {
-            long c = (long)i * Nx + j;
+            long c = IX(m, i, j);
             tmpx[c] = m->btx[j] * m->K[c] * lam->px[c];
             tmpz[c] = m->btz[i] * m->K[c] * lam->pz[c];
         }
 #pragma omp parallel for if (inner_parallel)
     for (int i = 0; i < Nz; ++i)
         for (int j = 0; j < Nx; ++j) {
-            long c = (long)i * Nx + j;
-            lam->vx[c] += dxp(tmpx, Nz, Nx, i, j, g->dx);
-            lam->vz[c] += dzp(tmpz, Nz, Nx, i, j, g->dz);
+            long c = IX(m, i, j);
+            lam->vx[c] += dxp(tmpx, m, i, j, g->dx);
+            lam->vz[c] += dzp(tmpz, m, i, j, g->dz);
             lam->px[c] *= m->ax[j];
             lam->pz[c] *= m->az[i];
         }
 
     /* dvx'/dbx = -bthx Dx+ p^n;  dvz'/dbz = -bthz Dz+ p^n */
 #pragma omp parallel for if (inner_parallel)
-    for (long c = 0; c < m->N; ++c)
+    for (long c = 0; c < m->NG; ++c)
         pn[c] = un->px[c] + un->pz[c];
 #pragma omp parallel for if (inner_parallel)
     for (int i = 0; i < Nz; ++i)
         for (int j = 0; j < Nx; ++j) {
-            long c = (long)i * Nx + j;
-            sens->gbx[c] += lam->vx[c] * (-m->bthx[j] * dxp(pn, Nz, Nx, i, j, g->dx));
-            sens->gbz[c] += lam->vz[c] * (-m->bthz[i] * dzp(pn, Nz, Nx, i, j, g->dz));
+            long c = IX(m, i, j);
+            sens->gbx[c] += lam->vx[c] * (-m->bthx[j] * dxp(pn, m, i, j, g->dx));
+            sens->gbz[c] += lam->vz[c] * (-m->bthz[i] * dzp(pn, m, i, j, g->dz));
         }
 
     /* T1^T: mu_p += Dx-(bthx bx lambda_vx) + Dz-(bthz bz lambda_vz) on both
@@ -570,22 +636,22 @@ static void step_adjoint(const ora_grid *g, const model_t *m, state_t *lam,
 #pragma omp parallel for if (inner_parallel)
     for (int i = 0; i < Nz; ++i)
         for (int j = 0; j < Nx; ++j) {
-            long c = (long)i * Nx + j;
+            long c = IX(m, i, j);
             tmpx[c] = m->bthx[j] * m->bx[c] * lam->vx[c];
             tmpz[c] = m->bthz[i] * m->bz[c] * lam->vz[c];
         }
 #pragma omp parallel for if (inner_parallel)
     for (int i = 0; i < Nz; ++i)
         for (int j = 0; j < Nx; ++j) {
-            long c = (long)i * Nx + j;
-            double t = dxm(tmpx, Nz, Nx, i, j, g->dx) + dzm(tmpz, Nz, Nx, i, j, g->dz);
+            long c = IX(m, i, j);
+            double t = dxm(tmpx, m, i, j, g->dx) + dzm(tmpz, m, i, j, g->dz);
             lam->px[c] += t;
             lam->pz[c] += t;
         }
 #pragma omp parallel for if (inner_parallel)
     for (int i = 0; i < Nz; ++i)
         for (int j = 0; j < Nx; ++j) {
-            long c = (long)i * Nx + j;
+            long c = IX(m, i, j);
             lam->vx[c] *= m->ahx[j];
             lam->vz[c] *= m->ahz[i];
         }
@@ -598,13 +664,13 @@ static int shot_adjoint(const ora_grid *g, const model_t *m, const stencil4 *src
                         const double *adj, int k, sens_t *sens)
 {
     int nt = g->nt;
-    long N = m->N;
+    long N = m->NG;   /* stored cells of a field, ghosts included */
     int nseg = (nt + k - 1) / k;
     int rc = 0;
     double *Q = malloc(sizeof(double) * nt);
-    double *p = malloc(sizeof(double) * N);
-    double *tmpx = malloc(sizeof(double) * N);
-    double *tmpz = malloc(sizeof(double) * N);
+    double *p = calloc(N, sizeof(double));
+    double *tmpx = calloc(N, sizeof(double));
+    double *tmpz = calloc(N, sizeof(double));
     state_t *ck = calloc(nseg, sizeof(state_t));
     state_t *seg = calloc(k + 1, sizeof(state_t));
     state_t lam;
@@ -653,9 +719,9 @@ done:
     return rc;
 }
 
-int ora_adjoint(const ora_grid *g, const ora_acq *a, const double *K,
-                const double *rho, const double *wavelet, const double *adj_src,
-                int ckpt_every, double *gK, double *grho, double *gwav)
+static int adjoint_impl(const ora_grid *g, const ora_acq *a, const double *K,
+                        const double *rho, const double *wavelet, const double *adj_src,
+                        int ckpt_every, double *gK, double *grho, double *gwav)
 {
     if (check_grid(g) || a->nshots < 1 || a->nrec < 0)
         return -1;
@@ -667,7 +733,7 @@ int ora_adjoint(const ora_grid *g, const ora_acq *a, const double *K,
         return -2;
     stencil4 *src = NULL, *rec = NULL;
     int rc = geometry(g, a, &src, &rec);
-    long N = m.N;
+    long N = m.NG;   /* stored cells of a grid array, ghosts included */
     int S = a->nshots, nt = g->nt;
     double *sK = NULL, *sbx = NULL, *sbz = NULL, *sQ = NULL;
     if (rc == 0) {
@@ -680,16 +746,27 @@ int ora_adjoint(const ora_grid *g, const ora_acq *a, const double *K,
     }
     if (rc == 0) {
         int fail = 0;
-        inner_parallel = S < ora_num_threads() && N >= kInnerMinCells;
-#pragma omp parallel for schedule(dynamic, 1) reduction(| : fail) if (!inner_parallel)
-        for (int s = 0; s < S; ++s) {
-            sens_t sens = { sK + (size_t)s * N, sbx + (size_t)s * N, sbz + (size_t)s * N,
-                            sQ + (size_t)s * nt };
-            const double *f = wavelet + (a->wavelet_per_shot ? (size_t)s * nt : 0);
-            const double *adj = adj_src + (size_t)s * a->nrec * nt;
-            fail |= shot_adjoint(g, &m, &src[s], rec + (size_t)s * a->nrec, a->nrec, f,
-                                 adj, k, &sens) != 0;
+        /* threads over grid rows (shots one after another) or over shots;
+         * the two loops run the same per-shot code */
+        inner_parallel = S < ora_num_threads() && m.N >= kInnerMinCells;
+#define ADJ_SHOT(s)                                                                  \
+        do {                                                                         \
+            sens_t sens = { sK + (size_t)(s) * N, sbx + (size_t)(s) * N,              \
+                            sbz + (size_t)(s) * N, sQ + (size_t)(s) * nt };           \
+            const double *f = wavelet + (a->wavelet_per_shot ? (size_t)(s) * nt : 0); \
+            const double *adj = adj_src + (size_t)(s) * a->nrec * nt;                 \
+            fail |= shot_adjoint(g, &m, &src[s], rec + (size_t)(s) * a->nrec, a->nrec, \
+                                 f, adj, k, &sens) != 0;                              \
+        } while (0)
+        if (inner_parallel) {
+            for (int s = 0; s < S; ++s)
+                ADJ_SHOT(s);
+        } else {
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : fail)
+            for (int s = 0; s < S; ++s)
+                ADJ_SHOT(s);
         }
+#undef ADJ_SHOT
         if (fail)
             rc = -2;
     }
@@ -702,18 +779,19 @@ int ora_adjoint(const ora_grid *g, const ora_acq *a, const double *K,
         } else {
             /* sum over shots in ascending order */
             for (int s = 0; s < S; ++s)
-                for (long c = 0; c < N; ++c) {
-                    tK[c] += sK[(size_t)s * N + c];
-                    /* bx = 2/(rho_c + rho_{c+x}): dbx/drho = -bx^2/2 for
-                     * each of the two densities; beyond the last node the
-                     * replicated density is the node's own */
-                    int i = (int)(c / Nx), j = (int)(c % Nx);
-                    double tx = -0.5 * sbx[(size_t)s * N + c] * m.bx[c] * m.bx[c];
-                    double tz = -0.5 * sbz[(size_t)s * N + c] * m.bz[c] * m.bz[c];
-                    tr[c] += tx + tz;
-                    tr[(long)i * Nx + (j + 1 < Nx ? j + 1 : j)] += tx;
-                    tr[(long)(i + 1 < Nz ? i + 1 : i) * Nx + j] += tz;
-                }
+                for (int i = 0; i < Nz; ++i)
+                    for (int j = 0; j < Nx; ++j) {
+                        long c = IX(&m, i, j);
+                        tK[c] += sK[(size_t)s * N + c];
+                        /* bx = 2/(rho_c + rho_{c+x}): dbx/drho = -bx^2/2 for
+                         * each of the two densities; beyond the last node the
+                         * replicated density is the node's own */
+                        double tx = -0.5 * sbx[(size_t)s * N + c] * m.bx[c] * m.bx[c];
+                        double tz = -0.5 * sbz[(size_t)s * N + c] * m.bz[c] * m.bz[c];
+                        tr[c] += tx + tz;
+                        tr[IX(&m, i, j + 1 < Nx ? j + 1 : j)] += tx;
+                        tr[IX(&m, i + 1 < Nz ? i + 1 : i, j)] += tz;
+                    }
             /* fold the PML (edge-replicated) cells back onto the physical model */
             memset(gK, 0, sizeof(double) * (size_t)g->nz * g->nx);
             memset(grho, 0, sizeof(double) * (size_t)g->nz * g->nx);
@@ -721,8 +799,8 @@ int ora_adjoint(const ora_grid *g, const ora_acq *a, const double *K,
                 for (int j = 0; j < Nx; ++j) {
                     int pi = clampi(i - g->npml, 0, g->nz - 1);
                     int pj = clampi(j - g->npml, 0, g->nx - 1);
-                    gK[(long)pi * g->nx + pj] += tK[(long)i * Nx + j];
-                    grho[(long)pi * g->nx + pj] += tr[(long)i * Nx + j];
+                    gK[(long)pi * g->nx + pj] += tK[IX(&m, i, j)];
+                    grho[(long)pi * g->nx + pj] += tr[IX(&m, i, j)];
                 }
             /* wavelet: Q^{n+1/2} = dt sum_{k<=n} f^k */
             if (gwav) {
@@ -745,5 +823,15 @@ int ora_adjoint(const ora_grid *g, const ora_acq *a, const double *K,
     free(src);
     free(rec);
     model_free(&m);
+    return rc;
+}
+
+int ora_adjoint(const ora_grid *g, const ora_acq *a, const double *K,
+                const double *rho, const double *wavelet, const double *adj_src,
+                int ckpt_every, double *gK, double *grho, double *gwav)
+{
+    unsigned mode = ftz_enter();
+    int rc = adjoint_impl(g, a, K, rho, wavelet, adj_src, ckpt_every, gK, grho, gwav);
+    ftz_leave(mode);
     return rc;
 }

@@ -56,3 +56,36 @@ def test_admission_respects_budget(env):
     for r in res:
         live = [x for x in res if x.admitted <= r.admitted < x.done]
         assert sum(x.footprint for x in live) <= budget
+
+
+def test_served_result_matches_oracle(env):
+    """A request served alongside others against the oracle: its misfit and
+    Vp-rho gradient for the same FP32 observed data.  End to end, the FP32
+    trace error enters through the residual, amplified by
+    kappa = max|d| / max|d - d_obs|, so the bound is 1e-4 kappa (as for the
+    library's own end-to-end gradient)."""
+    torch, serve = env
+    import oracle as O
+    from paper_1804_01184_amd import workloads as W
+    from paper_1804_01184_amd.api import Grid
+    w = W.gauss_problem(97, 3, 40, 260, npml=12, contrast=0.25, seed=33, name="oracle-req")
+    f = w.wavelet()
+    g = O.Grid(w.nz, w.nx, w.dz, w.dx, w.npml, w.nt, w.dt, w.vmax, w.pml_r)
+    obs = O.forward_krho(g, w.src_xz, w.rec_xz, w.rho_true * w.vp_true ** 2, w.rho_true,
+                         f).astype(np.float32)
+    J, e1, e2, d = O.gradient(g, O.VP_RHO, w.vp_start, w.rho_start, w.src_xz, w.rec_xz, f,
+                              obs.astype(np.float64))
+    kappa = np.abs(d).max() / np.abs(d - obs).max()
+
+    others = serve.make_requests(_specs(3, seed=5), nrec=32, npml=10)
+    target = serve.Request(99, 0.01, Grid.of(w), w.src_xz, w.rec_xz, "vp-rho", w.vp_start,
+                           w.rho_start, f, torch.from_numpy(obs).pin_memory())
+    res = {r.id: r for r in serve.GradientServer(max_slots=3).run(others + [target])}
+    r = res[99]
+
+    def maxrel(a, b):
+        return float(np.abs(a - b).max() / np.abs(b).max())
+
+    assert abs(r.J - J) <= 1e-4 * kappa * J
+    assert maxrel(r.g1.cpu().numpy(), e1) <= 1e-4 * kappa
+    assert maxrel(r.g2.cpu().numpy(), e2) <= 1e-4 * kappa
