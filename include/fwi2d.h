@@ -174,6 +174,22 @@ fwi_status fwi_forward(fwi_plan *plan, int32_t param, const float *m1, const flo
 fwi_status fwi_misfit(fwi_plan *plan, const float *traces, const float *observed,
                       float *residual, float *J, void *ws, size_t ws_bytes, void *stream);
 
+/* fwi_misfit without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation).  The partial sums of the reduction live in a static
+ * device array of 2048 floats (8 KiB) per GPU, held from the library's
+ * loading until the process ends; the call allocates nothing.  The array is
+ * shared by every call on that GPU and keeps the last call's sums: calls
+ * that overlap on one GPU (unordered streams) race, so order them.  Every
+ * sum is written before it is read, so nothing needs clearing between calls.
+ * Results are bitwise those of fwi_misfit.  FWI_EINVAL if the data would
+ * need more partial sums than the array holds (the reduction uses at most
+ * 2048 whatever the data size, so no plan does); FWI_ESTATE on a device
+ * other than the plan's; FWI_EDEVICE if the array's address on the current
+ * device cannot be found (looked up once per device, on the first call). */
+fwi_status fwi_misfit_noalloc(fwi_plan *plan, const float *traces, const float *observed,
+                              float *residual, float *J, void *stream);
+
 /* The misfit restricted to a subset of the data, as in the limited-aperture
  * regimes of section "Hierarchical Inversion": weights [S][nrec] (device,
  * one per trace, e.g. 0/1 by scattering angle); residual = w (traces -

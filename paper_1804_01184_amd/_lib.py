@@ -22,7 +22,7 @@ FWI_OP_FORWARD, FWI_OP_MISFIT, FWI_OP_GRADIENT = 0, 1, 2
 
 # exported symbols declared in include/fwi2d.h
 SYMBOLS = ["fwi_plan_create", "fwi_plan_destroy", "fwi_plan_get_info", "fwi_workspace_bytes",
-           "fwi_forward", "fwi_misfit", "fwi_misfit_weighted", "fwi_gradient", "fwi_adjoint", "fwi_forward_keep",
+           "fwi_forward", "fwi_misfit", "fwi_misfit_noalloc", "fwi_misfit_weighted", "fwi_gradient", "fwi_adjoint", "fwi_forward_keep",
            "fwi_adjoint_kept", "fwi_model_convert",
            "fwi_chain_rule", "fwi_contrast_scale", "fwi_descent_direction", "fwi_descent_apply",
            "fwi_descent_norms", "fwi_born_green", "fwi_born_workspace_bytes", "fwi_born_data",
@@ -107,6 +107,8 @@ def lib():
     L.fwi_forward.restype = st
     L.fwi_misfit.argtypes = [vp, fp, fp, fp, fp, vp, sz, vp]
     L.fwi_misfit.restype = st
+    L.fwi_misfit_noalloc.argtypes = [vp, fp, fp, fp, fp, vp]
+    L.fwi_misfit_noalloc.restype = st
     L.fwi_misfit_weighted.argtypes = [vp, fp, fp, fp, fp, fp, vp, sz, vp]
     L.fwi_misfit_weighted.restype = st
     L.fwi_gradient.argtypes = [vp, i32, fp, fp, fp, fp, fp, fp, fp, fp, vp, sz, vp]

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -702,6 +703,47 @@ fwi_status run_gradient(fwi_plan *p, int param, const float *m1, const float *m2
 
 }  // namespace
 
+// ------------------------------------------------------- static misfit scratch
+//
+// The partial sums of fwi_misfit_noalloc live in this file-scope device
+// array: one copy per GPU, created with the code object and held until the
+// process ends.  On the host, `scratch` names a stand-in, not device memory,
+// so host code never hands it to a kernel: the first call on a device looks
+// up that device's address once (with the device current) and every call
+// passes the address it found.
+
+constexpr int kScratchFloats = 2048;   // misfit partial sums (8 KiB)
+static __device__ __align__(256) float scratch[kScratchFloats];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float *g_scratch_ptr[kMaxDevices];
+
+// Address of `scratch` on the current device.
+fwi_status scratch_on_current_device(float **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+        return fail(FWI_EDEVICE, "no usable current HIP device (%d)", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return fail(FWI_EDEVICE, "address of the static scratch on device %d: %s", dev,
+                        hipGetErrorString(e));
+        }
+        g_scratch_ptr[dev] = (float *)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return FWI_OK;
+}
+
+}  // namespace
+
 // ------------------------------------------------------------------ C ABI
 
 extern "C" {
@@ -1098,6 +1140,32 @@ fwi_status fwi_misfit(fwi_plan *p, const float *traces, const float *observed, f
                       misfit_blocks(n), J, (hipStream_t)stream);
     }
     return launched("misfit");
+}
+
+fwi_status fwi_misfit_noalloc(fwi_plan *p, const float *traces, const float *observed,
+                              float *residual, float *J, void *stream)
+{
+    if (!p)
+        return fail(FWI_EINVAL, "plan is NULL");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != p->device)
+        return fail(FWI_ESTATE, "current device %d differs from the plan's device %d", dev,
+                    p->device);
+    if (!traces || !observed || !J)
+        return fail(FWI_EINVAL, "NULL array");
+    long long n = (long long)p->S * p->nrec * p->grid.nt;
+    const int nb = misfit_blocks(n);
+    if (nb > kScratchFloats)
+        return fail(FWI_EINVAL, "misfit of %lld samples needs %d partial sums; the static "
+                    "scratch holds %d", n, nb, kScratchFloats);
+    float *part = nullptr;
+    fwi_status st = scratch_on_current_device(&part);
+    if (st != FWI_OK)
+        return st;
+    // every partial sum is written by its block before the final sum reads
+    // it, so nothing left from an earlier call needs clearing
+    launch_misfit(traces, observed, residual, n, part, nb, J, (hipStream_t)stream);
+    return launched("misfit_noalloc");
 }
 
 fwi_status fwi_misfit_weighted(fwi_plan *p, const float *traces, const float *observed,
