@@ -1,13 +1,22 @@
 """Benchmark: adjoint-state FWI gradient throughput on one MI355X.
 
 One step = one complete gradient of the least-squares misfit for every shot
-of the workload (forward sweep keeping the pressure history, misfit, adjoint
-sweep with imaging, finalization), chain-ruled into the K-rho, Vp-rho, Ip-rho
-and Vp-Ip parameterizations.  The library keeps the whole history when it
-fits in half the HBM (97 GB for the 401² Gaussian benchmark), else sqrt(nt) checkpoints with
-segment recompute; the checkpointed form is timed beside it.  value = padded cells x time steps x shots /
-seconds per step (Gcell-updates/s; each cell-step counted once although the
-forward, recompute and adjoint sweeps all touch it).
+of the workload (forward sweep keeping checkpoints, misfit, per segment a
+recompute storing the pressure and the adjoint sweep with imaging,
+finalization), chain-ruled into the K-rho, Vp-rho, Ip-rho and Vp-Ip
+parameterizations.  The default workload is smooth-1001: 1001^2 at 5 m + 40
+PML, 64 shots, 4000 steps, checkpoints every 64 steps (its live state is far
+beyond the 256 MB Infinity Cache, so the sweeps stream from HBM).  The
+library keeps the whole pressure history instead when it fits in half the
+HBM (gauss-401: 97 GB), and then the checkpointed form is timed beside it.
+value = padded cells x time steps x shots / seconds per step
+(Gcell-updates/s; each cell-step counted once although the forward,
+recompute and adjoint sweeps all touch it).
+
+Beside the timed steps: the plain path (one shot per launch) on the same
+workload, a served stream of gradient requests of mixed sizes (p50 / p99
+latency and aggregate rate), and the FP64 oracle on a sample of the
+workload on the host cores.
 
 Prints one JSON line.  Inputs are synthetic (workloads.py), generated and
 resident in HBM before the timed region.  The timed steps run without
@@ -36,7 +45,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="gauss401", choices=["gauss401", "smooth1001", "layered2001"])
+    ap.add_argument("--workload", default="smooth1001",
+                    choices=["gauss401", "smooth1001", "layered2001"])
     ap.add_argument("--shots", type=int, default=0,
                     help="evenly spaced subset of the shots (default: all; layered2001: 32, one GPU's "
                          "share of 256 shots over 8)")
@@ -49,7 +59,16 @@ def parse():
                          "one (the tuner also runs unless a decomposition is given)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=0, help="time steps of the CPU sample")
+    ap.add_argument("--cpu-steps", type=int, default=0,
+                    help="time steps of the CPU sample (default: all of the workload's)")
+    ap.add_argument("--cpu-shots", type=int, default=1, help="shots of the CPU sample")
+    ap.add_argument("--cpu-single-steps", type=int, default=64,
+                    help="time steps of the single-thread CPU sample (0: none)")
+    ap.add_argument("--serve-requests", type=int, default=40,
+                    help="requests of the served Poisson stream (0: no serving leg)")
+    ap.add_argument("--serve-load", type=float, default=0.8,
+                    help="offered load of the served stream, as a fraction of the gradient "
+                         "rate measured in the timed steps")
     ap.add_argument("--time-steps", type=int, default=0,
                     help="run the workload for this many time steps instead of its own "
                          "(short runs under hardware-counter profiling; per-launch work is "
@@ -77,30 +96,36 @@ def workload(name, shots=0):
     return w
 
 
-def algorithmic_bytes(plan_info, S):
-    """Bytes one launch of each batched kernel must move at least (FP32),
-    with the model and the gradient touched once per launch:
-    forward step: read and write vx, vz, p for every cell and shot (24 B),
-    the pz split in the absorbing layer (8 B per layer cell), the model K,
-    bx, bz once (12 B per cell);
-    adjoint step: read and write the adjoint vx, vz, p (24 B) and its split
-    (8 B), read p^n and p^{n+1} (8 B) and their splits (8 B), the model once
-    and one read-modify-write of the three gradient arrays (12 + 24 B per
-    cell);
-    two forward steps in one launch: read vx, vz, p and its split once
-    (12 B + 4 B per layer cell), write p^{n+1} for the history and vx, vz,
-    p^{n+2} (16 B) with both splits (8 B), the model once.
-    Re-reads the kernels make beyond this (halo rows, the model and the
-    partial gradient once per shot group) show in the measured traffic."""
+def algorithmic_bytes(plan_info, S, k):
+    """Algorithmic HBM bytes per cell-step of each sweep (FP32 streaming,
+    the model and the gradient read once per pass over the S shots):
+      forward    24 + 8 fp + 8/S + 12/k   read and write vx, vz, p; the
+                                          absorbing-layer split (fp = layer
+                                          fraction); K and the buoyancies;
+                                          checkpoint writes every k steps
+      recompute  forward + 4              the pressure stored for the adjoint
+      adjoint    24 + 8 fp + 8/S + 4 + 16/S   adjoint state read and write,
+                                          its split, the model, the stored
+                                          pressure read once (carried over
+                                          from the previous reverse step),
+                                          gK and the buoyancy gradient pair
+                                          read and written once
+    and, per kernel class, the cell-steps one launch advances (a two-step
+    forward launch advances two).  The forward kernels in a gradient store
+    the pressure, so both are charged the recompute figure.  The kernels'
+    own minimum for one launch (a one-step adjoint must read both pressure
+    levels and their splits, and in this design reads the model and
+    read-modify-writes the gradient once per shot group) is larger; the
+    counter traffic shows what they move."""
     N = plan_info["Nz"] * plan_info["Nx"]
     fp = plan_info["pml_cells"] / N
-    fwd = N * S * (24 + 8 * fp) + N * 12
-    adj = N * S * (32 + 16 * fp) + N * (12 + 24)
-    pair = N * S * (28 + 12 * fp) + N * 12
-    out = {"fwd_step": fwd, "adj_step": adj, "fwd_pair": pair, "pml_fraction": fp}
-    for k in ("fwd_step", "adj_step", "fwd_pair"):
-        out["per_cell_" + k] = out[k] / (N * S)
-    return out
+    fwd = 24 + 8 * fp + 8 / S + 12 / k
+    rec = fwd + 4
+    adj = 24 + 8 * fp + 8 / S + 4 + 16 / S
+    per_cell = {"fwd_step": rec, "fwd_pair": rec, "adj_step": adj, "adj_pair": adj}
+    cells = {"fwd_step": N * S, "fwd_pair": 2 * N * S, "adj_step": N * S, "adj_pair": 2 * N * S}
+    return {"pml_fraction": fp, "per_cell": per_cell, "cell_steps": cells,
+            "gradient_per_cell": rec + rec + adj - 4 - 12 / k}
 
 
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1804_01184_amd", "csrc", "k_fused.hip")
@@ -138,25 +163,98 @@ def copy_calibration():
     print(json.dumps({"copy_calibration": {"bytes_read": 4 * n, "bytes_written": 4 * n}}))
 
 
-def cpu_baseline(w, steps):
+def host_cpu():
+    """Model name and logical CPU count of the host (from /proc/cpuinfo)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count(),
+            "usable_cpus": len(os.sched_getaffinity(0))}
+
+
+def cpu_baseline(w, shots, steps, single_steps):
     """The FP64 oracle on a bounded sample of the same workload: the full
-    grid, one shot per host thread (at most all shots), `steps` time steps;
-    observed data zero (same cost as any other)."""
+    grid, `shots` evenly spaced shots, `steps` time steps (checkpoints every
+    ceil(sqrt(steps)), as the GPU plan), the gradient in Vp-rho; all host
+    threads (over grid rows when there are fewer shots than threads), then
+    one thread on a shorter run.  Observed data zero (same cost as any)."""
+    import math
     import oracle as O
+
+    def run(nt):
+        idx = np.linspace(0, w.nshots - 1, shots).round().astype(int)
+        sub = w.subset(shots=idx, nt=nt)
+        g = O.Grid(sub.nz, sub.nx, sub.dz, sub.dx, sub.npml, sub.nt, sub.dt, sub.vmax,
+                   sub.pml_r)
+        f = sub.wavelet()
+        obs = np.zeros((shots, sub.nrec, sub.nt))
+        k = int(math.ceil(math.sqrt(nt)))
+        t = time.perf_counter()
+        O.gradient(g, O.VP_RHO, sub.vp_start, sub.rho_start, sub.src_xz, sub.rec_xz, f, obs, k)
+        dt = time.perf_counter() - t
+        Nz, Nx = sub.padded
+        return Nz * Nx * nt * shots / dt / 1e9, dt
+
     nth = O.num_threads()
-    S = min(w.nshots, nth)
-    sub = w.subset(shots=np.linspace(0, w.nshots - 1, S).round().astype(int), nt=steps)
-    g = O.Grid(sub.nz, sub.nx, sub.dz, sub.dx, sub.npml, sub.nt, sub.dt, sub.vmax, sub.pml_r)
-    f = sub.wavelet()
-    obs = np.zeros((S, sub.nrec, sub.nt))
+    print(f"bench: CPU oracle, {shots} shot(s) x {steps} steps on {nth} threads",
+          file=sys.stderr, flush=True)
+    rate, dt = run(steps)
+    out = {"value": round(rate, 5), "unit": "Gcell-updates/s", "cores": nth, "kind": "oracle",
+           "seconds": round(dt, 2), "host": host_cpu(),
+           "sample": f"{shots} shot(s) x {steps} of {w.nt} time steps of the full "
+                     f"{w.padded[0]}x{w.padded[1]} padded grid: a complete gradient of those "
+                     f"shots in Vp-rho (FP64, checkpoints every "
+                     f"{int(np.ceil(np.sqrt(steps)))} steps, OpenMP over "
+                     f"{'rows' if shots < nth else 'shots'})"}
+    if single_steps:
+        O.set_num_threads(1)
+        try:
+            r1, d1 = run(single_steps)
+        finally:
+            O.set_num_threads(nth)
+        out["single_thread"] = {"value": round(r1, 5), "seconds": round(d1, 2),
+                                "sample": f"{shots} shot(s) x {single_steps} time steps, "
+                                          f"one thread"}
+    return out
+
+
+def serve_leg(dev, rate_gcells, n, load):
+    """A seeded Poisson stream of `n` gradient requests of mixed sizes (the
+    serving workload: sides 201..1201 + 40 PML, 8-64 shots, 1000-4000 steps,
+    Gaussian-anomaly models) served by continuous batching on 4 streams.
+    Arrivals are scaled so the offered load is `load` of the batched
+    gradient rate measured in the timed steps.  Returns p50 / p99 latency
+    (arrival to completion) and the aggregate rate over the makespan."""
+    import torch
+    from paper_1804_01184_amd import serve, workloads as W
+    specs = W.serving_requests(n, rate_hz=1.0)
     t = time.perf_counter()
-    O.gradient(g, O.VP_RHO, sub.vp_start, sub.rho_start, sub.src_xz, sub.rec_xz, f, obs)
-    dt = time.perf_counter() - t
-    Nz, Nx = sub.padded
-    return {"value": Nz * Nx * sub.nt * S / dt / 1e9, "unit": "Gcell-updates/s", "cores": nth,
-            "kind": "oracle", "seconds": dt,
-            "sample": f"{S} shots x {steps} steps of the full {Nz}x{Nx} padded grid "
-                      f"(gradient in Vp-rho, FP64, OpenMP)"}
+    reqs = serve.make_requests(specs, device=dev)
+    torch.cuda.synchronize()
+    prep = time.perf_counter() - t
+    cells = np.array([q.cell_steps for q in reqs], dtype=np.float64)
+    mean_service = float(cells.mean()) / (rate_gcells * 1e9)
+    gap = float(np.mean(np.diff([0.0] + [s["arrival"] for s in specs])))
+    scale = mean_service / load / gap
+    for q, sp in zip(reqs, specs):
+        q.arrival = sp["arrival"] * scale
+    print(f"bench: serving {n} requests (Poisson, mean gap {mean_service / load:.2f} s)",
+          file=sys.stderr, flush=True)
+    srv = serve.GradientServer(max_slots=4, device=dev)
+    res = srv.run(reqs)
+    summ = serve.summary(res, srv.makespan)
+    return {"requests": n, "slots": 4, "offered_load": load,
+            "p50_ms": round(summ["p50_ms"], 1), "p99_ms": round(summ["p99_ms"], 1),
+            "mean_ms": round(summ["mean_ms"], 1),
+            "aggregate_gcells": round(summ["aggregate_gcells"], 3),
+            "makespan_s": round(srv.makespan, 2), "prepare_s": round(prep, 1),
+            "cell_steps": int(cells.sum())}
 
 
 def born_cpu_baseline(w, xk, xr, flops):
@@ -319,13 +417,15 @@ def main():
     value = cells / (ms * 1e-3) / 1e9
 
     S, G = w.nshots, info["shot_groups"]
-    ab = algorithmic_bytes(info, S)
+    ab = algorithmic_bytes(info, S, info["ckpt_every"])
     roof = None
     if not args.no_kernel_timing:
-        dom = max(("fwd_step", "adj_step", "fwd_pair"), key=lambda k: per_class[k][1])
+        sweeps = [k for k in ab["per_cell"] if per_class.get(k, (0, 0.0))[0]]
+        dom = max(sweeps, key=lambda k: per_class[k][1])
         n_launch, dom_ms = per_class[dom]
         avg_s = dom_ms / n_launch * 1e-3
-        achieved = ab[dom] / avg_s / 1e9
+        per_launch = ab["per_cell"][dom] * ab["cell_steps"][dom]
+        achieved = per_launch / avg_s / 1e9
         pre = "two_step_" if dom == "fwd_pair" else ""
         kdec = {"band_rows": info[pre + "band_rows"],
                 "shots_per_group": info[pre + "shots_per_group"],
@@ -334,9 +434,14 @@ def main():
                 "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(achieved / PEAK_HBM_GBS, 4),
                 "traffic": measured_traffic(dom, kdec),
+                "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated)",
                 "avg_launch_us": round(avg_s * 1e6, 2), "launches": n_launch,
-                "bytes_per_launch": int(ab[dom]),
-                "bytes_per_cell_step": round(ab["per_cell_" + dom], 2)}
+                "cell_steps_per_launch": ab["cell_steps"][dom],
+                "bytes_per_cell_step": round(ab["per_cell"][dom], 3),
+                "bytes_per_launch": int(per_launch),
+                "gradient_bytes_per_cell_step": round(ab["gradient_per_cell"], 2),
+                "gradient_roof_gcells": round(PEAK_HBM_GBS / ab["gradient_per_cell"], 1),
+                "pml_fraction": round(ab["pml_fraction"], 4)}
     classes = {k: {"launches": v[0], "ms": round(v[1], 3)} for k, v in per_class.items()
                if v[0]}
 
@@ -359,8 +464,9 @@ def main():
 
     plain = None
     if not args.no_plain:
+        print("bench: plain path (one shot per launch)", file=sys.stderr, flush=True)
         pp = api.Plan(grid, w.src_xz, w.rec_xz, mode="plain")
-        pp.gradient("k-rho", K0, r0, f, obs)          # warm
+        pp.workspace(2)             # allocated outside the timed call
         torch.cuda.synchronize()
         t = time.perf_counter()
         Jp, gKp, grp = pp.gradient("k-rho", K0, r0, f, obs)
@@ -372,12 +478,16 @@ def main():
                  "grad_K_maxrel_vs_batched": rel}
         del pp
 
+    served = None
+    if args.serve_requests > 0:
+        del plan
+        torch.cuda.empty_cache()
+        served = serve_leg(dev, value, args.serve_requests, args.serve_load)
+
     cpu = None
     if not args.no_cpu:
-        nt_s = args.cpu_steps or max(50, min(w.nt, int(3.0e8 / (info["Nz"] * info["Nx"]))))
-        cpu = cpu_baseline(w, nt_s)
-        cpu["value"] = round(cpu["value"], 5)
-        cpu["seconds"] = round(cpu["seconds"], 2)
+        cpu = cpu_baseline(w, min(args.cpu_shots, w.nshots), args.cpu_steps or w.nt,
+                           args.cpu_single_steps)
 
     rec = {
         "metric": METRIC, "value": round(value, 3), "unit": "Gcell-updates/s", "n_gpus": 1,
@@ -397,12 +507,14 @@ def main():
                    "decomposition": "autotuned" if tuned else "given" if any(
                        v for k, v in decomp.items() if k != "two_step") else "default",
                    "ckpt_every": info["ckpt_every"], "segments": info["segments"]},
-        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
-                       "p99": round(float(np.percentile(lat, 99)), 3)},
+        "step_latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
+                            "p99": round(float(np.percentile(lat, 99)), 3),
+                            "over": f"{args.steps} back-to-back gradient calls"},
         "roofline": roof,
         "kernels": classes,
         "checkpointed": ckpt,
         "plain": plain,
+        "serve": served,
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)

@@ -64,6 +64,8 @@ def lib():
         L.ora_padded_nz.argtypes = [ctypes.POINTER(_Grid)]
         L.ora_padded_nx.argtypes = [ctypes.POINTER(_Grid)]
         L.ora_num_threads.argtypes = []
+        L.ora_set_num_threads.argtypes = [ctypes.c_int]
+        L.ora_set_num_threads.restype = None
         _lib = L
     return _lib
 
@@ -224,3 +226,8 @@ def gradient(grid, param, m1, m2, src_xz, rec_xz, wavelet, observed, ckpt_every=
 
 def num_threads():
     return lib().ora_num_threads()
+
+
+def set_num_threads(n):
+    """Threads for the oracle calls this thread makes next."""
+    lib().ora_set_num_threads(int(n))

@@ -111,6 +111,16 @@ int ora_num_threads(void)
 #endif
 }
 
+void ora_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0)
+        omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* Parameter definitions and Table 1 parameterizations.                      */
 /* ------------------------------------------------------------------------ */

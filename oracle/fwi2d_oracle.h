@@ -84,8 +84,10 @@ int ora_adjoint(const ora_grid *g, const ora_acq *a, const double *K,
 int ora_padded_nz(const ora_grid *g);
 int ora_padded_nx(const ora_grid *g);
 
-/* Number of OpenMP threads the oracle runs on. */
+/* Number of OpenMP threads the oracle runs on, and a way to change it for
+ * the calls the calling thread makes next (n >= 1). */
 int ora_num_threads(void);
+void ora_set_num_threads(int n);
 
 #ifdef __cplusplus
 }
