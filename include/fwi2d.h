@@ -125,6 +125,15 @@ typedef struct {
     int32_t two_step_band_rows;       /* decomposition of the two-step     */
     int32_t two_step_shots_per_group; /* kernel, 0: defaults; supported    */
     int32_t two_step_lane_cols;       /* (shots, cols): (1|2, 1|2), (1, 4) */
+    int32_t adj_two_step; /* batched adjoint sweeps advance two time steps per
+                             launch (the intermediate adjoint state stays on
+                             chip; same results bit for bit): 0 default (on
+                             where supported), 1 off, 2 on.  The two-step
+                             adjoint uses the shots per group of the one-step
+                             kernels; supported (shots, cols): (1|2|4, 1),
+                             (1|2, 2)                                        */
+    int32_t adj_two_step_band_rows;   /* its band rows (4..4096), 0: default */
+    int32_t adj_two_step_lane_cols;   /* its columns per lane, 0: default    */
 } fwi_exec;
 
 typedef struct {
@@ -135,6 +144,8 @@ typedef struct {
     int32_t shot_groups;      /* ceil(nshots / shots_per_group)               */
     int32_t two_step;         /* 1: forward sweeps use the two-step kernel    */
     int32_t two_step_band_rows, two_step_shots_per_group, two_step_lane_cols;
+    int32_t adj_two_step;     /* 1: adjoint sweeps use the two-step kernel    */
+    int32_t adj_two_step_band_rows, adj_two_step_lane_cols;
     int32_t mode;
     int32_t device;           /* HIP device the plan lives on                 */
     int64_t pml_cells;        /* cells of the absorbing layer                 */
@@ -383,7 +394,8 @@ typedef enum {
     FWI_KC_INJECT = 7,     /* adjoint-source injection                         */
     FWI_KC_OTHER = 8,      /* preparation, copies, misfit, finalization        */
     FWI_KC_FWD_PAIR = 9,   /* batched two-step forward (all shots, 2 steps)    */
-    FWI_KC_COUNT = 10
+    FWI_KC_ADJ_PAIR = 10,  /* batched two-step adjoint with imaging (2 steps)  */
+    FWI_KC_COUNT = 11
 } fwi_kernel_class;
 
 typedef struct {

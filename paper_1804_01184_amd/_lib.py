@@ -31,7 +31,7 @@ SYMBOLS = ["fwi_plan_create", "fwi_plan_destroy", "fwi_plan_get_info", "fwi_work
            "fwi_sync", "fwi_status_str", "fwi_last_error"]
 
 KERNEL_CLASSES = ["fwd_step", "adj_step", "plain_vel", "plain_pres", "plain_adj_a",
-                  "plain_adj_b", "sample", "inject", "other", "fwd_pair"]
+                  "plain_adj_b", "sample", "inject", "other", "fwd_pair", "adj_pair"]
 
 
 class FwiGrid(ctypes.Structure):
@@ -53,7 +53,10 @@ class FwiExec(ctypes.Structure):
                 ("lane_cols", ctypes.c_int32), ("two_step", ctypes.c_int32),
                 ("two_step_band_rows", ctypes.c_int32),
                 ("two_step_shots_per_group", ctypes.c_int32),
-                ("two_step_lane_cols", ctypes.c_int32)]
+                ("two_step_lane_cols", ctypes.c_int32),
+                ("adj_two_step", ctypes.c_int32),
+                ("adj_two_step_band_rows", ctypes.c_int32),
+                ("adj_two_step_lane_cols", ctypes.c_int32)]
 
 
 class FwiPlanInfo(ctypes.Structure):
@@ -64,13 +67,16 @@ class FwiPlanInfo(ctypes.Structure):
                 ("two_step_band_rows", ctypes.c_int32),
                 ("two_step_shots_per_group", ctypes.c_int32),
                 ("two_step_lane_cols", ctypes.c_int32),
+                ("adj_two_step", ctypes.c_int32),
+                ("adj_two_step_band_rows", ctypes.c_int32),
+                ("adj_two_step_lane_cols", ctypes.c_int32),
                 ("mode", ctypes.c_int32),
                 ("device", ctypes.c_int32), ("pml_cells", ctypes.c_int64),
                 ("cfl", ctypes.c_double)]
 
 
 class FwiTiming(ctypes.Structure):
-    _fields_ = [("launches", ctypes.c_int64 * 10), ("ms", ctypes.c_double * 10)]
+    _fields_ = [("launches", ctypes.c_int64 * 11), ("ms", ctypes.c_double * 11)]
 
 
 class FwiError(RuntimeError):

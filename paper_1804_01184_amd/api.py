@@ -67,12 +67,15 @@ class Plan:
     launch, separate velocity/pressure launches).  band_rows,
     shots_per_group and lane_cols set the batched decomposition (0:
     defaults); two_step (0 default on, 1 off, 2 on) and the two_step_*
-    fields the two-step forward kernel.
+    fields the two-step forward kernel; adj_two_step (0 default on, 1 off,
+    2 on) and the adj_two_step_* fields the two-step adjoint kernel, which
+    shares shots_per_group.
     """
 
     def __init__(self, grid: Grid, src_xz, rec_xz, wavelet_per_shot=False, mode="batched",
                  ckpt_every=0, band_rows=0, shots_per_group=0, lane_cols=0, two_step=0,
                  two_step_band_rows=0, two_step_shots_per_group=0, two_step_lane_cols=0,
+                 adj_two_step=0, adj_two_step_band_rows=0, adj_two_step_lane_cols=0,
                  device=None):
         self.grid = grid
         self.device = (torch.device("cuda", torch.cuda.current_device()) if device is None
@@ -92,7 +95,8 @@ class Plan:
         m = {"batched": L.FWI_EXEC_BATCHED, "plain": L.FWI_EXEC_PLAIN}[mode]
         ex = L.FwiExec(m, int(ckpt_every), int(band_rows), int(shots_per_group), int(lane_cols),
                        int(two_step), int(two_step_band_rows), int(two_step_shots_per_group),
-                       int(two_step_lane_cols))
+                       int(two_step_lane_cols), int(adj_two_step), int(adj_two_step_band_rows),
+                       int(adj_two_step_lane_cols))
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             L.check(L.lib().fwi_plan_create(ctypes.byref(g), ctypes.byref(a), ctypes.byref(ex),

@@ -1,15 +1,18 @@
 """Decomposition autotuner for the batched kernels.
 
-The adjoint step kernel and the two-step forward kernel have decompositions
-of their own (band rows swept per wave, shots advanced together per wave,
-grid columns per lane), so they are tuned separately: on a short run of the
-real grid and shot count, with the whole pressure history kept, each
-adjoint candidate is timed by its adjoint launches and each two-step
-candidate by its forward launches, using the library's per-launch HIP event
-timing.  The one-step forward kernel (a leftover odd step) shares the
-adjoint decomposition.  Results are cached in a JSON file keyed by the shape
-and the GPU; the package ships the results measured on MI355X for the
-benchmark shapes (tuned_gfx950.json), consulted when the cache has none.
+The one-step adjoint kernel, the two-step adjoint kernel and the two-step
+forward kernel have decompositions of their own (band rows swept per wave,
+shots advanced together per wave, grid columns per lane), so they are tuned
+separately on a short run of the real grid and shot count, with the whole
+pressure history kept: each candidate is timed by its own launches, using
+the library's per-launch HIP event timing.  The two-step adjoint shares the
+shot groups (and so their partial gradients) with the one-step adjoint,
+which then runs only for a leftover odd step of a segment; it is chosen
+when its time per step beats the one-step kernel's.  The one-step forward
+kernel (a leftover odd forward step) shares the one-step adjoint
+decomposition.  Results are cached in a JSON file keyed by the shape and the
+GPU; the package ships the results measured on MI355X for the benchmark
+shapes (tuned_gfx950.json), consulted when the cache has none.
 """
 from __future__ import annotations
 
@@ -27,10 +30,12 @@ from .api import Grid, Plan
 # much as the height), then coarser steps
 ROWS = (8, 9, 10, 11, 12, 13, 14, 15, 16, 20, 24, 32, 48, 64, 96, 128)
 ROWS2 = (12, 14, 16, 18, 20, 24, 28, 32, 48, 64, 96)
+ROWSA = (12, 16, 20, 24, 32, 48, 64, 96, 128)
 # supported (shots per group, columns per lane) pairs of the one-step
 # kernels and of the two-step forward kernel
 PAIRS = ((1, 1), (2, 1), (4, 1), (8, 1), (1, 2), (2, 2), (4, 2), (1, 4), (2, 4))
 PAIRS2 = ((1, 1), (2, 1), (1, 2), (2, 2), (1, 4))
+PAIRSA = ((1, 1), (2, 1), (4, 1), (1, 2), (2, 2))
 
 
 def strip_cols(cols, steps=1):
@@ -49,7 +54,7 @@ def cache_path():
 
 
 def _key(Nz, Nx, S, npml, arch):
-    return f"{arch}:{Nz}x{Nx}:S{S}:pml{npml}:v4"
+    return f"{arch}:{Nz}x{Nx}:S{S}:pml{npml}:v5"
 
 
 def _arch():
@@ -85,6 +90,11 @@ def candidates2(Nz, Nx, S):
     """The same for the two-step forward kernel (halo of 6 rows and
     columns)."""
     return _triples(Nz, Nx, S, PAIRS2, ROWS2, 2)
+
+
+def candidates_adj2(Nz, Nx, S):
+    """The same for the two-step adjoint kernel."""
+    return _triples(Nz, Nx, S, PAIRSA, ROWSA, 2)
 
 
 def load_cache():
@@ -150,21 +160,42 @@ def tune(grid: Grid, src_xz, rec_xz, force=False, verbose=False, device=None):
         if key in shipped:
             return dict(shipped[key]["best"])
     t0 = time.perf_counter()
-    res1, res2 = [], []
+    res1, resa, res2 = [], [], []
     for H, spg, cols in candidates(Nz, Nx, S):
         t = measure(grid, src_xz, rec_xz, device=device, band_rows=H, shots_per_group=spg,
-                    lane_cols=cols, two_step=1)
+                    lane_cols=cols, two_step=1, adj_two_step=1)
         res1.append({"band_rows": H, "shots_per_group": spg, "lane_cols": cols,
                      "adj_ms": t.get("adj_step", 0.0), "fwd_ms": t.get("fwd_step", 0.0)})
         if verbose:
             print(f"  adjoint band_rows={H:4d} spg={spg} cols={cols}: "
                   f"{res1[-1]['adj_ms'] * 1e3:8.1f} us", flush=True)
-    # with the two-step kernel the one-step forward runs only for a leftover
-    # odd step: the adjoint time decides
+    for H, spg, cols in candidates_adj2(Nz, Nx, S):
+        t = measure(grid, src_xz, rec_xz, device=device, shots_per_group=spg, two_step=1,
+                    adj_two_step=2, adj_two_step_band_rows=H, adj_two_step_lane_cols=cols)
+        resa.append({"adj_two_step_band_rows": H, "shots_per_group": spg,
+                     "adj_two_step_lane_cols": cols, "pair_ms": t.get("adj_pair", 0.0)})
+        if verbose:
+            print(f"  two-step adjoint band_rows={H:4d} spg={spg} cols={cols}: "
+                  f"{resa[-1]['pair_ms'] * 1e3:8.1f} us per 2 steps", flush=True)
     best1 = min(res1, key=lambda r: r["adj_ms"])
+    best = {k: best1[k] for k in ("band_rows", "shots_per_group", "lane_cols")}
+    best["adj_two_step"] = 1
+    if resa:
+        besta = min(resa, key=lambda r: r["pair_ms"])
+        if besta["pair_ms"] < 2.0 * best1["adj_ms"]:
+            # the one-step kernels take the pair's shot groups
+            same = [r for r in res1 if r["shots_per_group"] == besta["shots_per_group"]]
+            one = min(same, key=lambda r: r["adj_ms"]) if same else None
+            best = {"band_rows": one["band_rows"] if one else 0,
+                    "shots_per_group": besta["shots_per_group"],
+                    "lane_cols": one["lane_cols"] if one else 1,
+                    "adj_two_step": 2,
+                    "adj_two_step_band_rows": besta["adj_two_step_band_rows"],
+                    "adj_two_step_lane_cols": besta["adj_two_step_lane_cols"]}
+    # with the two-step kernels the one-step kernels run only for a leftover
+    # odd step: the two-step times decide
     for H, spg, cols in candidates2(Nz, Nx, S):
-        t = measure(grid, src_xz, rec_xz, device=device, band_rows=best1["band_rows"],
-                    shots_per_group=best1["shots_per_group"], lane_cols=best1["lane_cols"],
+        t = measure(grid, src_xz, rec_xz, device=device, **best,
                     two_step=2, two_step_band_rows=H, two_step_shots_per_group=spg,
                     two_step_lane_cols=cols)
         if "fwd_pair" not in t:
@@ -174,10 +205,12 @@ def tune(grid: Grid, src_xz, rec_xz, force=False, verbose=False, device=None):
         if verbose:
             print(f"  two-step band_rows={H:4d} spg={spg} cols={cols}: "
                   f"{t['fwd_pair'] * 1e3:8.1f} us per 2 steps", flush=True)
-    best = {k: best1[k] for k in ("band_rows", "shots_per_group", "lane_cols")}
+    one_fwd = [r["fwd_ms"] for r in res1 if r["band_rows"] == best["band_rows"] and
+               r["shots_per_group"] == best["shots_per_group"] and
+               r["lane_cols"] == best["lane_cols"]]
     if res2:
         best2 = min(res2, key=lambda r: r["pair_ms"])
-        if best2["pair_ms"] < 2.0 * best1["fwd_ms"]:
+        if not one_fwd or best2["pair_ms"] < 2.0 * one_fwd[0]:
             best.update({k: best2[k] for k in ("two_step_band_rows", "two_step_shots_per_group",
                                                "two_step_lane_cols")})
             best["two_step"] = 2
@@ -186,7 +219,7 @@ def tune(grid: Grid, src_xz, rec_xz, force=False, verbose=False, device=None):
     else:
         best["two_step"] = 1
     cache = load_cache()
-    cache[key] = {"best": best, "adjoint": res1, "two_step": res2,
+    cache[key] = {"best": best, "adjoint": res1, "adj_two_step": resa, "two_step": res2,
                   "seconds": time.perf_counter() - t0}
     save_cache(cache)
     return dict(best)
@@ -198,4 +231,4 @@ def tuned_plan(grid: Grid, src_xz, rec_xz, **kw):
     return Plan(grid, src_xz, rec_xz, **{**best, **kw})
 
 
-__all__ = ["tune", "tuned_plan", "candidates", "candidates2", "measure"]
+__all__ = ["tune", "tuned_plan", "candidates", "candidates2", "candidates_adj2", "measure"]

@@ -54,6 +54,8 @@ struct fwi_plan {
     Sweep sweep;   // batched decomposition (band rows, shots per group)
     bool two_step = false;   // forward sweeps use the two-step kernel
     Sweep sweep2;            // its decomposition
+    bool adj2 = false;       // adjoint sweeps use the two-step kernel
+    Sweep sweep_a2;          // its decomposition (shots per group of `sweep`)
     int device;
     Geo geo;
     long long SS, ST;  // per-shot floats of a state record / a store record
@@ -68,6 +70,9 @@ struct fwi_plan {
     int *inj_shot = nullptr, *inj_cptr = nullptr, *inj_crec = nullptr;
     float *inj_cw = nullptr;
     int inj_nodes = 0;
+    unsigned *inj_win = nullptr;   // two-step adjoint: [Spad][Nz + 2 kZPad][strips] packed node ranges
+    float *zpad = nullptr;         // z damping tables with kZPad zero rows on each side
+    int *inj_col = nullptr;        // grid column of each injection node
     std::vector<int> shot_node_ptr;  // [S+1] node range of each shot
     SweepTables *sweep_tabs = nullptr;   // device copy of the source tables
     std::vector<int2> h_src_ij;
@@ -154,6 +159,7 @@ struct Layout {
     size_t work[2], lam[2];
     size_t ckpt, store, gpart, fold, traces, resid, partials;
     size_t mid;   // p^{n+1} of a two-step launch outside the stored history
+    size_t injacc;   // R^T r^{n-1} per injection node (two-step adjoint)
     size_t total;
 };
 
@@ -201,6 +207,8 @@ Layout layout(const fwi_plan *p, int op)
         L.traces = take(ntr);
         L.resid = take(ntr);
         L.partials = take(misfit_blocks(ntr));
+        if (p->adj2)
+            L.injacc = take((size_t)std::max(p->inj_nodes, 1));
     }
     L.total = off;
     return L;
@@ -408,6 +416,38 @@ void step_adj(const Ctx &c, int s0, int nb, const State &in, const State &out, F
     }
 }
 
+// Two adjoint steps n, n-1 for shots [s0, s0+nb) (batched only): injects
+// R^T r^n into `in` and keeps R^T r^{n-1} per node for the launch, which
+// adds it between its two steps; writes the adjoint state of step n-1 into
+// `out` and accumulates both steps' sensitivities into gpart.  pm, pn, pn1:
+// pressure records (p, then its split) at levels n-1, n, n+1.
+void step_adj2(const Ctx &c, int s0, int nb, const State &in, const State &out, Fld pm, Fld pn,
+               Fld pn1, const float *resid, float *gpart, int n)
+{
+    const fwi_plan *p = c.pl;
+    const Geo &g = p->geo;
+    float *acc = c.f(c.L.injacc);
+    {
+        Timed tm(c.pl, c.st, FWI_KC_INJECT);
+        launch_inject_pair(g, inj_of(c, s0, real_shots(p, s0, nb)), resid, p->nrec, p->grid.nt,
+                           n, in.p, s0, acc, c.st);
+    }
+    AdjStep2 a;
+    a.lin = recd(in.vx, 3 * g.N + g.Npml);
+    a.lout = recd(out.vx, 3 * g.N + g.Npml);
+    a.pm1 = recd(pm, g.N + g.Npml);
+    a.lvl = (unsigned)((const char *)pn.p - (const char *)pm.p);
+    (void)pn1;   // the level after pn, lvl bytes further (checked at plan creation)
+    a.gpart = gpart;
+    a.zpad = p->zpad;
+    a.injwin = p->inj_win;
+    a.injcol = p->inj_col;
+    a.injacc = acc;
+    a.n = n;
+    Timed tm(c.pl, c.st, FWI_KC_ADJ_PAIR, true);
+    launch_fused_adj2(g, p->pml, c.m.K, p->S, p->sweep_a2, a, c.st, tm.b, tm.e);
+}
+
 void zero_state(const Ctx &c, float *base, int nb)
 {
     Timed tm(c.pl, c.st, FWI_KC_OTHER);
@@ -553,10 +593,19 @@ void sweep_backward(const Ctx &c, int s0, int nb, const float *resid, float *gpa
                 cw = nw;
             }
         }
-        for (int n = n1 - 1; n >= n0; --n) {
-            auto a = slot(n - n0), b = slot(n + 1 - n0);
-            step_adj(c, s0, nb, lam[li], lam[li ^ 1], a.first, a.second, b.first, b.second, resid,
-                     gpart, n);
+        // adjoint steps n1-1 .. n0, in pairs where the two-step kernel is on
+        for (int n = n1 - 1; n >= n0;) {
+            if (p->adj2 && n - 1 >= n0) {
+                auto am = slot(n - 1 - n0), a = slot(n - n0), b = slot(n + 1 - n0);
+                step_adj2(c, s0, nb, lam[li], lam[li ^ 1], am.first, a.first, b.first, resid,
+                          gpart, n);
+                n -= 2;
+            } else {
+                auto a = slot(n - n0), b = slot(n + 1 - n0);
+                step_adj(c, s0, nb, lam[li], lam[li ^ 1], a.first, a.second, b.first, b.second,
+                         resid, gpart, n);
+                n -= 1;
+            }
             li ^= 1;
         }
     }
@@ -788,7 +837,7 @@ fwi_status fwi_plan_create(const fwi_grid *grid, const fwi_acq *acq, const fwi_e
         return fail(FWI_EUNSTABLE, "vmax dt sqrt(1/dx^2+1/dz^2)(9/8+1/24) = %.4f > 1", sn);
     if (acq->nshots < 1 || acq->nrec < 1 || !acq->src_xz || !acq->rec_xz)
         return fail(FWI_EINVAL, "need at least one shot and one receiver with positions");
-    fwi_exec ex{FWI_EXEC_BATCHED, 0, 0, 0, 0, 0, 0, 0, 0};
+    fwi_exec ex{FWI_EXEC_BATCHED, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (exec)
         ex = *exec;
     if (ex.mode != FWI_EXEC_BATCHED && ex.mode != FWI_EXEC_PLAIN)
@@ -816,6 +865,15 @@ fwi_status fwi_plan_create(const fwi_grid *grid, const fwi_acq *acq, const fwi_e
             return fail(FWI_EINVAL, "two-step kernel: shots_per_group %d with lane_cols %d not "
                         "supported", s2, c2);
     }
+    if (ex.adj_two_step < 0 || ex.adj_two_step > 2)
+        return fail(FWI_EINVAL, "adj_two_step %d out of range (0, 1, 2)", ex.adj_two_step);
+    if (ex.adj_two_step_band_rows != 0 &&
+        (ex.adj_two_step_band_rows < 4 || ex.adj_two_step_band_rows > 4096))
+        return fail(FWI_EINVAL, "adj_two_step_band_rows %d out of range (4..4096)",
+                    ex.adj_two_step_band_rows);
+    if (ex.adj_two_step_lane_cols < 0 || ex.adj_two_step_lane_cols > 2)
+        return fail(FWI_EINVAL, "adj_two_step_lane_cols %d not supported (1, 2)",
+                    ex.adj_two_step_lane_cols);
 
     fwi_plan *p = new fwi_plan();
     p->grid = G;
@@ -876,6 +934,33 @@ fwi_status fwi_plan_create(const fwi_grid *grid, const fwi_acq *acq, const fwi_e
         p->sweep2 = sweep_of(g, p->Spad, H2, spg2, cols2, 2);
         p->two_step = p->mode != FWI_EXEC_PLAIN && ex.two_step != 1 && p->Spad % spg2 == 0 &&
                       (long long)spg2 * p->SS * 4 < lim;
+        // two-step adjoint over the same shot groups (it shares their
+        // partial gradients with the one-step kernel): default one column
+        // per lane, bands giving about 4096 waves, 16 to 128 rows
+        const int ca = ex.adj_two_step_lane_cols ? ex.adj_two_step_lane_cols : 1;
+        const bool a2ok = p->mode != FWI_EXEC_PLAIN && adj2_supported(spg, ca);
+        if (ex.adj_two_step == 2 && !a2ok) {
+            delete p;
+            return fail(FWI_EINVAL, "two-step adjoint: shots_per_group %d with lane_cols %d not "
+                        "supported (or plain mode)", spg, ca);
+        }
+        // its three pressure levels of a group (consecutive store levels,
+        // Spad ST floats apart) are addressed through one buffer resource
+        const bool a2fits = (2LL * p->Spad + spg) * p->ST * 4 < lim;
+        if (ex.adj_two_step == 2 && a2ok && !a2fits) {
+            delete p;
+            return fail(FWI_EINVAL, "two-step adjoint: three pressure levels of %d shots exceed "
+                        "2 GiB", p->Spad);
+        }
+        p->adj2 = ex.adj_two_step != 1 && a2ok && a2fits;
+        int Ha = ex.adj_two_step_band_rows;
+        if (Ha == 0) {
+            Sweep one = sweep_of(g, p->Spad, (int)Nz, spg, ca, 2);
+            long long per_band = (long long)one.nstrips * one.ngroups;
+            long long bands = std::max<long long>(1, (4096 + per_band - 1) / per_band);
+            Ha = (int)std::min<long long>(128, std::max<long long>(16, (Nz + bands - 1) / bands));
+        }
+        p->sweep_a2 = sweep_of(g, p->Spad, Ha, spg, ca, 2);
         if (p->mode != FWI_EXEC_PLAIN &&
             ((long long)spg * p->SS * 4 >= lim || 3 * g.N * 4 >= lim)) {
             delete p;
@@ -982,6 +1067,52 @@ fwi_status fwi_plan_create(const fwi_grid *grid, const fwi_acq *acq, const fwi_e
     }
     inj_cptr.push_back((int)inj_crec.size());
     p->inj_nodes = (int)inj_node.size();
+    // two-step adjoint: for every shot, row and strip, the range of that
+    // shot's injection nodes in the row whose columns fall in the strip's
+    // window (its output columns and halo), packed (first << 9 | count)
+    std::vector<unsigned> inj_win;
+    std::vector<int> inj_col(inj_node.size());
+    for (size_t k = 0; k < inj_node.size(); ++k)
+        inj_col[k] = (int)(inj_node[k] % g.Nx);
+    if (p->adj2) {
+        const Sweep &sa = p->sweep_a2;
+        const int W = strip_cols(sa.cols, 2);
+        const int halo = (6 + sa.cols - 1) / sa.cols * sa.cols;
+        inj_win.assign((size_t)p->Spad * (g.Nz + 2 * kZPad) * sa.nstrips, 0u);
+        bool fits = inj_node.size() < (1u << 23);
+        for (int s = 0; s < S && fits; ++s) {
+            int k = p->shot_node_ptr[s];
+            const int kend = p->shot_node_ptr[s + 1];
+            while (k < kend) {
+                const long long row = inj_node[k] / g.Nx;
+                int ke = k;
+                while (ke < kend && inj_node[ke] / g.Nx == row)
+                    ++ke;
+                for (int st = 0; st < sa.nstrips; ++st) {
+                    const int lo = st * W - halo, hi = lo + 64 * sa.cols;
+                    int a0 = k;
+                    while (a0 < ke && inj_col[a0] < lo)
+                        ++a0;
+                    int a1 = a0;
+                    while (a1 < ke && inj_col[a1] < hi)
+                        ++a1;
+                    if (a1 > a0) {
+                        if (a1 - a0 > 511) {
+                            fits = false;
+                            break;
+                        }
+                        inj_win[((size_t)s * (g.Nz + 2 * kZPad) + kZPad + row) * sa.nstrips + st] =
+                            ((unsigned)a0 << 9) | (unsigned)(a1 - a0);
+                    }
+                }
+                k = ke;
+            }
+        }
+        if (!fits) {   // more nodes than the packing holds: one-step adjoint
+            p->adj2 = false;
+            inj_win.clear();
+        }
+    }
 
     if (hipGetDevice(&p->device) != hipSuccess) {
         delete p;
@@ -1003,6 +1134,9 @@ fwi_status fwi_plan_create(const fwi_grid *grid, const fwi_acq *acq, const fwi_e
     size_t o_ir = take(sizeof(int) * inj_crec.size());
     size_t o_iw = take(sizeof(float) * inj_cw.size());
     size_t o_st = take(sizeof(SweepTables));
+    size_t o_win = take(sizeof(unsigned) * inj_win.size());
+    size_t o_zpad = take(sizeof(float) * 4 * (g.Nz + 2 * kZPad));
+    size_t o_col = take(sizeof(int) * inj_col.size());
     if (hipMalloc(&p->dev, off) != hipSuccess) {
         (void)hipGetLastError();
         delete p;
@@ -1020,6 +1154,9 @@ fwi_status fwi_plan_create(const fwi_grid *grid, const fwi_acq *acq, const fwi_e
     p->inj_crec = (int *)(d + o_ir);
     p->inj_cw = (float *)(d + o_iw);
     p->sweep_tabs = (SweepTables *)(d + o_st);
+    p->inj_win = (unsigned *)(d + o_win);
+    p->zpad = (float *)(d + o_zpad);
+    p->inj_col = (int *)(d + o_col);
     SweepTables st_host;
     st_host.src_ij = p->src_ij;
     st_host.src_w = p->src_w;
@@ -1043,8 +1180,12 @@ fwi_status fwi_plan_create(const fwi_grid *grid, const fwi_acq *acq, const fwi_e
     up(p->inj_crec, inj_crec.data(), sizeof(int) * inj_crec.size());
     up(p->inj_cw, inj_cw.data(), sizeof(float) * inj_cw.size());
     up(p->sweep_tabs, &st_host, sizeof(SweepTables));
+    up(p->inj_win, inj_win.data(), sizeof(unsigned) * inj_win.size());
+    up(p->inj_col, inj_col.data(), sizeof(int) * inj_col.size());
     if (ok)
         launch_pml_tables(g, G.vmax, G.npml > 0 ? G.pml_r : 0.5, G.dx, G.dz, G.dt, p->pml, ps);
+    if (ok)
+        launch_ztab_pad(g, p->pml, p->zpad, ps);
     if (ok && (hipGetLastError() != hipSuccess || hipStreamSynchronize(ps) != hipSuccess))
         ok = false;
     if (ps)
@@ -1086,6 +1227,9 @@ fwi_status fwi_plan_get_info(const fwi_plan *p, fwi_plan_info *info)
     info->two_step_band_rows = p->sweep2.H;
     info->two_step_shots_per_group = p->sweep2.spg;
     info->two_step_lane_cols = p->sweep2.cols;
+    info->adj_two_step = p->adj2 ? 1 : 0;
+    info->adj_two_step_band_rows = p->sweep_a2.H;
+    info->adj_two_step_lane_cols = p->sweep_a2.cols;
     info->shot_groups = groups_of(p);
     info->mode = p->mode;
     info->device = p->device;

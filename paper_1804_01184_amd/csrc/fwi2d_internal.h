@@ -91,6 +91,11 @@ struct Inj {
 
 // ---------------------------------------------------------------- common
 void launch_fill(float *p, long long n, float v, hipStream_t st);
+// The four z damping tables (alpha, beta at nodes, alpha_h, beta_h at half
+// nodes; 4 Nx floats into `tabs`) copied to zpad with kZPad zero rows on
+// each side: table q, row r at zpad[q (Nz + 2 kZPad) + kZPad + r].
+constexpr int kZPad = 8;
+void launch_ztab_pad(const Geo &g, const float *tabs, float *zpad, hipStream_t st);
 void launch_pml_tables(const Geo &g, double vmax, double pml_r, double dx, double dz,
                        double dt, float *tabs, hipStream_t st);
 void launch_prep_model(const Geo &g, int param, const float *m1, const float *m2,
@@ -108,6 +113,10 @@ void launch_sample_hist(const Geo &g, const float *hist, long long slot_stride, 
 // shot0: shot index of lp.shot(0) (the table holds global shot indices).
 void launch_inject(const Geo &g, const Inj &inj, const float *resid, int nrec, int nt, int n,
                    Fld lp, int shot0, hipStream_t st);
+// Injection before a two-step adjoint launch (steps n, n-1): R^T r^n into
+// lp as launch_inject, and R^T r^{n-1} of node k of the table into next[k].
+void launch_inject_pair(const Geo &g, const Inj &inj, const float *resid, int nrec, int nt,
+                        int n, Fld lp, int shot0, float *next, hipStream_t st);
 // wt (may be null): one weight per trace of nt samples.
 void launch_misfit(const float *d, const float *dobs, float *resid, long long n,
                    float *partials, int nblocks, float *J, hipStream_t st,
@@ -165,6 +174,7 @@ struct Sweep {
 };
 bool fused_supported(int spg, int cols);
 bool fused2_supported(int spg, int cols);
+bool adj2_supported(int spg, int cols);
 // Output columns of one strip of the one-step (steps = 1) or two-step
 // (steps = 2) forward kernels; the two-step kernels need twice the halo.
 int strip_cols(int cols, int steps = 1);
@@ -206,6 +216,23 @@ struct AdjStep {
     float *gpart;       // [groups][3][N]: gK, gbx, gbz
     int n;
 };
+// Two adjoint steps n, n-1 (in order): pm1 holds p^{n-1}, p^n and p^{n+1}
+// follow lvl and 2 lvl bytes after it (consecutive levels of the pressure
+// store).  The adjoint source of step n-1 is added between the steps at the
+// receiver nodes: injwin[(s Nz + i) nstrips + strip] packs
+// (first << 9 | count) of the nodes of shot s in row i within the strip's
+// window (halo included; 0: none), injcol the grid column of each node,
+// injacc R^T r^{n-1} at each node.
+struct AdjStep2 {
+    Recd lin, lout, pm1;
+    unsigned lvl;
+    const float *zpad;     // z damping tables padded by kZPad zero rows (ztab_pad)
+    float *gpart;
+    const unsigned *injwin;
+    const int *injcol;
+    const float *injacc;
+    int n;
+};
 
 // tabs: the 8 damping tables (x: alpha, beta, alpha_h, beta_h; then z) in
 // one block; model: K, bx, bz as one block of 3N floats.  e0 / e1 (may be
@@ -216,6 +243,11 @@ void launch_fused_fwd(const Geo &g, const float *tabs, const float *model,
 void launch_fused_adj(const Geo &g, const float *tabs, const float *model,
                       const SweepTables *tab_dev, int S, const Sweep &sw, const AdjStep &a,
                       hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+// sw: a decomposition made with steps = 2 and the shots per group of the
+// one-step adjoint (the two share the partial gradients of each group).
+void launch_fused_adj2(const Geo &g, const float *tabs, const float *model, int S,
+                       const Sweep &sw, const AdjStep2 &a, hipStream_t st,
+                       hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // sw: a decomposition made with steps = 2.
 void launch_fused_fwd2(const Geo &g, const float *tabs, const float *model,
                        const SweepTables *tab_dev, int S, const Sweep &sw, const FwdStep2 &a,

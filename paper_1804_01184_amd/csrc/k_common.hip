@@ -59,6 +59,16 @@ __global__ void k_pml_tables(int Nz, int Nx, int nz, int nx, int npml, double vm
     tabs[k] = (float)v;
 }
 
+__global__ void k_ztab_pad(int Nz, int Nx, const float *tabs, float *zpad)
+{
+    const int n = Nz + 2 * kZPad;
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= 4 * n)
+        return;
+    const int q = k / n, r = k % n - kZPad;
+    zpad[k] = (unsigned)r < (unsigned)Nz ? tabs[4 * Nx + q * Nz + r] : 0.0f;
+}
+
 // (m1, m2) of a parameterization -> (K, rho); parameter definitions
 // Ip = rho Vp, K = rho Vp^2.
 __device__ inline void to_krho(int param, float a, float b, float &K, float &rho)
@@ -232,6 +242,16 @@ __global__ void __launch_bounds__(256) k_sample_hist(Geo g, const float *hist, l
 // lambda_p[s][node] += sum over receivers touching the node (ascending
 // receiver order) of weight * residual[s][r][n].  Receivers lie outside the
 // absorbing layer, where both split components share the main array.
+// R^T r^n at node k: its receivers' contributions in ascending receiver order.
+__device__ inline float inj_sum(const Inj &inj, const float *resid, int nrec, int nt, int n,
+                                int k, int s)
+{
+    float acc = 0.0f;
+    for (int c = inj.cptr[k]; c < inj.cptr[k + 1]; ++c)
+        acc += inj.cw[c] * resid[((long long)s * nrec + inj.crec[c]) * nt + n];
+    return acc;
+}
+
 __global__ void k_inject(Inj inj, const float *resid, int nrec, int nt, int n, Fld lp,
                          int shot0)
 {
@@ -239,10 +259,21 @@ __global__ void k_inject(Inj inj, const float *resid, int nrec, int nt, int n, F
     if (k >= inj.nnodes)
         return;
     int s = inj.shot[k];
-    float acc = 0.0f;
-    for (int c = inj.cptr[k]; c < inj.cptr[k + 1]; ++c)
-        acc += inj.cw[c] * resid[((long long)s * nrec + inj.crec[c]) * nt + n];
-    lp.shot(s - shot0)[inj.node[k]] += acc;
+    lp.shot(s - shot0)[inj.node[k]] += inj_sum(inj, resid, nrec, nt, n, k, s);
+}
+
+// Before a two-step adjoint launch (steps n and n-1): R^T r^n added to the
+// adjoint pressure as k_inject does, and R^T r^{n-1} per node kept in `next`
+// for the launch to add between its two steps.
+__global__ void k_inject_pair(Inj inj, const float *resid, int nrec, int nt, int n, Fld lp,
+                              int shot0, float *next)
+{
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= inj.nnodes)
+        return;
+    int s = inj.shot[k];
+    lp.shot(s - shot0)[inj.node[k]] += inj_sum(inj, resid, nrec, nt, n, k, s);
+    next[k] = inj_sum(inj, resid, nrec, nt, n - 1, k, s);
 }
 
 __device__ inline float wave_sum(float v)
@@ -500,6 +531,13 @@ void launch_pml_tables(const Geo &g, double vmax, double pml_r, double dx, doubl
                        g.nz, g.nx, g.npml, vmax, pml_r, dx, dz, dt, tabs);
 }
 
+void launch_ztab_pad(const Geo &g, const float *tabs, float *zpad, hipStream_t st)
+{
+    const int total = 4 * (g.Nz + 2 * kZPad);
+    hipLaunchKernelGGL(k_ztab_pad, dim3(blocks_for(total)), dim3(kBlock), 0, st, g.Nz, g.Nx,
+                       tabs, zpad);
+}
+
 void launch_prep_model(const Geo &g, int param, const float *m1, const float *m2,
                        float *Kphys, float *rhophys, float *Kpad, float *bx, float *bz,
                        hipStream_t st)
@@ -543,6 +581,16 @@ void launch_inject(const Geo &, const Inj &inj, const float *resid, int nrec, in
         return;
     hipLaunchKernelGGL(k_inject, dim3(blocks_for(inj.nnodes)), dim3(kBlock), 0, st, inj, resid,
                        nrec, nt, n, lp, shot0);
+}
+
+void launch_inject_pair(const Geo &g, const Inj &inj, const float *resid, int nrec, int nt,
+                        int n, Fld lp, int shot0, float *next, hipStream_t st)
+{
+    (void)g;
+    if (inj.nnodes <= 0)
+        return;
+    hipLaunchKernelGGL(k_inject_pair, dim3(blocks_for(inj.nnodes)), dim3(kBlock), 0, st, inj,
+                       resid, nrec, nt, n, lp, shot0, next);
 }
 
 int misfit_blocks(long long n)

@@ -872,6 +872,67 @@ __global__ void __launch_bounds__(NTHR)
 // earlier step).  Outside the layer the split forms reduce to the unsplit
 // ones (alpha = 1, pz = 0).
 
+// One shot's part of an adjoint step at output row i (the update above).
+// Ring slots S0 .. S3 of MU, MZ, PN hold rows i .. i+3 of mu_px, mu_pz and
+// p^n, bK rows i .. i+3 of beta_z K, and WZ rows i-2 .. i+1 of
+// beta_h bz lvz_mid (slot S3 receives row i+1 here).  Adds the shot's
+// bulk-modulus numerator (at row i) and buoyancy sensitivities (gbx at row
+// i, gbz at row i+1) to numK, accX, accZ, and returns the new adjoint state
+// of row i (lvz of row i+1).  Both adjoint kernels call it, so one step
+// rounds the same way in either.
+template <int C>
+struct AdjOut {
+    float opx[C], opz[C], ovx[C], ovz[C];   // mu_px, mu_pz, lvx at row i; lvz at row i+1
+};
+
+template <int C, int S0, int S1, int S2, int S3>
+__device__ inline void adj_shot(const Geo &g, const XTab<C> &xt, const WaveGeo<C> &w, bool rn,
+                                float ahz1, float bhz1, float az, const float (&bK)[4][C],
+                                const float (&K0)[C], const float (&MU)[4][C],
+                                const float (&MZ)[4][C], const float (&PN)[4][C],
+                                float (&WZ)[4][C], const float (&lvz1)[C], const float (&lvx)[C],
+                                const float (&bx)[C], const float (&bz1)[C], const float (&p1)[C],
+                                const float (&z0)[C], const float (&z1)[C], float (&numK)[C],
+                                float (&accX)[C], float (&accZ)[C], AdjOut<C> &o)
+{
+    float lvzm[C], qx[C], dqx[C], dpx[C], lvxm[C], wx[C], dwx[C], tsum[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        // lvz_mid at row (i+1): D+z of beta_z K mu_pz
+        const float q0 = bK[0][c] * MZ[S0][c], q1 = bK[1][c] * MZ[S1][c];
+        const float q2 = bK[2][c] * MZ[S2][c], q3 = bK[3][c] * MZ[S3][c];
+        lvzm[c] = rn ? lvz1[c] + (kC1 * (q2 - q1) + kC2 * (q3 - q0)) * g.rdz : 0.f;
+        accZ[c] += lvzm[c] * (-bhz1 * (kC1 * (PN[S2][c] - PN[S1][c]) +
+                                       kC2 * (PN[S3][c] - PN[S0][c])) * g.rdz);
+        WZ[S3][c] = bhz1 * bz1[c] * lvzm[c];
+        // lvx_mid at row i: D+x of beta_x K mu_px
+        qx[c] = xt.btx[c] * K0[c] * MU[S0][c];
+    }
+    dfwd<C>(qx, dqx);
+    dfwd<C>(PN[S0], dpx);
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        lvxm[c] = w.colok[c] ? lvx[c] + dqx[c] * g.rdx : 0.f;
+        accX[c] += lvxm[c] * (-xt.bhx[c] * dpx[c] * g.rdx);
+        wx[c] = xt.bhx[c] * bx[c] * lvxm[c];
+    }
+    dbwd<C>(wx, dwx);
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const float dwz = kC1 * (WZ[S2][c] - WZ[S1][c]) + kC2 * (WZ[S3][c] - WZ[S0][c]);
+        tsum[c] = dwx[c] * g.rdx + dwz * g.rdz;
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const float mux = MU[S0][c], muz = MZ[S0][c], p0 = PN[S0][c];
+        numK[c] += mux * ((p1[c] - z1[c]) - xt.ax[c] * (p0 - z0[c])) + muz * (z1[c] - az * z0[c]);
+        o.opx[c] = xt.ax[c] * mux + tsum[c];
+        o.opz[c] = az * muz + tsum[c];
+        o.ovx[c] = xt.ahx[c] * lvxm[c];
+        o.ovz[c] = ahz1 * lvzm[c];
+    }
+}
+
 template <int SPG, int C>
 struct ARow {   // loads needed early in the row (double buffered)
     float K3[C], bx[C], bz1[C];                 // K at r+3, bx at r, bz at r+1
@@ -1125,54 +1186,23 @@ __global__ void __launch_bounds__(NTHR)
 #pragma unroll
         for (int k = 0; k < SPG; ++k) {
             mask_cols<C>(w, b.pn3[k]);
-            float lvzm[C], qx[C], dqx[C], dpx[C], lvxm[C], wx[C], dwx[C], tsum[C];
 #pragma unroll
             for (int c = 0; c < C; ++c) {
                 MU[k][S3][c] = b.mu3[k][c];
                 MZ[k][S3][c] = rp3 || w.colpml[c] ? b.mz3[k][c] : b.mu3[k][c];
                 PN[k][S3][c] = b.pn3[k][c];
-                // lvz_mid at row (i+1): D+z of beta_z K mu_pz
-                const float q0 = bK[0][c] * MZ[k][S0][c], q1 = bK[1][c] * MZ[k][S1][c];
-                const float q2 = bK[2][c] * MZ[k][S2][c], q3 = bK[3][c] * MZ[k][S3][c];
-                lvzm[c] = rn ? b.lvz1[k][c] + (kC1 * (q2 - q1) + kC2 * (q3 - q0)) * g.rdz : 0.f;
-                accZ[c] += lvzm[c] * (-bhz1 * (kC1 * (PN[k][S2][c] - PN[k][S1][c]) +
-                                               kC2 * (PN[k][S3][c] - PN[k][S0][c])) * g.rdz);
-                WZ[k][S3][c] = bhz1 * b.bz1[c] * lvzm[c];
-                // lvx_mid at row i: D+x of beta_x K mu_px
-                qx[c] = xt.btx[c] * KW[S0][c] * MU[k][S0][c];
             }
-            dfwd<C>(qx, dqx);
-            dfwd<C>(PN[k][S0], dpx);
-#pragma unroll
-            for (int c = 0; c < C; ++c) {
-                lvxm[c] = w.colok[c] ? b.lvx[k][c] + dqx[c] * g.rdx : 0.f;
-                accX[c] += lvxm[c] * (-xt.bhx[c] * dpx[c] * g.rdx);
-                wx[c] = xt.bhx[c] * b.bx[c] * lvxm[c];
-            }
-            dbwd<C>(wx, dwx);
-#pragma unroll
-            for (int c = 0; c < C; ++c) {
-                const float dwz = kC1 * (WZ[k][S2][c] - WZ[k][S1][c]) + kC2 * (WZ[k][S3][c] - WZ[k][S0][c]);
-                tsum[c] = dwx[c] * g.rdx + dwz * g.rdz;
-            }
-            float opx[C], opz[C], ovx[C], ovz[C];
-#pragma unroll
-            for (int c = 0; c < C; ++c) {
-                const float mux = MU[k][S0][c], muz = MZ[k][S0][c], p0 = PN[k][S0][c];
-                const float z0 = t.z0[k][c], z1 = t.z1[k][c], p1 = t.pn1[k][c];
-                numK[c] += mux * ((p1 - z1) - xt.ax[c] * (p0 - z0)) + muz * (z1 - az * z0);
-                opx[c] = xt.ax[c] * mux + tsum[c];
-                opz[c] = az * muz + tsum[c];
-                ovx[c] = xt.ahx[c] * lvxm[c];
-                ovz[c] = ahz1 * lvzm[c];
-            }
+            AdjOut<C> o;
+            adj_shot<C, S0, S1, S2, S3>(g, xt, w, rn, ahz1, bhz1, az, bK, KW[S0], MU[k], MZ[k],
+                                        PN[k], WZ[k], b.lvz1[k], b.lvx[k], b.bx, b.bz1,
+                                        t.pn1[k], t.z0[k], t.z1[k], numK, accX, accZ, o);
             const unsigned ko = skoff(a.lout, k);
-            vst_row<C>(rLout, w, true, rb + 2u * FB + ko, opx);
+            vst_row<C>(rLout, w, true, rb + 2u * FB + ko, o.opx);
 #pragma unroll
             for (int c = 0; c < C; ++c)
-                bst(rLout, zw[c], z.base + 3u * FB + ko, opz[c]);
-            vst_row<C>(rLout, w, true, rb + ko, ovx);
-            vst_row<C>(rLout, w, more, rb + rowN + FB + ko, ovz);
+                bst(rLout, zw[c], z.base + 3u * FB + ko, o.opz[c]);
+            vst_row<C>(rLout, w, true, rb + ko, o.ovx);
+            vst_row<C>(rLout, w, more, rb + rowN + FB + ko, o.ovz);
         }
         // one reciprocal per row for the bulk-modulus sensitivity (1 ulp)
         float gk[C], gx[C], gz[C];
@@ -1219,6 +1249,418 @@ __global__ void __launch_bounds__(NTHR)
     }
 }
 
+// ------------------------------------------------------- adjoint, two steps
+//
+// Adjoint steps n and n-1 in one pass, the reverse counterpart of k_fwd2.
+// Step A (adjoint step n) runs on rows [i0-3, i1+3) of the band with a
+// 6-column halo; step B (adjoint step n-1) follows three rows behind, on
+// rows [i0-3, i1) (its first three rows only fill its windows, their
+// results are dropped).  Step A's new adjoint state never leaves the chip:
+// its pressure rows feed step B's windows, and its velocities, the model
+// rows and p^n reach step B through four-slot rings read three rows later.
+// Between the two steps the adjoint source of step n-1, summed per receiver
+// node by the injection launch before this one, is added to step A's new
+// pressure at the nodes in the wave's window, the value the separate
+// injection launch adds between two one-step launches.  Step A's
+// sensitivities on the wave's own rows wait three rows and are added to the
+// group's partial gradient before step B's, each with the one-step kernel's
+// expression, so the pair rounds exactly as two one-step launches.
+
+template <int SPG, int C>
+struct A2Row {   // loads of iteration t (double buffered)
+    float K3[C], bx[C], bz1[C];                   // K at t+3, bx at t, bz at t+1
+    float mu3[SPG][C], mz3[SPG][C], pn3[SPG][C];  // mu_px, mu_pz, p^n at t+3
+    float lvz1[SPG][C], lvx[SPG][C];              // lvz at t+1, lvx at t
+    float pm[SPG][C];                             // p^{n-1} at t
+    unsigned inj[SPG];                            // injection nodes of row t (packed)
+};
+template <int SPG, int C>
+struct A2Late {  // loads needed at the end of iteration t (single set)
+    float gK[C], gX[C], gZ1[C];                   // partials at r = t-3 (gbz at r+1)
+    float pn1[SPG][C], z0[SPG][C], z1[SPG][C];    // p^{n+1} at t; splits of p^n, p^{n+1} at t
+    float zm[SPG][C], zn[SPG][C];                 // splits of p^{n-1}, p^n at r
+};
+
+typedef const __attribute__((address_space(4))) unsigned cuint;
+typedef const __attribute__((address_space(4))) int cint;
+
+template <int SPG, int C>
+__global__ void __launch_bounds__(NTHR)
+    k_adj2(Geo g, const float *__restrict__ tabs, const float *model, int S, Sweep sw, AdjStep2 a)
+{
+    WaveGeo<C> w;
+    if (!wave_geo<C, 2 * HALO>(g, sw, w))
+        return;
+    XTab<C> xt;
+    xtab<C>(g, tabs, w, xt);
+    // z tables with kZPad zero rows on each side (rows outside the grid
+    // read zero without a branch)
+    const int ZP = g.Nz + 2 * kZPad;
+    cfloat *zaz = ctab(a.zpad) + kZPad, *zbz = zaz + ZP;
+    cfloat *zahz = zbz + ZP, *zbhz = zahz + ZP;
+    cuint *injwin = (cuint *)a.injwin;
+    cint *injcol = (cint *)a.injcol;
+    cfloat *injacc = ctab(a.injacc);
+    const unsigned FB = 4u * (unsigned)g.N;
+    const rsrc_t rM = res(model, 3u * FB);                                  // K, bx, bz
+    const rsrc_t rG = res(a.gpart + (long long)w.grp * 3 * g.N, 3u * FB);  // gK, gbx, gbz
+    const rsrc_t rLin = grp_res(a.lin, w.s0, SPG), rLout = grp_res(a.lout, w.s0, SPG);
+    // the three pressure levels of the group: p^{n-1} at 0, p^n at lvl,
+    // p^{n+1} at 2 lvl bytes
+    const rsrc_t rP = res((const float *)((const char *)a.pm1.base + (size_t)w.s0 * a.pm1.sbytes),
+                          2u * a.lvl + (unsigned)(SPG - 1) * a.pm1.sbytes + a.pm1.bytes);
+    const unsigned LN = a.lvl, LN1 = 2u * a.lvl;
+    auto rowpml = [&](int r) { return r < g.npml || r >= g.Nz - g.npml; };
+    // byte offset of row r plus `extra`, 0 for rows outside the grid (whose
+    // lane offsets are then kOOB)
+    auto rofs = [&](int r, unsigned extra) -> unsigned {
+        return row_ok(g, r) ? rowb(g, r) + extra : 0u;
+    };
+    auto vo = [&](bool ok) -> unsigned { return ok ? w.vcol : kOOB; };
+    // mu_pz of shot k at row r (zero outside the grid)
+    auto muz_at = [&](int k, int r, float (&o)[C]) {
+        const bool ok = row_ok(g, r);
+        const unsigned kl = skoff(a.lin, k);
+        float mx[C];
+        vld<C>(rLin, vo(ok), rofs(r, 2u * FB + kl), mx);
+        const ZRow z = zrow(g, ok ? r : 0);
+        unsigned oz[C];
+        zoffs<C>(w, z, ok, oz);
+        const bool rp = rowpml(r);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const float mz = bld(rLin, oz[c], z.base + 3u * FB + kl);
+            o[c] = rp || w.colpml[c] ? mz : mx[c];
+        }
+    };
+
+    const int tA0 = w.i0 - 3, tend = w.i1 + 3;   // step-A rows [tA0, tend)
+
+    // Windows (rings of 4 slots relabelled by the phase R = (t - tA0) mod 4,
+    // as in k_adj): step A's rows t .. t+3 (WZA: t-2 .. t+1), step B's rows
+    // r .. r+3 (WZB: r-2 .. r+1) with r = t-3.  Delay rings: slot R holds
+    // the value of iteration t, slot R+1 that of iteration t-3.
+    float KA[4][C], KB[4][C];
+    float MUA[SPG][4][C], MZA[SPG][4][C], PNA[SPG][4][C], WZA[SPG][4][C];
+    float MUB[SPG][4][C], MZB[SPG][4][C], PMB[SPG][4][C], WZB[SPG][4][C];
+    float DLX[SPG][4][C], DLZ[SPG][4][C], DPN[SPG][4][C];   // A's lvx (row t), lvz (t+1), p^n (t)
+    float DBX[4][C], DBZ[4][C];                             // bx (row t), bz (t+1)
+    float DNK[4][C], DAX[4][C], DAZ[4][C];                  // A's gK numerator, gbx (t), gbz (t+1)
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            KB[q][c] = DBX[q][c] = DBZ[q][c] = DNK[q][c] = DAX[q][c] = DAZ[q][c] = 0.f;
+#pragma unroll
+            for (int k = 0; k < SPG; ++k)
+                MUB[k][q][c] = MZB[k][q][c] = PMB[k][q][c] = WZB[k][q][c] = DLX[k][q][c] =
+                    DLZ[k][q][c] = DPN[k][q][c] = 0.f;
+        }
+
+    // step A's windows at its first row tA0 (k_adj's start of a band)
+    {
+        float Kr[6][C], btzr[6], wzr[3][C];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            const int r = tA0 - 3 + q;
+            vld<C>(rM, vo(row_ok(g, r)), rofs(r, 0u), Kr[q]);
+            btzr[q] = zbz[r];
+        }
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int r = tA0 - 2 + q;
+            float bz[C];
+            vld<C>(rM, vo(row_ok(g, r)), rofs(r, 2u * FB), bz);
+            const float bhz = zbhz[r];
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                wzr[q][c] = bhz * bz[c];
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            KA[0][c] = Kr[3][c];
+            KA[1][c] = Kr[4][c];
+            KA[2][c] = Kr[5][c];
+            KA[3][c] = 0.f;
+        }
+#pragma unroll
+        for (int k = 0; k < SPG; ++k) {
+            const unsigned kl = skoff(a.lin, k), kn = skoff(a.pm1, k);
+            float qz[6][C], pnr[4][C];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                float mz[C];
+                muz_at(k, tA0 - 3 + q, mz);
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+                    qz[q][c] = Kr[q][c] * btzr[q] * mz[c];
+                if (q >= 3) {
+#pragma unroll
+                    for (int c = 0; c < C; ++c)
+                        MZA[k][q - 3][c] = mz[c];
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int r = tA0 - 1 + q;
+                vld<C>(rP, vo(row_ok(g, r)), rofs(r, LN + kn), pnr[q]);
+                mask_cols<C>(w, pnr[q]);
+            }
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                WZA[k][3][c] = 0.f;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                const int r = tA0 - 2 + q;
+                const bool ok = row_ok(g, r);
+                float lz[C];
+                vld<C>(rLin, vo(ok), rofs(r, FB + kl), lz);
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    const float l = ok ? lz[c] + (kC1 * (qz[q + 2][c] - qz[q + 1][c]) +
+                                                  kC2 * (qz[q + 3][c] - qz[q][c])) * g.rdz
+                                       : 0.f;
+                    WZA[k][q][c] = wzr[q][c] * l;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                const int r = tA0 + q;
+                vld<C>(rLin, vo(row_ok(g, r)), rofs(r, 2u * FB + kl), MUA[k][q]);
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+                    PNA[k][q][c] = pnr[q + 1][c];
+            }
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                MUA[k][3][c] = MZA[k][3][c] = PNA[k][3][c] = 0.f;
+        }
+    }
+
+    auto load_row = [&](int t, A2Row<SPG, C> &b) {
+        const bool live = t < tend;
+        const bool ok0 = live && row_ok(g, t), ok1 = live && row_ok(g, t + 1);
+        const bool ok3 = live && row_ok(g, t + 3);
+        const ZRow z3 = zrow(g, ok3 ? t + 3 : 0);
+        unsigned oz3[C];
+        zoffs<C>(w, z3, ok3, oz3);
+        vld<C>(rM, vo(ok3), rofs(t + 3, 0u), b.K3);
+        vld<C>(rM, vo(ok0), rofs(t, FB), b.bx);
+        vld<C>(rM, vo(ok1), rofs(t + 1, 2u * FB), b.bz1);
+#pragma unroll
+        for (int k = 0; k < SPG; ++k) {
+            const unsigned kl = skoff(a.lin, k), kp = skoff(a.pm1, k);
+            vld<C>(rLin, vo(ok3), rofs(t + 3, 2u * FB + kl), b.mu3[k]);
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                b.mz3[k][c] = bld(rLin, oz3[c], z3.base + 3u * FB + kl);
+            vld<C>(rP, vo(ok3), rofs(t + 3, LN + kp), b.pn3[k]);
+            vld<C>(rLin, vo(ok1), rofs(t + 1, FB + kl), b.lvz1[k]);
+            vld<C>(rLin, vo(ok0), rofs(t, kl), b.lvx[k]);
+            vld<C>(rP, vo(ok0), rofs(t, kp), b.pm[k]);
+            const int s = w.s0 + k;
+            // (rows and padding shots without nodes hold 0)
+            b.inj[k] = injwin[((unsigned)s * (unsigned)ZP + (unsigned)(t + kZPad)) *
+                                  (unsigned)sw.nstrips + (unsigned)w.strip];
+        }
+    };
+    // values needed late in iteration t (issued before the next row's loads)
+    auto load_late = [&](int t, A2Late<SPG, C> &L) {
+        const int r = t - 3;
+        const bool own = r >= w.i0 && r < w.i1, ownz = r + 1 >= w.i0 && r + 1 < w.i1;
+        // partial gradient of step B's row: this wave's output columns only
+        // (the lane holding the last column reads its elements one by one)
+        const unsigned gk = own ? w.vcolw : kOOB, gz = ownz ? w.vcolw : kOOB;
+        const unsigned ob = own ? rowb(g, r) : 0u, obz = ownz ? rowb(g, r + 1) : 0u;
+        vld<C>(rG, gk, ob, L.gK);
+        vld<C>(rG, gk, ob + FB, L.gX);
+        vld<C>(rG, gz, obz + 2u * FB, L.gZ1);
+#pragma unroll
+        for (int c = 0; c + 1 < C; ++c) {
+            const float a0 = bld(rG, own ? w.vtail[c] : kOOB, ob);
+            const float a1 = bld(rG, own ? w.vtail[c] : kOOB, ob + FB);
+            const float a2 = bld(rG, ownz ? w.vtail[c] : kOOB, obz + 2u * FB);
+            const bool tl = w.vtail[c] != kOOB;
+            L.gK[c] = tl ? a0 : L.gK[c];
+            L.gX[c] = tl ? a1 : L.gX[c];
+            L.gZ1[c] = tl ? a2 : L.gZ1[c];
+        }
+        const bool okt = row_ok(g, t), okr = row_ok(g, r);
+        const ZRow zt_ = zrow(g, okt ? t : 0), zr = zrow(g, okr ? r : 0);
+        unsigned oz[C], ozr[C];
+        zoffs<C>(w, zt_, okt, oz);
+        zoffs<C>(w, zr, okr, ozr);
+#pragma unroll
+        for (int k = 0; k < SPG; ++k) {
+            const unsigned kp = skoff(a.pm1, k);
+            vld<C>(rP, vo(okt), rofs(t, LN1 + kp), L.pn1[k]);
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                L.z0[k][c] = bld(rP, oz[c], zt_.base + FB + LN + kp);
+                L.z1[k][c] = bld(rP, oz[c], zt_.base + FB + LN1 + kp);
+                L.zm[k][c] = bld(rP, ozr[c], zr.base + FB + kp);
+                L.zn[k][c] = bld(rP, ozr[c], zr.base + FB + LN + kp);
+            }
+        }
+    };
+
+    auto row = [&](auto phase, int t, A2Row<SPG, C> &b, const A2Late<SPG, C> &L) {
+        constexpr int R = decltype(phase)::value;
+        constexpr int S0 = R & 3, S1 = (1 + R) & 3, S2 = (2 + R) & 3, S3 = (3 + R) & 3;
+        // ---- step A (adjoint step n) at row t
+        const bool okt = row_ok(g, t), rnA = row_ok(g, t + 1);
+        cfloat *bzt = zbz + t;
+        const float ahz1A = zahz[t + 1], bhz1A = zbhz[t + 1], azA = zaz[t];
+        const float bt0 = bzt[0], bt1 = bzt[1], bt2 = bzt[2], bt3 = bzt[3];
+        const bool rp3 = rowpml(t + 3), rpt = rowpml(t);
+        // ---- step B (adjoint step n-1) at row r
+        const int r = t - 3;
+        const bool runB = t >= w.i0;                          // r >= i0 - 3
+        const bool own = r >= w.i0;                           // (r < i1 always)
+        const bool ownz = r + 1 >= w.i0 && r + 1 < w.i1;      // owns lvz / gbz row r+1
+        const bool rnB = row_ok(g, r + 1);
+        const float ahz1B = zahz[r + 1], bhz1B = zbhz[r + 1], azB = zaz[r];
+        const float bu0 = bzt[-3], bu1 = bzt[-2], bu2 = bzt[-1], bu3 = bzt[0];
+        const unsigned rbB = own ? rowb(g, r) : 0u, rbZ = ownz ? rowb(g, r + 1) : 0u;
+        const ZRow zB = zrow(g, own ? r : 0);
+        unsigned zwB[C];
+        zoffs_w<C>(w, zB, zwB);
+        float numA[C], axA[C], azA_[C], bKA[4][C];
+        float numB[C], axB[C], azB_[C], bKB[4][C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            KA[S3][c] = b.K3[c];
+            KB[S3][c] = KA[S0][c];   // K at row t = r+3
+            numA[c] = axA[c] = azA_[c] = numB[c] = axB[c] = azB_[c] = 0.f;
+            bKA[0][c] = KA[S0][c] * bt0;
+            bKA[1][c] = KA[S1][c] * bt1;
+            bKA[2][c] = KA[S2][c] * bt2;
+            bKA[3][c] = KA[S3][c] * bt3;
+            bKB[0][c] = KB[S0][c] * bu0;
+            bKB[1][c] = KB[S1][c] * bu1;
+            bKB[2][c] = KB[S2][c] * bu2;
+            bKB[3][c] = KB[S3][c] * bu3;
+        }
+#pragma unroll
+        for (int k = 0; k < SPG; ++k) {
+            mask_cols<C>(w, b.pn3[k]);
+            mask_cols<C>(w, b.pm[k]);
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                MUA[k][S3][c] = b.mu3[k][c];
+                MZA[k][S3][c] = rp3 || w.colpml[c] ? b.mz3[k][c] : b.mu3[k][c];
+                PNA[k][S3][c] = b.pn3[k][c];
+            }
+            AdjOut<C> oA;
+            adj_shot<C, S0, S1, S2, S3>(g, xt, w, rnA, ahz1A, bhz1A, azA, bKA, KA[S0], MUA[k],
+                                        MZA[k], PNA[k], WZA[k], b.lvz1[k], b.lvx[k], b.bx, b.bz1,
+                                        L.pn1[k], L.z0[k], L.z1[k], numA, axA, azA_, oA);
+            // step A's new state as step B's input: zero outside the grid
+            float mA[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                mA[c] = okt && w.colok[c] ? oA.opx[c] : 0.f;
+            // the adjoint source of step n-1 at the receiver nodes of row t
+            const unsigned ie = b.inj[k];
+            if (ie != 0u) {
+                const unsigned first = ie >> 9, cnt = ie & 511u;
+                for (unsigned e = 0; e < cnt; ++e) {
+                    const int j = injcol[first + e];
+                    const float v = injacc[first + e];
+#pragma unroll
+                    for (int c = 0; c < C; ++c)
+                        if (w.j0 + c == j)
+                            mA[c] += v;
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const bool in = okt && w.colok[c];
+                MUB[k][S3][c] = mA[c];
+                MZB[k][S3][c] = rpt || w.colpml[c] ? (in ? oA.opz[c] : 0.f) : mA[c];
+                PMB[k][S3][c] = b.pm[k][c];
+            }
+            if (runB) {
+                AdjOut<C> oB;
+                adj_shot<C, S0, S1, S2, S3>(g, xt, w, rnB, ahz1B, bhz1B, azB, bKB, KB[S0],
+                                            MUB[k], MZB[k], PMB[k], WZB[k], DLZ[k][S1],
+                                            DLX[k][S1], DBX[S1], DBZ[S1], DPN[k][S1], L.zm[k],
+                                            L.zn[k], numB, axB, azB_, oB);
+                const unsigned ko = skoff(a.lout, k);
+                vst_row<C>(rLout, w, own, rbB + 2u * FB + ko, oB.opx);
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+                    bst(rLout, own ? zwB[c] : kOOB, zB.base + 3u * FB + ko, oB.opz[c]);
+                vst_row<C>(rLout, w, own, rbB + ko, oB.ovx);
+                vst_row<C>(rLout, w, ownz, rbZ + FB + ko, oB.ovz);
+            }
+            // step A's values for step B three rows later
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                DLX[k][S0][c] = okt && w.colok[c] ? oA.ovx[c] : 0.f;
+                DLZ[k][S0][c] = rnA && w.colok[c] ? oA.ovz[c] : 0.f;
+                DPN[k][S0][c] = PNA[k][S0][c];
+            }
+        }
+        if (runB) {
+            // step A's sensitivities at row r, then step B's, as two one-step
+            // launches add them (one reciprocal per row, 1 ulp)
+            float gk[C], gx[C], gz[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const float rK = KB[S0][c] != 0.f ? __builtin_amdgcn_rcpf(KB[S0][c]) : 0.f;
+                gk[c] = L.gK[c] + DNK[S1][c] * rK;
+                gk[c] = gk[c] + numB[c] * rK;
+                gx[c] = L.gX[c] + DAX[S1][c];
+                gx[c] = gx[c] + axB[c];
+                gz[c] = L.gZ1[c] + DAZ[S1][c];
+                gz[c] = gz[c] + azB_[c];
+            }
+            vst_row<C>(rG, w, own, rbB, gk);
+            vst_row<C>(rG, w, own, rbB + FB, gx);
+            vst_row<C>(rG, w, ownz, rbZ + 2u * FB, gz);
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            DNK[S0][c] = numA[c];
+            DAX[S0][c] = axA[c];
+            DAZ[S0][c] = azA_[c];
+            DBX[S0][c] = b.bx[c];
+            DBZ[S0][c] = b.bz1[c];
+        }
+    };
+
+    A2Row<SPG, C> A, B;
+    A2Late<SPG, C> L;
+    using P0 = std::integral_constant<int, 0>;
+    using P1 = std::integral_constant<int, 1>;
+    using P2 = std::integral_constant<int, 2>;
+    using P3 = std::integral_constant<int, 3>;
+    load_row(tA0, A);
+    for (int t = tA0;;) {
+        load_late(t, L);
+        load_row(t + 1, B);
+        row(P0{}, t, A, L);
+        if (++t >= tend)
+            break;
+        load_late(t, L);
+        load_row(t + 1, A);
+        row(P1{}, t, B, L);
+        if (++t >= tend)
+            break;
+        load_late(t, L);
+        load_row(t + 1, B);
+        row(P2{}, t, A, L);
+        if (++t >= tend)
+            break;
+        load_late(t, L);
+        load_row(t + 1, A);
+        row(P3{}, t, B, L);
+        if (++t >= tend)
+            break;
+    }
+}
+
 inline unsigned blocks_of(const Sweep &sw)
 {
     return (unsigned)((sw.nwaves + NTHR / WAVE - 1) / (NTHR / WAVE));
@@ -1248,7 +1690,22 @@ void launch_a(const Geo &g, const float *tabs, const float *model, const SweepTa
                           tabs, model, T, S, sw, a);
 }
 
+template <int SPG, int C>
+void launch_a2(const Geo &g, const float *tabs, const float *model, int S, const Sweep &sw,
+               const AdjStep2 &a, hipStream_t st, hipEvent_t e0, hipEvent_t e1)
+{
+    hipExtLaunchKernelGGL((k_adj2<SPG, C>), dim3(blocks_of(sw)), dim3(NTHR), 0, st, e0, e1, 0, g,
+                          tabs, model, S, sw, a);
+}
+
 }  // namespace
+
+// Instantiated (shots per group, columns per lane) pairs of the two-step
+// adjoint kernel.
+bool adj2_supported(int spg, int cols)
+{
+    return cols == 1 ? (spg == 1 || spg == 2 || spg == 4) : (cols == 2 && (spg == 1 || spg == 2));
+}
 
 // Instantiated (shots per group, columns per lane) pairs of the two-step
 // forward kernel.
@@ -1329,6 +1786,20 @@ void launch_fused_fwd2(const Geo &g, const float *tabs, const float *model,
     case 32 + 1: launch_f2<1, 2>(g, tabs, model, T, S, sw, a, st, e0, e1); break;
     case 32 + 2: launch_f2<2, 2>(g, tabs, model, T, S, sw, a, st, e0, e1); break;
     case 64 + 1: launch_f2<1, 4>(g, tabs, model, T, S, sw, a, st, e0, e1); break;
+    default: break;
+    }
+}
+
+void launch_fused_adj2(const Geo &g, const float *tabs, const float *model, int S,
+                       const Sweep &sw, const AdjStep2 &a, hipStream_t st, hipEvent_t e0,
+                       hipEvent_t e1)
+{
+    switch (sw.cols * 16 + sw.spg) {
+    case 16 + 1: launch_a2<1, 1>(g, tabs, model, S, sw, a, st, e0, e1); break;
+    case 16 + 2: launch_a2<2, 1>(g, tabs, model, S, sw, a, st, e0, e1); break;
+    case 16 + 4: launch_a2<4, 1>(g, tabs, model, S, sw, a, st, e0, e1); break;
+    case 32 + 1: launch_a2<1, 2>(g, tabs, model, S, sw, a, st, e0, e1); break;
+    case 32 + 2: launch_a2<2, 2>(g, tabs, model, S, sw, a, st, e0, e1); break;
     default: break;
     }
 }

@@ -20,6 +20,9 @@ def test_tune_and_cache(tmp_path, monkeypatch):
     Nz, Nx = g.padded
     assert (best["band_rows"], best["shots_per_group"], best["lane_cols"]) in \
         autotune.candidates(Nz, Nx, w.nshots)
+    if best["adj_two_step"] == 2:
+        assert (best["adj_two_step_band_rows"], best["shots_per_group"],
+                best["adj_two_step_lane_cols"]) in autotune.candidates_adj2(Nz, Nx, w.nshots)
     if best["two_step"] == 2:
         assert (best["two_step_band_rows"], best["two_step_shots_per_group"],
                 best["two_step_lane_cols"]) in autotune.candidates2(Nz, Nx, w.nshots)
