@@ -418,30 +418,39 @@ def main():
 
     S, G = w.nshots, info["shot_groups"]
     ab = algorithmic_bytes(info, S, info["ckpt_every"])
-    roof = None
+    roof, roof_all = None, {}
     if not args.no_kernel_timing:
-        sweeps = [k for k in ab["per_cell"] if per_class.get(k, (0, 0.0))[0]]
-        dom = max(sweeps, key=lambda k: per_class[k][1])
-        n_launch, dom_ms = per_class[dom]
-        avg_s = dom_ms / n_launch * 1e-3
-        per_launch = ab["per_cell"][dom] * ab["cell_steps"][dom]
-        achieved = per_launch / avg_s / 1e9
-        pre = "two_step_" if dom == "fwd_pair" else ""
-        kdec = {"band_rows": info[pre + "band_rows"],
-                "shots_per_group": info[pre + "shots_per_group"],
-                "lane_cols": info[pre + "lane_cols"], "workload": w.name}
-        roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
-                "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(achieved / PEAK_HBM_GBS, 4),
-                "traffic": measured_traffic(dom, kdec),
+        # every sweep kernel that ran: achieved = its per-cell-step algorithmic
+        # bytes x the cell-steps of one launch / its average launch time; the
+        # entry of the kernel with the largest total time is `roofline`
+        prefix = {"fwd_pair": "two_step_", "adj_pair": "adj_two_step_"}
+        for kc in ab["per_cell"]:
+            n_launch, kc_ms = per_class.get(kc, (0, 0.0))
+            if not n_launch:
+                continue
+            avg_s = kc_ms / n_launch * 1e-3
+            per_launch = ab["per_cell"][kc] * ab["cell_steps"][kc]
+            achieved = per_launch / avg_s / 1e9
+            pre = prefix.get(kc, "")
+            kdec = {"band_rows": info[pre + "band_rows"],
+                    "shots_per_group": info["two_step_shots_per_group" if kc == "fwd_pair"
+                                            else "shots_per_group"],
+                    "lane_cols": info[pre + "lane_cols"], "workload": w.name}
+            roof_all[kc] = {
+                "bound": "hbm", "kernel": kc, "achieved": round(achieved, 1),
+                "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                "traffic": measured_traffic(kc, kdec),
                 "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated)",
                 "avg_launch_us": round(avg_s * 1e6, 2), "launches": n_launch,
-                "cell_steps_per_launch": ab["cell_steps"][dom],
-                "bytes_per_cell_step": round(ab["per_cell"][dom], 3),
+                "total_ms": round(kc_ms, 2), "decomposition": kdec,
+                "cell_steps_per_launch": ab["cell_steps"][kc],
+                "bytes_per_cell_step": round(ab["per_cell"][kc], 3),
                 "bytes_per_launch": int(per_launch),
                 "gradient_bytes_per_cell_step": round(ab["gradient_per_cell"], 2),
                 "gradient_roof_gcells": round(PEAK_HBM_GBS / ab["gradient_per_cell"], 1),
                 "pml_fraction": round(ab["pml_fraction"], 4)}
+        if roof_all:
+            roof = roof_all[max(roof_all, key=lambda k: roof_all[k]["total_ms"])]
     classes = {k: {"launches": v[0], "ms": round(v[1], 3)} for k, v in per_class.items()
                if v[0]}
 
@@ -504,6 +513,9 @@ def main():
                    "two_step_band_rows": info["two_step_band_rows"],
                    "two_step_shots_per_group": info["two_step_shots_per_group"],
                    "two_step_lane_cols": info["two_step_lane_cols"],
+                   "adj_two_step": info["adj_two_step"],
+                   "adj_two_step_band_rows": info["adj_two_step_band_rows"],
+                   "adj_two_step_lane_cols": info["adj_two_step_lane_cols"],
                    "decomposition": "autotuned" if tuned else "given" if any(
                        v for k, v in decomp.items() if k != "two_step") else "default",
                    "ckpt_every": info["ckpt_every"], "segments": info["segments"]},
@@ -511,6 +523,7 @@ def main():
                             "p99": round(float(np.percentile(lat, 99)), 3),
                             "over": f"{args.steps} back-to-back gradient calls"},
         "roofline": roof,
+        "roofline_by_kernel": roof_all,
         "kernels": classes,
         "checkpointed": ckpt,
         "plain": plain,

@@ -30,7 +30,7 @@ from .api import Grid, Plan
 # much as the height), then coarser steps
 ROWS = (8, 9, 10, 11, 12, 13, 14, 15, 16, 20, 24, 32, 48, 64, 96, 128)
 ROWS2 = (12, 14, 16, 18, 20, 24, 28, 32, 48, 64, 96)
-ROWSA = (12, 16, 20, 24, 32, 48, 64, 96, 128)
+ROWSA = (12, 16, 20, 24, 32, 48, 64, 96, 128, 192, 256)
 # supported (shots per group, columns per lane) pairs of the one-step
 # kernels and of the two-step forward kernel
 PAIRS = ((1, 1), (2, 1), (4, 1), (8, 1), (1, 2), (2, 2), (4, 2), (1, 4), (2, 4))
@@ -161,14 +161,6 @@ def tune(grid: Grid, src_xz, rec_xz, force=False, verbose=False, device=None):
             return dict(shipped[key]["best"])
     t0 = time.perf_counter()
     res1, resa, res2 = [], [], []
-    for H, spg, cols in candidates(Nz, Nx, S):
-        t = measure(grid, src_xz, rec_xz, device=device, band_rows=H, shots_per_group=spg,
-                    lane_cols=cols, two_step=1, adj_two_step=1)
-        res1.append({"band_rows": H, "shots_per_group": spg, "lane_cols": cols,
-                     "adj_ms": t.get("adj_step", 0.0), "fwd_ms": t.get("fwd_step", 0.0)})
-        if verbose:
-            print(f"  adjoint band_rows={H:4d} spg={spg} cols={cols}: "
-                  f"{res1[-1]['adj_ms'] * 1e3:8.1f} us", flush=True)
     for H, spg, cols in candidates_adj2(Nz, Nx, S):
         t = measure(grid, src_xz, rec_xz, device=device, shots_per_group=spg, two_step=1,
                     adj_two_step=2, adj_two_step_band_rows=H, adj_two_step_lane_cols=cols)
@@ -177,6 +169,19 @@ def tune(grid: Grid, src_xz, rec_xz, force=False, verbose=False, device=None):
         if verbose:
             print(f"  two-step adjoint band_rows={H:4d} spg={spg} cols={cols}: "
                   f"{resa[-1]['pair_ms'] * 1e3:8.1f} us per 2 steps", flush=True)
+    # one-step adjoint: the shot grouping of the best pair (whose leftover
+    # steps it takes) and the widest grouping (if the pair loses)
+    spg_pair = min(resa, key=lambda r: r["pair_ms"])["shots_per_group"] if resa else 0
+    for H, spg, cols in candidates(Nz, Nx, S):
+        if spg not in (spg_pair, 8) and resa:
+            continue
+        t = measure(grid, src_xz, rec_xz, device=device, band_rows=H, shots_per_group=spg,
+                    lane_cols=cols, two_step=1, adj_two_step=1)
+        res1.append({"band_rows": H, "shots_per_group": spg, "lane_cols": cols,
+                     "adj_ms": t.get("adj_step", 0.0), "fwd_ms": t.get("fwd_step", 0.0)})
+        if verbose:
+            print(f"  adjoint band_rows={H:4d} spg={spg} cols={cols}: "
+                  f"{res1[-1]['adj_ms'] * 1e3:8.1f} us", flush=True)
     best1 = min(res1, key=lambda r: r["adj_ms"])
     best = {k: best1[k] for k in ("band_rows", "shots_per_group", "lane_cols")}
     best["adj_two_step"] = 1

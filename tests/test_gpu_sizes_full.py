@@ -33,6 +33,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+from paper_1804_01184_amd import autotune
 from paper_1804_01184_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -68,7 +69,7 @@ def shipped_decomposition(w):
     Nz, Nx = w.padded
     with open(SHIPPED) as fh:
         table = json.load(fh)
-    return dict(table[f"gfx950:{Nz}x{Nx}:S{w.nshots}:pml{w.npml}:v4"]["best"])
+    return dict(table[autotune._key(Nz, Nx, w.nshots, w.npml, "gfx950")]["best"])
 
 
 def ogrid(w):
@@ -256,7 +257,7 @@ def test_layered2001_traces(api):
     ora = Oracle(w)
     Nz, Nx = full.padded
     with open(SHIPPED) as fh:
-        d = dict(json.load(fh)[f"gfx950:{Nz}x{Nx}:S32:pml40:v4"]["best"])
+        d = dict(json.load(fh)[autotune._key(Nz, Nx, 32, 40, "gfx950")]["best"])
     plan = api.Plan(api.Grid.of(w), w.src_xz, w.rec_xz, ckpt_every=90, **d)
     tr = plan.forward("k-rho", ora.K0, ora.r0, ora.f).cpu().numpy()
     err = gather_err(tr, ora.traces())
