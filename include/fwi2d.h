@@ -34,9 +34,12 @@
  *  - Work is enqueued on `stream` (a hipStream_t; NULL is the default
  *    stream) and the calls return without waiting for it.  Scalars such as J
  *    are written to device memory.
- *  - Scratch memory comes from the caller's workspace `ws` of at least
- *    fwi_workspace_bytes(plan, op) bytes, 256-byte aligned.  The plan owns
- *    only small geometry tables, allocated at creation.
+ *  - The library never allocates device memory.  Scratch memory comes from
+ *    the caller's workspace `ws` of at least fwi_workspace_bytes(plan, op)
+ *    bytes, 256-byte aligned; calls that need the plan's geometry tables
+ *    (forward, gradient, adjoint) copy them from the plan's host memory into
+ *    the workspace when they start (a few MB at most) and build the damping
+ *    tables there.
  *  - Calls return a status and never throw.  Argument errors are reported
  *    before any work is enqueued; fwi_last_error() then describes the
  *    failure (thread-local).  Device faults surface from fwi_sync().
@@ -56,7 +59,7 @@ extern "C" {
 typedef enum {
     FWI_OK = 0,
     FWI_EINVAL = -1,      /* bad argument, shape or geometry                  */
-    FWI_ENOMEM = -2,      /* host or device allocation of plan tables failed */
+    FWI_ENOMEM = -2,      /* host allocation of the plan's tables failed      */
     FWI_EDEVICE = -3,     /* HIP runtime error                                */
     FWI_EUNSTABLE = -4,   /* dt * vmax / min(dx, dz) above the stability limit */
     FWI_ENONFINITE = -5,  /* non-finite value detected                        */
@@ -159,12 +162,16 @@ typedef struct fwi_plan fwi_plan;
  * fourth-order staggered scheme in 2-D, else FWI_EUNSTABLE) and the
  * geometry: every source and receiver must have its four bilinear nodes
  * inside the physical grid, outside the absorbing layer (else FWI_EINVAL).
- * `exec` may be NULL (batched defaults).  On success *out owns small device
- * tables; release with fwi_plan_destroy. */
+ * `exec` may be NULL (batched defaults).  The plan holds host memory only
+ * (the geometry tables, copied into the workspace by every call that needs
+ * them); no device memory is allocated and no device work is enqueued.
+ * FWI_ENOMEM if the host tables cannot be allocated.  Release with
+ * fwi_plan_destroy. */
 fwi_status fwi_plan_create(const fwi_grid *grid, const fwi_acq *acq,
                            const fwi_exec *exec, fwi_plan **out);
 
-/* Releases a plan (NULL is ignored).  Work using it must have finished. */
+/* Releases a plan (NULL is ignored).  Work using it must have finished: its
+ * host tables are the source of the table copies enqueued by the calls. */
 void fwi_plan_destroy(fwi_plan *plan);
 
 fwi_status fwi_plan_get_info(const fwi_plan *plan, fwi_plan_info *info);

@@ -106,8 +106,9 @@ class Plan:
         self._ws = {}
 
     def __del__(self):
-        # fwi_plan_destroy frees the plan's device tables; hipFree waits for
-        # the device, so work still using them completes first
+        # the plan holds host memory only; fwi_plan_destroy keeps its tables
+        # until the last queued copy of them has run, so this never waits
+        # for the device
         h = getattr(self, "_h", None)
         if h is not None and h.value:
             L.lib().fwi_plan_destroy(h)

@@ -59,22 +59,20 @@ struct fwi_plan {
     int device;
     Geo geo;
     long long SS, ST;  // per-shot floats of a state record / a store record
-    // device tables (one allocation)
-    void *dev = nullptr;
-    float *pml = nullptr;
-    int2 *src_ij = nullptr;
-    float4 *src_w = nullptr;
-    long long *rec_idx = nullptr;
-    float4 *rec_w = nullptr;
-    long long *inj_node = nullptr;
-    int *inj_shot = nullptr, *inj_cptr = nullptr, *inj_crec = nullptr;
-    float *inj_cw = nullptr;
+    // Geometry tables.  The plan holds no device memory: every call that
+    // needs them copies the host image `blob` into its workspace and builds
+    // the damping tables there (TabOff: byte offsets in the workspace's
+    // table region).
+    struct TabOff {
+        size_t pml, zpad, st;                            // built on the device
+        size_t sij, sw, ri, rw, in, is, ip, ir, iw, win, col; // copied from blob
+        size_t blob;                                     // offset of blob's image
+        size_t bytes;                                    // size of the region
+    } to{};
+    std::vector<char> blob;
+    hipEvent_t blob_ev = nullptr;   // recorded after the last copy of blob
     int inj_nodes = 0;
-    unsigned *inj_win = nullptr;   // two-step adjoint: [Spad][Nz + 2 kZPad][strips] packed node ranges
-    float *zpad = nullptr;         // z damping tables with kZPad zero rows on each side
-    int *inj_col = nullptr;        // grid column of each injection node
     std::vector<int> shot_node_ptr;  // [S+1] node range of each shot
-    SweepTables *sweep_tabs = nullptr;   // device copy of the source tables
     std::vector<int2> h_src_ij;
     std::vector<float4> h_src_w;
     // per-launch event timing (instrumentation)
@@ -155,6 +153,7 @@ fwi_status collect_marks(fwi_plan *p)
 }
 
 struct Layout {
+    size_t tab;   // geometry and damping tables (FWI_OP_FORWARD / FWI_OP_GRADIENT)
     size_t Kphys, rhophys, Kpad, bx, bz, Q;
     size_t work[2], lam[2];
     size_t ckpt, store, gpart, fold, traces, resid, partials;
@@ -171,10 +170,15 @@ Layout layout(const fwi_plan *p, int op)
     Layout L{};
     size_t off = 0;
     // every array is followed by at least 64 spare bytes (the batched
-    // kernels may read a few bytes past a field and discard them)
+    // kernels may read a few bytes past a field and discard them); arrays of
+    // 8 MB and more start on 2 MB boundaries (from a 2 MB-aligned workspace,
+    // huge-page boundaries): measured on MI355X, the sweeps then run 5-7 %
+    // faster than with 256-byte alignment
     auto take = [&](size_t floats) {
+        const size_t bytes = floats * sizeof(float) + 64;
+        off = align_up(off, bytes >= (8u << 20) ? (size_t)2 << 20 : kAlign);
         size_t o = off;
-        off = align_up(off + floats * sizeof(float) + 64, kAlign);
+        off = align_up(off + bytes, kAlign);
         return o;
     };
     const Geo &g = p->geo;
@@ -186,6 +190,8 @@ Layout layout(const fwi_plan *p, int op)
         L.total = off;
         return L;
     }
+    L.tab = off;
+    off = align_up(off + p->to.bytes + 64, kAlign);
     L.Kphys = take(nphys);
     L.rhophys = take(nphys);
     // K, bx, bz as one block (the batched kernels address them from K)
@@ -230,20 +236,35 @@ State state_at(float *base, const fwi_plan *pl)
     return s;
 }
 
+// Device addresses of the plan's tables in a workspace.
+struct DevTabs {
+    float *pml = nullptr, *zpad = nullptr;
+    SweepTables *sweep_tabs = nullptr;
+    int2 *src_ij = nullptr;
+    float4 *src_w = nullptr;
+    long long *rec_idx = nullptr;
+    float4 *rec_w = nullptr;
+    long long *inj_node = nullptr;
+    int *inj_shot = nullptr, *inj_cptr = nullptr, *inj_crec = nullptr;
+    float *inj_cw = nullptr;
+    unsigned *inj_win = nullptr;   // two-step adjoint: [Spad][Nz + 2 kZPad][strips]
+    int *inj_col = nullptr;        // grid column of each injection node
+};
+
 struct Ctx {
     fwi_plan *pl;
     hipStream_t st;
     char *ws;
     Layout L;
+    DevTabs tb;
     Pml t;
     Mdl m;
     float *f(size_t off) const { return (float *)(ws + off); }
 };
 
-Pml pml_tables(const fwi_plan *p)
+Pml pml_tables(const fwi_plan *p, const float *b)
 {
     const Geo &g = p->geo;
-    const float *b = p->pml;
     Pml t;
     t.ax = b;
     t.bx = b + g.Nx;
@@ -288,8 +309,8 @@ void copy_p(const Ctx &c, Fld dp, Fld dpz, Fld sp, Fld spz, int nb)
 Src src_of(const Ctx &c, int s0)
 {
     Src s;
-    s.ij = c.pl->src_ij + s0;
-    s.w = c.pl->src_w + s0;
+    s.ij = c.tb.src_ij + s0;
+    s.w = c.tb.src_w + s0;
     s.Q = c.f(c.L.Q) + (size_t)s0 * c.pl->grid.nt;
     s.nt = c.pl->grid.nt;
     return s;
@@ -298,8 +319,8 @@ Src src_of(const Ctx &c, int s0)
 Rec rec_of(const Ctx &c, int s0)
 {
     Rec r;
-    r.idx = c.pl->rec_idx + (size_t)s0 * c.pl->nrec;
-    r.w = c.pl->rec_w + (size_t)s0 * c.pl->nrec;
+    r.idx = c.tb.rec_idx + (size_t)s0 * c.pl->nrec;
+    r.w = c.tb.rec_w + (size_t)s0 * c.pl->nrec;
     r.nrec = c.pl->nrec;
     return r;
 }
@@ -309,11 +330,11 @@ Inj inj_of(const Ctx &c, int s0, int nb)
     const fwi_plan *p = c.pl;
     int a = p->shot_node_ptr[s0], b = p->shot_node_ptr[s0 + nb];
     Inj in;
-    in.node = p->inj_node + a;
-    in.shot = p->inj_shot + a;
-    in.cptr = p->inj_cptr + a;
-    in.crec = p->inj_crec;
-    in.cw = p->inj_cw;
+    in.node = c.tb.inj_node + a;
+    in.shot = c.tb.inj_shot + a;
+    in.cptr = c.tb.inj_cptr + a;
+    in.crec = c.tb.inj_crec;
+    in.cw = c.tb.inj_cw;
     in.nnodes = b - a;
     return in;
 }
@@ -353,7 +374,8 @@ void step_fwd(const Ctx &c, int s0, int nb, const State &in, const State &out, i
         a.Q = src.Q;
         a.n = n;
         Timed tm(c.pl, c.st, FWI_KC_FWD_STEP, true);
-        launch_fused_fwd(g, p->pml, c.m.K, p->sweep_tabs, p->S, p->sweep, a, c.st, tm.b, tm.e);
+        launch_fused_fwd(g, c.tb.pml, c.m.K, c.tb.sweep_tabs, p->S, p->sweep, a, c.st, tm.b,
+                         tm.e);
     }
 }
 
@@ -374,7 +396,7 @@ void step_fwd2(const Ctx &c, int s0, int nb, const State &in, Fld mid, const Sta
     a.Q = src_of(c, s0).Q;
     a.n = n;
     Timed tm(c.pl, c.st, FWI_KC_FWD_PAIR, true);
-    launch_fused_fwd2(g, p->pml, c.m.K, p->sweep_tabs, p->S, p->sweep2, a, c.st, tm.b, tm.e);
+    launch_fused_fwd2(g, c.tb.pml, c.m.K, c.tb.sweep_tabs, p->S, p->sweep2, a, c.st, tm.b, tm.e);
 }
 
 // One adjoint step n for shots [s0, s0+nb): injects R^T r^n into `in`, then
@@ -412,7 +434,8 @@ void step_adj(const Ctx &c, int s0, int nb, const State &in, const State &out, F
         a.gpart = gpart;
         a.n = n;
         Timed tm(c.pl, c.st, FWI_KC_ADJ_STEP, true);
-        launch_fused_adj(g, p->pml, c.m.K, p->sweep_tabs, p->S, p->sweep, a, c.st, tm.b, tm.e);
+        launch_fused_adj(g, c.tb.pml, c.m.K, c.tb.sweep_tabs, p->S, p->sweep, a, c.st, tm.b,
+                         tm.e);
     }
 }
 
@@ -439,13 +462,13 @@ void step_adj2(const Ctx &c, int s0, int nb, const State &in, const State &out, 
     a.lvl = (unsigned)((const char *)pn.p - (const char *)pm.p);
     (void)pn1;   // the level after pn, lvl bytes further (checked at plan creation)
     a.gpart = gpart;
-    a.zpad = p->zpad;
-    a.injwin = p->inj_win;
-    a.injcol = p->inj_col;
+    a.zpad = c.tb.zpad;
+    a.injwin = c.tb.inj_win;
+    a.injcol = c.tb.inj_col;
     a.injacc = acc;
     a.n = n;
     Timed tm(c.pl, c.st, FWI_KC_ADJ_PAIR, true);
-    launch_fused_adj2(g, p->pml, c.m.K, p->S, p->sweep_a2, a, c.st, tm.b, tm.e);
+    launch_fused_adj2(g, c.tb.pml, c.m.K, p->S, p->sweep_a2, a, c.st, tm.b, tm.e);
 }
 
 void zero_state(const Ctx &c, float *base, int nb)
@@ -648,16 +671,67 @@ Ctx make_ctx(fwi_plan *p, void *ws, void *stream, int op)
     c.st = (hipStream_t)stream;
     c.ws = (char *)ws;
     c.L = layout(p, op);
-    c.t = pml_tables(p);
+    if (op != FWI_OP_MISFIT) {
+        char *b = c.ws + c.L.tab;
+        const fwi_plan::TabOff &o = p->to;
+        c.tb.pml = (float *)(b + o.pml);
+        c.tb.zpad = (float *)(b + o.zpad);
+        c.tb.sweep_tabs = (SweepTables *)(b + o.st);
+        c.tb.src_ij = (int2 *)(b + o.sij);
+        c.tb.src_w = (float4 *)(b + o.sw);
+        c.tb.rec_idx = (long long *)(b + o.ri);
+        c.tb.rec_w = (float4 *)(b + o.rw);
+        c.tb.inj_node = (long long *)(b + o.in);
+        c.tb.inj_shot = (int *)(b + o.is);
+        c.tb.inj_cptr = (int *)(b + o.ip);
+        c.tb.inj_crec = (int *)(b + o.ir);
+        c.tb.inj_cw = (float *)(b + o.iw);
+        c.tb.inj_win = (unsigned *)(b + o.win);
+        c.tb.inj_col = (int *)(b + o.col);
+        c.t = pml_tables(p, c.tb.pml);
+    }
     c.m.K = c.f(c.L.Kpad);
     c.m.bx = c.f(c.L.bx);
     c.m.bz = c.f(c.L.bz);
     return c;
 }
 
+__global__ void k_sweep_tables(SweepTables *T, const int2 *ij, const float4 *w, int nt)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        T->src_ij = ij;
+        T->src_w = w;
+        T->nt = nt;
+    }
+}
+
+// Puts the plan's tables into the call's workspace: the geometry tables
+// copied from the plan's host image (immutable while the plan lives, so the
+// copy may complete after this returns), the damping tables and the
+// source-table record of the batched kernels built on the device.
+void upload_tables(const Ctx &c)
+{
+    fwi_plan *p = c.pl;
+    const fwi_grid &G = p->grid;
+    Timed tm(c.pl, c.st, FWI_KC_OTHER);
+    (void)hipMemcpyAsync(c.ws + c.L.tab + p->to.blob, p->blob.data(), p->blob.size(),
+                         hipMemcpyHostToDevice, c.st);
+    // the plan keeps blob until this copy has run (fwi_plan_destroy)
+    if (!p->blob_ev)
+        (void)hipEventCreateWithFlags(&p->blob_ev, hipEventDisableTiming);
+    if (p->blob_ev)
+        (void)hipEventRecord(p->blob_ev, c.st);
+    launch_pml_tables(p->geo, G.vmax, G.npml > 0 ? G.pml_r : 0.5, G.dx, G.dz, G.dt, c.tb.pml,
+                      c.st);
+    launch_ztab_pad(p->geo, c.tb.pml, c.tb.zpad, c.st);
+    hipLaunchKernelGGL(k_sweep_tables, dim3(1), dim3(64), 0, c.st, c.tb.sweep_tabs,
+                       (const int2 *)c.tb.src_ij, (const float4 *)c.tb.src_w, G.nt);
+}
+
 void prepare(const Ctx &c, int param, const float *m1, const float *m2, const float *wavelet)
 {
     const fwi_plan *p = c.pl;
+    upload_tables(c);
     Timed tm(c.pl, c.st, FWI_KC_OTHER);
     launch_prep_model(p->geo, param, m1, m2, c.f(c.L.Kphys), c.f(c.L.rhophys), c.f(c.L.Kpad),
                       c.f(c.L.bx), c.f(c.L.bz), c.st);
@@ -768,6 +842,30 @@ namespace {
 
 constexpr int kMaxDevices = 64;
 std::mutex g_scratch_mu;
+
+// Host tables of destroyed plans whose last copy into a workspace was still
+// queued, with the event that marks its completion.
+struct Retired {
+    std::vector<char> blob;
+    hipEvent_t ev;
+};
+std::mutex g_retired_mu;
+std::vector<Retired> g_retired;
+
+void sweep_retired()
+{
+    std::lock_guard<std::mutex> lock(g_retired_mu);
+    for (size_t k = 0; k < g_retired.size();) {
+        if (hipEventQuery(g_retired[k].ev) == hipErrorNotReady) {
+            ++k;
+            continue;
+        }
+        (void)hipEventDestroy(g_retired[k].ev);
+        g_retired[k] = std::move(g_retired.back());
+        g_retired.pop_back();
+    }
+    (void)hipGetLastError();
+}
 float *g_scratch_ptr[kMaxDevices];
 
 // Address of `scratch` on the current device.
@@ -875,6 +973,7 @@ fwi_status fwi_plan_create(const fwi_grid *grid, const fwi_acq *acq, const fwi_e
         return fail(FWI_EINVAL, "adj_two_step_lane_cols %d not supported (1, 2)",
                     ex.adj_two_step_lane_cols);
 
+    sweep_retired();
     fwi_plan *p = new fwi_plan();
     p->grid = G;
     p->S = acq->nshots;
@@ -892,8 +991,10 @@ fwi_status fwi_plan_create(const fwi_grid *grid, const fwi_acq *acq, const fwi_e
     g.dt = (float)G.dt;
     g.N = Nz * Nx;
     g.Npml = 2LL * G.npml * Nx + (Nz - 2LL * G.npml) * 2 * G.npml;
-    p->SS = align64(3 * g.N + g.Npml);
-    p->ST = align64(g.N + g.Npml);
+    // record strides 4 KB longer than the records (consecutive shots' fields
+    // do not fall on the same offsets modulo large powers of two)
+    p->SS = align64(3 * g.N + g.Npml) + 1024;
+    p->ST = align64(g.N + g.Npml) + 1024;
     {
         // defaults (from decomposition sweeps on MI355X): up to four shots per
         // wave, one column per lane, bands short enough for about 4096
@@ -1118,84 +1219,54 @@ fwi_status fwi_plan_create(const fwi_grid *grid, const fwi_acq *acq, const fwi_e
         delete p;
         return fail(FWI_EDEVICE, "no HIP device");
     }
-    // one device allocation for all tables
+    // the tables' layout in a workspace's table region: the damping tables
+    // and the batched kernels' source-table record are built there by each
+    // call, the rest is copied from the host image `blob`
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t o = off;
         off = align_up(off + std::max<size_t>(bytes, 1), kAlign);
         return o;
     };
-    size_t o_pml = take(sizeof(float) * (4 * g.Nx + 4 * g.Nz));
-    size_t o_sij = take(sizeof(int2) * S), o_sw = take(sizeof(float4) * S);
-    size_t o_ri = take(sizeof(long long) * rec_idx.size()), o_rw = take(sizeof(float4) * rec_w.size());
-    size_t o_in = take(sizeof(long long) * inj_node.size());
-    size_t o_is = take(sizeof(int) * inj_shot.size());
-    size_t o_ip = take(sizeof(int) * inj_cptr.size());
-    size_t o_ir = take(sizeof(int) * inj_crec.size());
-    size_t o_iw = take(sizeof(float) * inj_cw.size());
-    size_t o_st = take(sizeof(SweepTables));
-    size_t o_win = take(sizeof(unsigned) * inj_win.size());
-    size_t o_zpad = take(sizeof(float) * 4 * (g.Nz + 2 * kZPad));
-    size_t o_col = take(sizeof(int) * inj_col.size());
-    if (hipMalloc(&p->dev, off) != hipSuccess) {
-        (void)hipGetLastError();
+    fwi_plan::TabOff &o = p->to;
+    o.pml = take(sizeof(float) * (4 * g.Nx + 4 * g.Nz));
+    o.zpad = take(sizeof(float) * 4 * (g.Nz + 2 * kZPad));
+    o.st = take(sizeof(SweepTables));
+    o.blob = off;
+    o.sij = take(sizeof(int2) * S);
+    o.sw = take(sizeof(float4) * S);
+    o.ri = take(sizeof(long long) * rec_idx.size());
+    o.rw = take(sizeof(float4) * rec_w.size());
+    o.in = take(sizeof(long long) * inj_node.size());
+    o.is = take(sizeof(int) * inj_shot.size());
+    o.ip = take(sizeof(int) * inj_cptr.size());
+    o.ir = take(sizeof(int) * inj_crec.size());
+    o.iw = take(sizeof(float) * inj_cw.size());
+    o.win = take(sizeof(unsigned) * inj_win.size());
+    o.col = take(sizeof(int) * inj_col.size());
+    o.bytes = off;
+    try {
+        p->blob.assign(off - o.blob, 0);
+    } catch (const std::bad_alloc &) {
         delete p;
-        return fail(FWI_ENOMEM, "device allocation of %zu bytes for plan tables failed", off);
+        return fail(FWI_ENOMEM, "host allocation of %zu bytes for plan tables failed",
+                    off - o.blob);
     }
-    char *d = (char *)p->dev;
-    p->pml = (float *)(d + o_pml);
-    p->src_ij = (int2 *)(d + o_sij);
-    p->src_w = (float4 *)(d + o_sw);
-    p->rec_idx = (long long *)(d + o_ri);
-    p->rec_w = (float4 *)(d + o_rw);
-    p->inj_node = (long long *)(d + o_in);
-    p->inj_shot = (int *)(d + o_is);
-    p->inj_cptr = (int *)(d + o_ip);
-    p->inj_crec = (int *)(d + o_ir);
-    p->inj_cw = (float *)(d + o_iw);
-    p->sweep_tabs = (SweepTables *)(d + o_st);
-    p->inj_win = (unsigned *)(d + o_win);
-    p->zpad = (float *)(d + o_zpad);
-    p->inj_col = (int *)(d + o_col);
-    SweepTables st_host;
-    st_host.src_ij = p->src_ij;
-    st_host.src_w = p->src_w;
-    st_host.nt = G.nt;
-    // uploads and the table kernel run on a private stream, and only that
-    // stream is waited for: work other streams have in flight (a server
-    // creating plans while earlier requests run) is not drained
-    hipStream_t ps = nullptr;
-    bool ok = hipStreamCreateWithFlags(&ps, hipStreamNonBlocking) == hipSuccess;
-    auto up = [&](void *dst, const void *src, size_t bytes) {
-        if (ok && bytes && hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, ps) != hipSuccess)
-            ok = false;
+    auto put = [&](size_t at, const void *src, size_t bytes) {
+        if (bytes)
+            std::memcpy(p->blob.data() + (at - o.blob), src, bytes);
     };
-    up(p->src_ij, p->h_src_ij.data(), sizeof(int2) * S);
-    up(p->src_w, p->h_src_w.data(), sizeof(float4) * S);
-    up(p->rec_idx, rec_idx.data(), sizeof(long long) * rec_idx.size());
-    up(p->rec_w, rec_w.data(), sizeof(float4) * rec_w.size());
-    up(p->inj_node, inj_node.data(), sizeof(long long) * inj_node.size());
-    up(p->inj_shot, inj_shot.data(), sizeof(int) * inj_shot.size());
-    up(p->inj_cptr, inj_cptr.data(), sizeof(int) * inj_cptr.size());
-    up(p->inj_crec, inj_crec.data(), sizeof(int) * inj_crec.size());
-    up(p->inj_cw, inj_cw.data(), sizeof(float) * inj_cw.size());
-    up(p->sweep_tabs, &st_host, sizeof(SweepTables));
-    up(p->inj_win, inj_win.data(), sizeof(unsigned) * inj_win.size());
-    up(p->inj_col, inj_col.data(), sizeof(int) * inj_col.size());
-    if (ok)
-        launch_pml_tables(g, G.vmax, G.npml > 0 ? G.pml_r : 0.5, G.dx, G.dz, G.dt, p->pml, ps);
-    if (ok)
-        launch_ztab_pad(g, p->pml, p->zpad, ps);
-    if (ok && (hipGetLastError() != hipSuccess || hipStreamSynchronize(ps) != hipSuccess))
-        ok = false;
-    if (ps)
-        (void)hipStreamDestroy(ps);
-    if (!ok) {
-        (void)hipGetLastError();
-        (void)hipFree(p->dev);
-        delete p;
-        return fail(FWI_EDEVICE, "uploading plan tables failed");
-    }
+    put(o.sij, p->h_src_ij.data(), sizeof(int2) * S);
+    put(o.sw, p->h_src_w.data(), sizeof(float4) * S);
+    put(o.ri, rec_idx.data(), sizeof(long long) * rec_idx.size());
+    put(o.rw, rec_w.data(), sizeof(float4) * rec_w.size());
+    put(o.in, inj_node.data(), sizeof(long long) * inj_node.size());
+    put(o.is, inj_shot.data(), sizeof(int) * inj_shot.size());
+    put(o.ip, inj_cptr.data(), sizeof(int) * inj_cptr.size());
+    put(o.ir, inj_crec.data(), sizeof(int) * inj_crec.size());
+    put(o.iw, inj_cw.data(), sizeof(float) * inj_cw.size());
+    put(o.win, inj_win.data(), sizeof(unsigned) * inj_win.size());
+    put(o.col, inj_col.data(), sizeof(int) * inj_col.size());
     *out = p;
     return FWI_OK;
 }
@@ -1207,8 +1278,15 @@ void fwi_plan_destroy(fwi_plan *p)
     (void)collect_marks(p);
     for (hipEvent_t e : p->spare)
         (void)hipEventDestroy(e);
-    if (p->dev)
-        (void)hipFree(p->dev);
+    sweep_retired();
+    if (p->blob_ev && hipEventQuery(p->blob_ev) == hipErrorNotReady) {
+        // a copy of the tables may still be queued: keep them until it ran
+        std::lock_guard<std::mutex> lock(g_retired_mu);
+        g_retired.push_back({std::move(p->blob), p->blob_ev});
+    } else if (p->blob_ev) {
+        (void)hipEventDestroy(p->blob_ev);
+    }
+    (void)hipGetLastError();
     delete p;
 }
 

@@ -109,7 +109,9 @@ class GradientServer:
 
     def plan_for(self, q):
         """The request's plan: whole history if it fits a slot's share of
-        the budget, else sqrt(nt) checkpoints (unless plan_kw fixes it)."""
+        the budget, else sqrt(nt) checkpoints (unless plan_kw fixes it).
+        Plans hold host memory only, so making one (and dropping the
+        whole-history one) never waits for the device."""
         plan = Plan(q.grid, q.src_xz, q.rec_xz, device=self.device, **self.plan_kw)
         if "ckpt_every" not in self.plan_kw and \
                 footprint(plan, q) > self.budget / self.max_slots:
@@ -157,7 +159,6 @@ class GradientServer:
         free_streams = list(self.streams)
         used = 0
         results = []
-        retired = []    # plans of finished jobs, released when the device is idle
         t0 = time.perf_counter()
         while pending or waiting or running:
             now = time.perf_counter() - t0
@@ -195,13 +196,11 @@ class GradientServer:
                     used -= job.footprint
                     job.bufs = None
                     job.plan.release_workspace()
-                    retired.append(job.plan)
+                    job.plan = None
                     progressed = True
                     if verbose:
                         print(f"  req {res.id:3d} done: latency {res.latency * 1e3:9.1f} ms "
                               f"(queued {(res.admitted - res.arrival) * 1e3:8.1f} ms)", flush=True)
-            if not running and retired:
-                retired.clear()     # destroying a plan frees device memory (synchronizing)
             if not progressed:
                 time.sleep(2e-4)
         torch.cuda.synchronize(self.device)

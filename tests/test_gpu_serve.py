@@ -89,3 +89,36 @@ def test_served_result_matches_oracle(env):
     assert abs(r.J - J) <= 1e-4 * kappa * J
     assert maxrel(r.g1.cpu().numpy(), e1) <= 1e-4 * kappa
     assert maxrel(r.g2.cpu().numpy(), e2) <= 1e-4 * kappa
+
+
+def test_plan_creation_does_not_wait_for_the_device(env):
+    """A request that takes the checkpoint branch arrives while another
+    request's gradient runs: making its plans (the whole-history one it
+    discards, then the checkpointed one) and dropping them must not wait for
+    the running work, so the serving loop keeps admitting and retiring."""
+    torch, serve = env
+    from paper_1804_01184_amd import workloads as W
+    from paper_1804_01184_amd.api import Grid, Plan
+    q = serve.make_requests(_specs(1, seed=9), nrec=48, npml=12)[0]
+    fp_full = serve.footprint(Plan(q.grid, q.src_xz, q.rec_xz), q)
+    big = W.gauss_problem(301, 32, 120, 4000, npml=30, seed=41)
+    dev = torch.device("cuda")
+    f = torch.tensor(big.wavelet(), dtype=torch.float32, device=dev)
+    p_big = Plan(Grid.of(big), big.src_xz, big.rec_xz, ckpt_every=63)
+    m1 = torch.tensor(big.vp_start, dtype=torch.float32, device=dev)
+    m2 = torch.tensor(big.rho_start, dtype=torch.float32, device=dev)
+    obs = torch.zeros(p_big._traces_shape(), device=dev)
+    p_big.workspace(2)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    done = torch.cuda.Event()
+    with torch.cuda.stream(s):
+        p_big.gradient("vp-rho", m1, m2, f, obs, stream=s)   # about 0.3 s of work
+        done.record(s)
+    srv = serve.GradientServer(max_slots=2, hbm_budget=int(1.5 * fp_full))
+    plan = srv.plan_for(q)                 # the checkpoint branch
+    assert plan.info["ckpt_every"] < q.grid.nt
+    del plan
+    running = not done.query()
+    torch.cuda.synchronize()
+    assert running, "making or dropping a plan waited for the device"
