@@ -145,7 +145,9 @@ def measured_traffic(kernel, decomposition, traffic_file=TRAFFIC_FILE, source=KE
             sha = hashlib.sha256(fh.read()).hexdigest()
     except (OSError, ValueError):
         return None
-    k = prof.get("kernels", {}).get(kernel)
+    # entries are keyed "<kernel class>@<workload>" (or by the class alone)
+    kern = prof.get("kernels", {})
+    k = kern.get(f"{kernel}@{decomposition.get('workload')}", kern.get(kernel))
     if prof.get("source_sha256") != sha or k is None or k.get("decomposition") != decomposition:
         return None
     return int(k["bytes_per_launch"])
@@ -449,6 +451,16 @@ def main():
                 "gradient_bytes_per_cell_step": round(ab["gradient_per_cell"], 2),
                 "gradient_roof_gcells": round(PEAK_HBM_GBS / ab["gradient_per_cell"], 1),
                 "pml_fraction": round(ab["pml_fraction"], 4)}
+            tr = roof_all[kc]["traffic"]
+            if tr:
+                # what the kernel moves (counters) at this launch time
+                roof_all[kc]["traffic_achieved"] = round(tr / avg_s / 1e9, 1)
+                roof_all[kc]["traffic_frac"] = round(tr / avg_s / 1e9 / PEAK_HBM_GBS, 4)
+            if kc.endswith("_pair"):
+                roof_all[kc]["note"] = (
+                    "two time steps per launch: the state between them stays on chip, so "
+                    "the per-cell-step algorithmic bytes include bytes this kernel never "
+                    "moves (traffic is what it moves)")
         if roof_all:
             roof = roof_all[max(roof_all, key=lambda k: roof_all[k]["total_ms"])]
     classes = {k: {"launches": v[0], "ms": round(v[1], 3)} for k, v in per_class.items()

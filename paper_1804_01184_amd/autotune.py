@@ -27,10 +27,11 @@ from .api import Grid, Plan
 
 # band heights: every height from 8 to 16 (the kernels are bounded per CU,
 # so how evenly the workgroups of a height spread over the CUs matters as
-# much as the height), then coarser steps
+# much as the height), then coarser steps.  Each is lowered to the smallest
+# height with the same number of bands (see balanced_rows).
 ROWS = (8, 9, 10, 11, 12, 13, 14, 15, 16, 20, 24, 32, 48, 64, 96, 128)
 ROWS2 = (12, 14, 16, 18, 20, 24, 28, 32, 48, 64, 96)
-ROWSA = (12, 16, 20, 24, 32, 48, 64, 96, 128, 192, 256)
+ROWSA = (12, 16, 20, 24, 32, 48, 64, 96, 128, 160, 192, 256)
 # supported (shots per group, columns per lane) pairs of the one-step
 # kernels and of the two-step forward kernel
 PAIRS = ((1, 1), (2, 1), (4, 1), (8, 1), (1, 2), (2, 2), (4, 2), (1, 4), (2, 4))
@@ -54,7 +55,7 @@ def cache_path():
 
 
 def _key(Nz, Nx, S, npml, arch):
-    return f"{arch}:{Nz}x{Nx}:S{S}:pml{npml}:v5"
+    return f"{arch}:{Nz}x{Nx}:S{S}:pml{npml}:v6"
 
 
 def _arch():
@@ -69,8 +70,19 @@ def _waves(Nz, Nx, S, H, spg, cols, steps):
     return strips * -(-Nz // H) * -(-S // spg)
 
 
+def balanced_rows(Nz, H):
+    """The smallest band height giving as many bands of Nz rows as H does.
+    A launch of a few rounds of waves lasts about as long as its tallest
+    band, so with the band count fixed the last band should not be the
+    short one: over 1081 rows, 192-row bands leave a last band of 121 rows
+    and take as long as 181-row bands would with all six nearly equal."""
+    bands = -(-Nz // H)
+    return -(-Nz // bands)
+
+
 def _triples(Nz, Nx, S, pairs, rows, steps):
     out = []
+    rows = sorted({balanced_rows(Nz, H) for H in rows})
     for spg, cols in pairs:
         if spg > 1 and spg > 2 * S:
             continue
@@ -236,4 +248,5 @@ def tuned_plan(grid: Grid, src_xz, rec_xz, **kw):
     return Plan(grid, src_xz, rec_xz, **{**best, **kw})
 
 
-__all__ = ["tune", "tuned_plan", "candidates", "candidates2", "candidates_adj2", "measure"]
+__all__ = ["tune", "tuned_plan", "candidates", "candidates2", "candidates_adj2", "measure",
+           "balanced_rows"]

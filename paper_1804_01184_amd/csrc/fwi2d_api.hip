@@ -35,6 +35,13 @@ fwi_status fail(fwi_status s, const char *fmt, ...)
 constexpr size_t kAlign = 256;
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 inline long long align64(long long v) { return (v + 63) / 64 * 64; }
+// the smallest band height giving as many bands of Nz rows as H does: a
+// launch of a few rounds of waves lasts about as long as its tallest band
+inline int balanced_rows(long long Nz, int H)
+{
+    const long long bands = (Nz + H - 1) / H;
+    return (int)((Nz + bands - 1) / bands);
+}
 
 // Stability limit of the fourth-order staggered leapfrog scheme in 2-D:
 // vmax dt sqrt(1/dx^2 + 1/dz^2) (|c1| + |c2|) <= 1.
@@ -1012,7 +1019,8 @@ fwi_status fwi_plan_create(const fwi_grid *grid, const fwi_acq *acq, const fwi_e
             Sweep one = sweep_of(g, p->S, (int)Nz, spg, cols);
             long long per_band = (long long)one.nstrips * one.ngroups;
             long long bands = std::max<long long>(1, (4096 + per_band - 1) / per_band);
-            H = (int)std::min<long long>(64, std::max<long long>(8, (Nz + bands - 1) / bands));
+            H = balanced_rows(Nz, (int)std::min<long long>(64, std::max<long long>(
+                                      8, (Nz + bands - 1) / bands)));
         }
         p->sweep = sweep_of(g, p->S, H, spg, cols);
         p->Spad = p->mode == FWI_EXEC_PLAIN ? p->S : p->sweep.ngroups * spg;
@@ -1030,7 +1038,8 @@ fwi_status fwi_plan_create(const fwi_grid *grid, const fwi_acq *acq, const fwi_e
             Sweep one = sweep_of(g, p->Spad, (int)Nz, spg2, cols2, 2);
             long long per_band = (long long)one.nstrips * one.ngroups;
             long long bands = std::max<long long>(1, (8192 + per_band - 1) / per_band);
-            H2 = (int)std::min<long long>(96, std::max<long long>(16, (Nz + bands - 1) / bands));
+            H2 = balanced_rows(Nz, (int)std::min<long long>(96, std::max<long long>(
+                                       16, (Nz + bands - 1) / bands)));
         }
         p->sweep2 = sweep_of(g, p->Spad, H2, spg2, cols2, 2);
         p->two_step = p->mode != FWI_EXEC_PLAIN && ex.two_step != 1 && p->Spad % spg2 == 0 &&
@@ -1059,7 +1068,8 @@ fwi_status fwi_plan_create(const fwi_grid *grid, const fwi_acq *acq, const fwi_e
             Sweep one = sweep_of(g, p->Spad, (int)Nz, spg, ca, 2);
             long long per_band = (long long)one.nstrips * one.ngroups;
             long long bands = std::max<long long>(1, (4096 + per_band - 1) / per_band);
-            Ha = (int)std::min<long long>(128, std::max<long long>(16, (Nz + bands - 1) / bands));
+            Ha = balanced_rows(Nz, (int)std::min<long long>(128, std::max<long long>(
+                                       16, (Nz + bands - 1) / bands)));
         }
         p->sweep_a2 = sweep_of(g, p->Spad, Ha, spg, ca, 2);
         if (p->mode != FWI_EXEC_PLAIN &&

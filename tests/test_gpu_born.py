@@ -317,14 +317,23 @@ def test_amplitude_descent_matches_oracle_loop(env):
                                                                      w.rho0)), qo)[0]
 
         ref = OI.descend(grad_fn, value_fn, np.ones(1), np.ones(1), 3)
-        # J falls by more than 10^3 over the first two steps, and the
-        # parabola takes its curvature from a difference of FP32 misfits:
-        # the later steps and misfits agree to a few 1e-3 (the bound of the
-        # scheme-III loop test)
-        np.testing.assert_allclose(res.J, ref["J"], rtol=5e-3)
-        np.testing.assert_allclose(res.alpha, ref["alpha"], rtol=5e-3)
+        # J = |r|^2 / 2 with r = d - q.  A data error delta with
+        # |delta| <= eps |q| (eps = 1e-4, the data bound above; J0 = |q|^2 / 2
+        # at zero contrast) moves J by at most |r| |delta|, so
+        #   |J~ - J| / J <= 2 eps sqrt(J0 / J):
+        # the relative error grows as J falls (J falls by more than 10^3 over
+        # two steps).  A step length is a parabola through misfits of the
+        # size of the J it starts from, so it carries the same relative
+        # error.  Measured: J within 1.6e-3 where sqrt(J0 / J) = 53 (bound
+        # 1.1e-2), steps within 6e-4, amplitudes within 5e-5.
+        Jr = np.asarray(ref["J"])
+        bound = 2 * 1e-4 * np.sqrt(Jr[0] / Jr)
+        assert len(res.J) == len(Jr)
+        assert np.all(np.abs(np.asarray(res.J) - Jr) <= bound * Jr), (res.J, Jr)
+        ar = np.asarray(ref["alpha"])
+        assert np.all(np.abs(np.asarray(res.alpha) - ar) <= bound[:len(ar)] * np.abs(ar))
         np.testing.assert_allclose([float(res.m1[0]), float(res.m2[0])],
-                                   [ref["m1"][0] - 1.0, ref["m2"][0] - 1.0], rtol=5e-3, atol=1e-6)
+                                   [ref["m1"][0] - 1.0, ref["m2"][0] - 1.0], rtol=1e-3, atol=1e-6)
 
 
 def test_point_scatterer_amplitudes_are_recovered(env):

@@ -26,6 +26,27 @@ def test_candidates_cover_rows_shot_groups_and_lane_widths():
         assert 512 <= waves <= 65536
 
 
+def test_candidate_band_heights_are_balanced():
+    # every candidate height is the smallest one with its band count, so the
+    # last band is at most one row per band shorter than the others
+    from paper_1804_01184_amd import autotune
+    assert autotune.balanced_rows(1081, 192) == 181
+    assert autotune.balanced_rows(1081, 181) == 181
+    assert autotune.balanced_rows(2081, 128) == 123
+    assert autotune.balanced_rows(481, 481) == 481
+    assert autotune.balanced_rows(7, 1) == 1
+    for Nz in (9, 481, 1081, 2081):
+        for H in range(1, Nz + 1, 7):
+            b = -(-Nz // H)
+            h = autotune.balanced_rows(Nz, H)
+            assert h <= H and -(-Nz // h) == b and (h == 1 or -(-Nz // (h - 1)) > b)
+            assert Nz - (b - 1) * h >= h - b + 1
+    for fn in (autotune.candidates, autotune.candidates2, autotune.candidates_adj2):
+        for Nz, S in ((481, 40), (1081, 64), (2081, 32)):
+            for H, _, _ in fn(Nz, Nz, S):
+                assert autotune.balanced_rows(Nz, H) == H
+
+
 def test_workloads_seeded_and_shaped():
     a, b = W.gauss401(), W.gauss401()
     np.testing.assert_array_equal(a.vp_true, b.vp_true)
