@@ -13,7 +13,8 @@ value = padded cells x time steps x shots / seconds per step
 (Gcell-updates/s; each cell-step counted once although the forward,
 recompute and adjoint sweeps all touch it).
 
-Beside the timed steps: the plain path (one shot per launch) on the same
+Beside the timed steps: the forward-only modelling rate (traces of every
+shot, nothing kept), the plain path (one shot per launch) on the same
 workload, a served stream of gradient requests of mixed sizes (p50 / p99
 latency and aggregate rate), and the FP64 oracle on a sample of the
 workload on the host cores.
@@ -59,6 +60,8 @@ def parse():
                          "one (the tuner also runs unless a decomposition is given)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-forward", action="store_true",
+                    help="no forward-only modelling leg")
     ap.add_argument("--cpu-steps", type=int, default=0,
                     help="time steps of the CPU sample (default: all of the workload's)")
     ap.add_argument("--cpu-shots", type=int, default=1, help="shots of the CPU sample")
@@ -483,6 +486,25 @@ def main():
                 "ms_per_step": round(tc * 1e3, 2)}
         del pc
 
+    # forward-only modelling (traces of every shot, no pressure kept), the
+    # same batched kernels; forward-only algorithmic bytes 24 + 8 fp + 8/S
+    fwd_only = None
+    if not args.no_forward:
+        tr = torch.empty(plan._traces_shape(), dtype=torch.float32, device=dev)
+        plan.forward("k-rho", K0, r0, f, traces=tr)          # warm
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(2):
+            plan.forward("k-rho", K0, r0, f, traces=tr)
+        torch.cuda.synchronize()
+        tf = (time.perf_counter() - t) / 2
+        b_fwd = 24 + 8 * ab["pml_fraction"] + 8 / S
+        fwd_only = {"value": round(cells / tf / 1e9, 3), "ms_per_forward": round(tf * 1e3, 2),
+                    "bytes_per_cell_step": round(b_fwd, 3),
+                    "roof_gcells": round(PEAK_HBM_GBS / b_fwd, 1),
+                    "frac_of_roof": round(cells / tf / 1e9 / (PEAK_HBM_GBS / b_fwd), 4)}
+        del tr
+
     plain = None
     if not args.no_plain:
         print("bench: plain path (one shot per launch)", file=sys.stderr, flush=True)
@@ -538,6 +560,7 @@ def main():
         "roofline_by_kernel": roof_all,
         "kernels": classes,
         "checkpointed": ckpt,
+        "forward_only": fwd_only,
         "plain": plain,
         "serve": served,
         "cpu_baseline": cpu,

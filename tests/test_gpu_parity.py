@@ -186,15 +186,21 @@ def test_two_step_forward_and_adjoint(api, small, rows, spg, cols, ckpt):
     assert maxrel(gr.cpu().numpy(), small.gr) <= TOL
 
 
-def test_two_step_matches_one_step_bitwise(api, small):
+@pytest.mark.parametrize("spg,cols", [(1, 1), (2, 1), (1, 2), (2, 2), (1, 4)])
+def test_two_step_matches_one_step_bitwise(api, small, spg, cols):
     """The two-step kernel performs exactly the operations of two one-step
     launches: traces and gradients agree bitwise, with full history and with
-    checkpoints (where pairs stop at checkpoint levels)."""
+    checkpoints (where pairs stop at checkpoint levels), in every shot-group
+    and lane-width combination (band heights not a multiple of the row
+    loop's four phases)."""
     w = small.w
     out = {}
     for ts in (1, 2):
         for k in (0, 7):
-            p = api.Plan(agrid(api, w), w.src_xz, w.rec_xz, two_step=ts, ckpt_every=k)
+            p = api.Plan(agrid(api, w), w.src_xz, w.rec_xz, two_step=ts, ckpt_every=k,
+                         two_step_band_rows=17 + 6 * spg, two_step_shots_per_group=spg,
+                         two_step_lane_cols=cols)
+            assert p.info["two_step"] == ts - 1
             tr = p.forward("k-rho", small.K0, small.r0, small.f).cpu().numpy()
             g = [x.cpu().numpy() for x in p.adjoint("k-rho", small.K0, small.r0, small.f,
                                                     small.adj)]
