@@ -10,7 +10,7 @@
  *  - The operator (section "Modelling and Inversion"): the 2-D variable
  *    density acoustic equation with bulk modulus K and density rho.  Scheme
  *    III solves it in the time domain with a staggered-grid finite-difference
- *    code, with absorbing boundaries on all sides, for the forward and the
+ *    code, absorbing at every edge of the grid, for the forward and the
  *    adjoint wavefields.  Spatial order, staggering, boundary type, source
  *    injection and sampling are not given; the readings used here:
  *      * fourth-order staggered space derivatives, second-order leapfrog time;
