@@ -61,6 +61,8 @@ struct fwi_plan {
     Sweep sweep;   // batched decomposition (band rows, shots per group)
     bool two_step = false;   // forward sweeps use the two-step kernel
     Sweep sweep2;            // its decomposition
+    bool samp_nodes = false; // its intermediate level, when only sampled, is
+                             // kept at the receiver nodes alone
     bool adj2 = false;       // adjoint sweeps use the two-step kernel
     Sweep sweep_a2;          // its decomposition (shots per group of `sweep`)
     int device;
@@ -73,6 +75,7 @@ struct fwi_plan {
     struct TabOff {
         size_t pml, zpad, st;                            // built on the device
         size_t sij, sw, ri, rw, in, is, ip, ir, iw, win, col; // copied from blob
+        size_t swin, rnode;                              // copied from blob
         size_t blob;                                     // offset of blob's image
         size_t bytes;                                    // size of the region
     } to{};
@@ -166,6 +169,7 @@ struct Layout {
     size_t ckpt, store, gpart, fold, traces, resid, partials;
     size_t mid;   // p^{n+1} of a two-step launch outside the stored history
     size_t injacc;   // R^T r^{n-1} per injection node (two-step adjoint)
+    size_t nodes;    // p^{n+1} at the receiver nodes (two-step forward, level only sampled)
     size_t total;
 };
 
@@ -210,6 +214,8 @@ Layout layout(const fwi_plan *p, int op)
     L.work[1] = take((size_t)B * p->SS);
     if (p->two_step)
         L.mid = take((size_t)B * p->ST);
+    if (p->samp_nodes)
+        L.nodes = take((size_t)std::max(p->inj_nodes, 1));
     if (op == FWI_OP_GRADIENT) {
         L.lam[0] = take((size_t)B * p->SS);
         L.lam[1] = take((size_t)B * p->SS);
@@ -256,6 +262,8 @@ struct DevTabs {
     float *inj_cw = nullptr;
     unsigned *inj_win = nullptr;   // two-step adjoint: [Spad][Nz + 2 kZPad][strips]
     int *inj_col = nullptr;        // grid column of each injection node
+    unsigned *samp_win = nullptr;  // two-step forward: [S][Nz][strips]
+    int4 *rec_node = nullptr;      // [S][nrec]: node index of each bilinear corner
 };
 
 struct Ctx {
@@ -389,7 +397,8 @@ void step_fwd(const Ctx &c, int s0, int nb, const State &in, const State &out, i
 // Two forward steps n -> n+2 for shots [s0, s0+nb) (batched only): `mid`
 // (a pressure record: p, then its split N floats later) receives p^{n+1},
 // `out` the state at n+2; out's velocities must not be in's.
-void step_fwd2(const Ctx &c, int s0, int nb, const State &in, Fld mid, const State &out, int n)
+void step_fwd2(const Ctx &c, int s0, int nb, const State &in, Fld mid, const State &out, int n,
+               int midw = 0)
 {
     const fwi_plan *p = c.pl;
     const Geo &g = p->geo;
@@ -401,6 +410,10 @@ void step_fwd2(const Ctx &c, int s0, int nb, const State &in, Fld mid, const Sta
     a.pout = recd(out.p, g.N + g.Npml);
     a.pmid = recd(mid, g.N + g.Npml);
     a.Q = src_of(c, s0).Q;
+    a.nodes = midw == 1 ? c.f(c.L.nodes) : nullptr;
+    a.nwin = c.tb.samp_win;
+    a.ncol = c.tb.inj_col;
+    a.midw = midw;
     a.n = n;
     Timed tm(c.pl, c.st, FWI_KC_FWD_PAIR, true);
     launch_fused_fwd2(g, c.tb.pml, c.m.K, c.tb.sweep_tabs, p->S, p->sweep2, a, c.st, tm.b, tm.e);
@@ -538,19 +551,32 @@ void sweep_forward(const Ctx &c, int s0, int nb, bool keep, float *traces)
         if (p->two_step && n + 1 < nt && !full_state(n + 1)) {
             // two steps: level n+1 only as pressure (history slot or scratch)
             std::pair<Fld, Fld> mid;
-            if (keep && n + 1 > nlast)
+            // level n+1 outside the stored history is only sampled: where
+            // the node tables exist, just its receiver nodes are kept (or
+            // nothing, without traces)
+            int midw = 0;
+            if (keep && n + 1 > nlast) {
                 mid = slot_p(n + 1);
-            else
+            } else {
                 mid = {Fld{c.f(c.L.mid), p->ST}, Fld{c.f(c.L.mid) + g.N, p->ST}};
+                if (p->samp_nodes)
+                    midw = traces ? 1 : 2;
+            }
             int cw2;
             State out = target(n + 1, cw, cw2);
             if (cw2 == cw)   // velocities of n+2 must not overwrite those of n
                 cw2 = -1;
-            step_fwd2(c, s0, nb, cur, mid.first, out, n);
-            State ms = cur;
-            ms.p = mid.first;
-            ms.pz = mid.second;
-            sample(ms, n);
+            step_fwd2(c, s0, nb, cur, mid.first, out, n, midw);
+            if (midw == 1) {
+                Timed tm(c.pl, c.st, FWI_KC_SAMPLE);
+                launch_sample_nodes(c.f(c.L.nodes), c.tb.rec_node + (size_t)s0 * p->nrec,
+                                    rec.w, p->nrec, real_shots(p, s0, nb), traces, nt, n, c.st);
+            } else {
+                State ms = cur;
+                ms.p = mid.first;
+                ms.pz = mid.second;
+                sample(ms, n);
+            }
             sample(out, n + 1);
             cur = out;
             cw = cw2;
@@ -695,6 +721,8 @@ Ctx make_ctx(fwi_plan *p, void *ws, void *stream, int op)
         c.tb.inj_cw = (float *)(b + o.iw);
         c.tb.inj_win = (unsigned *)(b + o.win);
         c.tb.inj_col = (int *)(b + o.col);
+        c.tb.samp_win = (unsigned *)(b + o.swin);
+        c.tb.rec_node = (int4 *)(b + o.rnode);
         c.t = pml_tables(p, c.tb.pml);
     }
     c.m.K = c.f(c.L.Kpad);
@@ -1224,6 +1252,69 @@ fwi_status fwi_plan_create(const fwi_grid *grid, const fwi_acq *acq, const fwi_e
             inj_win.clear();
         }
     }
+    // two-step forward: when its intermediate level is only sampled, the
+    // kernel writes just the receiver nodes of each row.  For every shot,
+    // row and strip, the range of that shot's nodes in the row whose columns
+    // the strip owns (packed as above), and for every receiver the nodes of
+    // its four bilinear corners (-1 where the weight is zero, which has no
+    // node)
+    std::vector<unsigned> samp_win;
+    std::vector<int4> rec_node;
+    if (p->two_step) {
+        const Sweep &s2 = p->sweep2;
+        const int W = strip_cols(s2.cols, 2);
+        samp_win.assign((size_t)S * g.Nz * s2.nstrips, 0u);
+        bool fits = inj_node.size() < (1u << 23);
+        for (int s = 0; s < S && fits; ++s) {
+            int k = p->shot_node_ptr[s];
+            const int kend = p->shot_node_ptr[s + 1];
+            while (k < kend && fits) {
+                const long long row = inj_node[k] / g.Nx;
+                int ke = k;
+                while (ke < kend && inj_node[ke] / g.Nx == row)
+                    ++ke;
+                for (int a0 = k; a0 < ke;) {
+                    const int st = inj_col[a0] / W;
+                    int a1 = a0;
+                    while (a1 < ke && inj_col[a1] / W == st)
+                        ++a1;
+                    if (a1 - a0 > 511) {
+                        fits = false;
+                        break;
+                    }
+                    samp_win[((size_t)s * g.Nz + row) * s2.nstrips + st] =
+                        ((unsigned)a0 << 9) | (unsigned)(a1 - a0);
+                    a0 = a1;
+                }
+                k = ke;
+            }
+        }
+        if (fits) {
+            rec_node.resize((size_t)S * nr);
+            for (int s = 0; s < S; ++s) {
+                const auto b0 = inj_node.begin() + p->shot_node_ptr[s];
+                const auto b1 = inj_node.begin() + p->shot_node_ptr[s + 1];
+                for (int r = 0; r < nr; ++r) {
+                    const long long c = rec_idx[(size_t)s * nr + r];
+                    const float4 w = rec_w[(size_t)s * nr + r];
+                    const long long cs[4] = {c, c + 1, c + g.Nx, c + g.Nx + 1};
+                    const float ws[4] = {w.x, w.y, w.z, w.w};
+                    int q4[4];
+                    for (int q = 0; q < 4; ++q) {
+                        q4[q] = -1;
+                        if (ws[q] != 0.0f) {
+                            const auto it = std::lower_bound(b0, b1, cs[q]);
+                            q4[q] = (int)(it - inj_node.begin());
+                        }
+                    }
+                    rec_node[(size_t)s * nr + r] = make_int4(q4[0], q4[1], q4[2], q4[3]);
+                }
+            }
+        } else {
+            samp_win.clear();
+        }
+        p->samp_nodes = fits;
+    }
 
     if (hipGetDevice(&p->device) != hipSuccess) {
         delete p;
@@ -1254,6 +1345,8 @@ fwi_status fwi_plan_create(const fwi_grid *grid, const fwi_acq *acq, const fwi_e
     o.iw = take(sizeof(float) * inj_cw.size());
     o.win = take(sizeof(unsigned) * inj_win.size());
     o.col = take(sizeof(int) * inj_col.size());
+    o.swin = take(sizeof(unsigned) * samp_win.size());
+    o.rnode = take(sizeof(int4) * rec_node.size());
     o.bytes = off;
     try {
         p->blob.assign(off - o.blob, 0);
@@ -1277,6 +1370,8 @@ fwi_status fwi_plan_create(const fwi_grid *grid, const fwi_acq *acq, const fwi_e
     put(o.iw, inj_cw.data(), sizeof(float) * inj_cw.size());
     put(o.win, inj_win.data(), sizeof(unsigned) * inj_win.size());
     put(o.col, inj_col.data(), sizeof(int) * inj_col.size());
+    put(o.swin, samp_win.data(), sizeof(unsigned) * samp_win.size());
+    put(o.rnode, rec_node.data(), sizeof(int4) * rec_node.size());
     *out = p;
     return FWI_OK;
 }

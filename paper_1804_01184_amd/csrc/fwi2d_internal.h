@@ -105,6 +105,10 @@ void launch_cumulative_wavelet(const float *f, int per_shot, int S, int nt, floa
                                hipStream_t st);
 void launch_sample(const Geo &g, Fld p, Fld pz, const Rec &r, int S, float *traces, int nt,
                    int n, hipStream_t st);
+// Receiver samples of one level from its receiver-node values: node indices
+// of the four bilinear corners per receiver (rnode, -1: zero weight).
+void launch_sample_nodes(const float *nodes, const int4 *rnode, const float4 *rw, int nrec,
+                         int S, float *traces, int nt, int n, hipStream_t st);
 // Samples traces[s][r][n0 + m] for m < nsteps from stored pressure levels:
 // level m of shot s at hist + m * slot_stride + s * ss.
 void launch_sample_hist(const Geo &g, const float *hist, long long slot_stride, long long ss,
@@ -206,9 +210,18 @@ struct FwdStep {
     int n;              // time step being taken (n -> n+1)
 };
 // Two forward steps n -> n+2: pmid receives p^{n+1} and its split.
+// Two forward steps n, n+1.  p^{n+1} goes to pmid (midw 0), or, when the
+// level is only sampled, just its receiver nodes go to `nodes` (midw 1:
+// nwin[(s Nz + i) nstrips + strip] packs (first << 9 | count) of the nodes
+// of shot s in row i whose columns the strip owns, ncol the grid column of
+// each node), or nothing is kept (midw 2).
 struct FwdStep2 {
     Recd vin, pin, vout, pout, pmid;
     const float *Q;
+    float *nodes;
+    const unsigned *nwin;
+    const int *ncol;
+    int midw;
     int n;
 };
 struct AdjStep {

@@ -201,6 +201,24 @@ __global__ void k_sample(Geo g, Fld p, Rec rec, int S, float *traces, int nt, in
     traces[(long long)t * nt + n] = v;
 }
 
+// Receiver samples of one level kept only at the receiver nodes (the
+// intermediate level of a two-step forward launch that is not stored): the
+// same bilinear sum as k_sample, over the node values (a corner of zero
+// weight reads 0 instead of the field).
+__global__ void k_sample_nodes(const float *nodes, const int4 *rnode, const float4 *rw, int nrec,
+                               int S, float *traces, int nt, int n)
+{
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= S * nrec)
+        return;
+    const int4 q = rnode[t];
+    const float4 w = rw[t];
+    const float a = q.x >= 0 ? nodes[q.x] : 0.f, b = q.y >= 0 ? nodes[q.y] : 0.f;
+    const float c = q.z >= 0 ? nodes[q.z] : 0.f, d = q.w >= 0 ? nodes[q.w] : 0.f;
+    float v = w.x * a + w.y * b + w.z * c + w.w * d;
+    traces[(long long)t * nt + n] = v;
+}
+
 // Receiver samples of a run of stored pressure levels: trace sample n0 + m
 // of shot s is read from level slot m (at hist + m * slot_stride, shot s at
 // s * ss).  A block covers 64 receivers by 64 steps and writes through a
@@ -561,6 +579,14 @@ void launch_sample(const Geo &g, Fld p, Fld, const Rec &r, int S, float *traces,
     int total = S * r.nrec;
     hipLaunchKernelGGL(k_sample, dim3(blocks_for(total)), dim3(kBlock), 0, st, g, p, r, S,
                        traces, nt, n);
+}
+
+void launch_sample_nodes(const float *nodes, const int4 *rnode, const float4 *rw, int nrec,
+                         int S, float *traces, int nt, int n, hipStream_t st)
+{
+    int total = S * nrec;
+    hipLaunchKernelGGL(k_sample_nodes, dim3(blocks_for(total)), dim3(kBlock), 0, st, nodes, rnode,
+                       rw, nrec, S, traces, nt, n);
 }
 
 void launch_sample_hist(const Geo &g, const float *hist, long long slot_stride, long long ss,

@@ -147,6 +147,8 @@ __device__ inline int imin(int a, int b) { return a < b ? a : b; }
 // compiler from proving the tables unchanged inside the row loops).
 typedef const __attribute__((address_space(4))) float cfloat;
 __device__ inline cfloat *ctab(const float *p) { return (cfloat *)p; }
+typedef const __attribute__((address_space(4))) unsigned cuint;
+typedef const __attribute__((address_space(4))) int cint;
 __device__ inline int imax(int a, int b) { return a > b ? a : b; }
 __device__ inline int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
@@ -590,6 +592,8 @@ __global__ void __launch_bounds__(NTHR)
     const rsrc_t rPin = grp_res(a.pin, w.s0, SPG), rVin = grp_res(a.vin, w.s0, SPG);
     const rsrc_t rPmid = grp_res(a.pmid, w.s0, SPG);
     const rsrc_t rPout = grp_res(a.pout, w.s0, SPG), rVout = grp_res(a.vout, w.s0, SPG);
+    cuint *nwin = (cuint *)a.nwin;
+    cint *ncol = (cint *)a.ncol;
     // z tables with zero outside the grid (step-one rows run past it)
     auto zt = [&](cfloat *t, int r) -> float { return row_ok(g, r) ? t[r] : 0.f; };
     // row byte offset of row r plus `extra`, or 0 when row r is outside the
@@ -753,11 +757,26 @@ __global__ void __launch_bounds__(NTHR)
             // p^{n+1} past the last grid column must read zero in step two's
             // horizontal differences
             mask_cols<C>(w, pn);
-            const unsigned km = skoff(a.pmid, k);
-            vst_row<C>(rPmid, w, mid_on, rb1 + km, pn);
+            if (a.midw == 0) {
+                const unsigned km = skoff(a.pmid, k);
+                vst_row<C>(rPmid, w, mid_on, rb1 + km, pn);
 #pragma unroll
-            for (int c = 0; c < C; ++c)
-                bst(rPmid, mid_on ? zw1[c] : kOOB, z1.base + FB + km, pzn[c]);
+                for (int c = 0; c < C; ++c)
+                    bst(rPmid, mid_on ? zw1[c] : kOOB, z1.base + FB + km, pzn[c]);
+            } else if (a.midw == 1 && mid_on && w.s0 + k < S) {
+                // only the receiver nodes of the row that this strip owns
+                const unsigned ie = nwin[((unsigned)(w.s0 + k) * (unsigned)g.Nz + (unsigned)t) *
+                                             (unsigned)sw.nstrips +
+                                         (unsigned)w.strip];
+                const unsigned first = ie >> 9, cnt = ie & 511u;
+                for (unsigned e = 0; e < cnt; ++e) {
+                    const int j = ncol[first + e];
+#pragma unroll
+                    for (int c = 0; c < C; ++c)
+                        if (w.j0 + c == j)
+                            a.nodes[first + e] = pn[c];
+                }
+            }
             // ---- step two at row r = t-3 (p^{n+1} rows r .. r+3 = P2, pn)
             if (two) {
                 float vz2[C];
@@ -1280,9 +1299,6 @@ struct A2Late {  // loads needed at the end of iteration t (single set)
     float pn1[SPG][C], z0[SPG][C], z1[SPG][C];    // p^{n+1} at t; splits of p^n, p^{n+1} at t
     float zm[SPG][C], zn[SPG][C];                 // splits of p^{n-1}, p^n at r
 };
-
-typedef const __attribute__((address_space(4))) unsigned cuint;
-typedef const __attribute__((address_space(4))) int cint;
 
 template <int SPG, int C>
 __global__ void __launch_bounds__(NTHR)
