@@ -114,7 +114,10 @@ typedef struct {
                              history <= half the device memory), else
                              ceil(sqrt(nt)); >= nt keeps the whole history   */
     int32_t band_rows;    /* batched kernels: rows each wave sweeps (4..4096);
-                             0: chosen from the grid and shot count          */
+                             0: chosen from the grid and shot count (bands
+                             for a few thousand waves, each default height
+                             lowered to the smallest one giving the same
+                             number of bands)                                */
     int32_t shots_per_group; /* batched kernels: shots a wave advances together;
                              0: default                                      */
     int32_t lane_cols;    /* batched kernels: adjacent grid columns each lane
@@ -124,7 +127,10 @@ typedef struct {
                              lane_cols 4 with 1, 2 (else FWI_EINVAL)         */
     int32_t two_step;     /* batched forward sweeps advance two time steps per
                              launch (the intermediate velocities stay on
-                             chip): 0 default (on), 1 off, 2 on              */
+                             chip; an intermediate level that is only
+                             sampled is kept at the receiver nodes alone;
+                             same results bit for bit): 0 default (on), 1
+                             off, 2 on                                       */
     int32_t two_step_band_rows;       /* decomposition of the two-step     */
     int32_t two_step_shots_per_group; /* kernel, 0: defaults; supported    */
     int32_t two_step_lane_cols;       /* (shots, cols): (1|2, 1|2), (1, 4) */
