@@ -182,9 +182,10 @@ Layout layout(const fwi_plan *p, int op)
     size_t off = 0;
     // every array is followed by at least 64 spare bytes (the batched
     // kernels may read a few bytes past a field and discard them); arrays of
-    // 8 MB and more start on 2 MB boundaries (from a 2 MB-aligned workspace,
-    // huge-page boundaries): measured on MI355X, the sweeps then run 5-7 %
-    // faster than with 256-byte alignment
+    // 8 MB and more start on 2 MB boundaries (huge-page boundaries of a 2
+    // MB-aligned workspace).  Measured on MI355X on one and the same device
+    // buffer, the sweeps take the same time (within 0.2 %) with 256-byte
+    // starts: the boundaries cost at most a few MB and buy nothing measurable
     auto take = [&](size_t floats) {
         const size_t bytes = floats * sizeof(float) + 64;
         off = align_up(off, bytes >= (8u << 20) ? (size_t)2 << 20 : kAlign);
@@ -1026,8 +1027,9 @@ fwi_status fwi_plan_create(const fwi_grid *grid, const fwi_acq *acq, const fwi_e
     g.dt = (float)G.dt;
     g.N = Nz * Nx;
     g.Npml = 2LL * G.npml * Nx + (Nz - 2LL * G.npml) * 2 * G.npml;
-    // record strides 4 KB longer than the records (consecutive shots' fields
-    // do not fall on the same offsets modulo large powers of two)
+    // record strides 4 KB longer than the records, so that consecutive
+    // shots' fields do not fall on the same offsets modulo large powers of
+    // two (measured on MI355X: no change in the sweeps' time either way)
     p->SS = align64(3 * g.N + g.Npml) + 1024;
     p->ST = align64(g.N + g.Npml) + 1024;
     {
