@@ -358,3 +358,45 @@ def test_two_step_adjoint_matches_one_step_bitwise(api, small, spg, cols):
             out.append([x.cpu().numpy() for x in (J, g1, g2)])
         for x, y in zip(*out):
             np.testing.assert_array_equal(x, y)
+
+
+# ------------------------------------------------- dense receiver lines
+
+@pytest.fixture(scope="module")
+def dense():
+    """Receivers at every grid column of two lines: one on nodes (one
+    bilinear corner of weight one, three of weight zero), one at cell
+    centres (four corners, each node shared by two receivers), so rows hold
+    as many receiver nodes as a strip has columns."""
+    w = _small(n=97, shots=3, nrec=8, nt=160, npml=10, seed=21)
+    js = np.arange(3, w.nx - 4)
+    on = np.stack([js * w.dx, np.full(js.size, 20.0 * w.dz)], axis=1)
+    mid = np.stack([(js + 0.5) * w.dx, np.full(js.size, 70.5 * w.dz)], axis=1)
+    rec = np.concatenate([on, mid])
+    w.rec_xz = np.ascontiguousarray(np.broadcast_to(rec, (w.nshots,) + rec.shape))
+    return Case(w)
+
+
+@pytest.mark.parametrize("spg,cols", [(1, 1), (2, 2), (1, 4)])
+def test_dense_receiver_lines(api, dense, spg, cols):
+    """Traces and gradients against the oracle with the two-step kernels
+    (whose node tables hold the receivers' nodes), and bitwise equal to
+    one-step launches, with the whole history and with checkpoints."""
+    w = dense.w
+    out = {}
+    for ts in (1, 2):
+        for k in (0, 9):
+            p = api.Plan(agrid(api, w), w.src_xz, w.rec_xz, ckpt_every=k, shots_per_group=spg,
+                         two_step=ts, two_step_band_rows=19, two_step_shots_per_group=spg,
+                         two_step_lane_cols=cols, adj_two_step=ts,
+                         adj_two_step_band_rows=23, adj_two_step_lane_cols=1)
+            assert p.info["two_step"] == ts - 1 and p.info["adj_two_step"] == ts - 1
+            tr = p.forward("k-rho", dense.K0, dense.r0, dense.f).cpu().numpy()
+            gK, gr = (x.cpu().numpy() for x in p.adjoint("k-rho", dense.K0, dense.r0,
+                                                          dense.f, dense.adj))
+            assert gather_err(tr, dense.d) <= TOL
+            assert maxrel(gK, dense.gK) <= TOL and maxrel(gr, dense.gr) <= TOL
+            out[(ts, k)] = (tr, gK, gr)
+    for key in out:
+        for x, y in zip(out[key], out[(1, 0)]):
+            np.testing.assert_array_equal(x, y)
