@@ -1,4 +1,6 @@
-// Batched path: one launch per time step covers every shot of the model.
+// Batched path: every launch covers every shot of the model, for one time
+// step (k_fwd, k_adj) or two (k_fwd2, k_adj2: the intermediate state stays
+// on chip).
 //
 // Each wave64 owns a strip of consecutive columns and a band of rows, and
 // marches down the band one row at a time.  A lane holds C adjacent columns
@@ -38,6 +40,10 @@
 // launches, one thread per receiver or node (done inside the sweep, they
 // made the waves holding receivers walk their lists serially, a few memory
 // round trips per node, and those waves set the length of the launch).
+// Inside a two-step launch only per-row table lookups remain: k_adj2 adds
+// its second step's adjoint source, staged per node by the injection launch
+// before it, and k_fwd2 writes the receiver nodes of an intermediate level
+// that is only sampled, for a node sampling launch after it.
 // Workgroups are numbered so that each XCD receives a contiguous range of
 // waves (neighbouring strips, the shot groups of a band and neighbouring
 // bands share its L2).
