@@ -148,3 +148,26 @@ def test_paper_example_geometry_and_scatterers():
     wf, s, known = W.paper_fd("v")
     assert wf.padded == (161, 161) and wf.nshots == 10 and wf.nrec == 100
     assert known and s[60, 60] == 1.0 and wf.rho_true.max() == pytest.approx(2200.0)
+
+
+def test_bench_algorithmic_bytes_per_cell_step():
+    # the bench prices its roofline with the streaming bytes per cell-step:
+    # forward with the pressure stored 24 + 8 fp + 8/S + 12/k + 4, adjoint
+    # 24 + 8 fp + 8/S + 4 + 16/S, times the cell-steps a launch advances
+    import bench
+    w = bench.workload("smooth1001")
+    Nz, Nx = w.padded
+    N = Nz * Nx
+    info = {"Nz": Nz, "Nx": Nx, "pml_cells": N - w.nz * w.nx}
+    ab = bench.algorithmic_bytes(info, w.nshots, 64)
+    fp = (N - w.nz * w.nx) / N
+    assert abs(fp - 0.1425) < 5e-4
+    assert abs(ab["per_cell"]["fwd_pair"] - (24 + 8 * fp + 8 / 64 + 12 / 64 + 4)) < 1e-12
+    assert abs(ab["per_cell"]["adj_pair"] - (24 + 8 * fp + 8 / 64 + 4 + 16 / 64)) < 1e-12
+    assert round(ab["per_cell"]["fwd_pair"], 2) == 29.45
+    assert round(ab["per_cell"]["adj_pair"], 2) == 29.52
+    assert ab["cell_steps"]["adj_pair"] == 2 * N * 64 == 2 * ab["cell_steps"]["adj_step"]
+    # the whole gradient (first forward sweep with checkpoints, recompute
+    # storing the pressure, adjoint): 80 + 24 fp + 40/S + 12/k bytes
+    assert abs(ab["gradient_per_cell"] - (80 + 24 * fp + 40 / 64 + 12 / 64)) < 1e-12
+    assert round(ab["gradient_per_cell"], 1) == 84.2
