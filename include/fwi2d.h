@@ -11,7 +11,7 @@
  * modelled and observed data; and the gradient of J with respect to the
  * chosen parameters, obtained by the adjoint-state method with respect to
  * bulk modulus and density and then the chain rule (scheme III: time-domain
- * staggered-grid finite differences with absorbing boundaries on all sides).
+ * staggered-grid finite differences, absorbing at every edge of the grid).
  *
  * Discretisation (the paper leaves it open; these are the readings used):
  * fourth-order staggered space derivatives and leapfrog time stepping of the
