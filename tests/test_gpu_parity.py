@@ -237,6 +237,23 @@ def test_kept_sweep_traces_match_forward(api, small, mode, ckpt):
     np.testing.assert_array_equal(kept, ref)
 
 
+@pytest.mark.parametrize("ckpt", [0, 7])
+def test_batch_member_traces_equal_alone(api, small, ckpt):
+    """A shot's traces do not depend on the shots batched with it: the
+    whole batch (shot groups of several shots, padding shots) and each shot
+    alone (groups of one) give bitwise the same traces."""
+    w = small.w
+    grid = agrid(api, w)
+    p = api.Plan(grid, w.src_xz, w.rec_xz, ckpt_every=ckpt)
+    assert p.info["shots_per_group"] > 1
+    tr = p.forward("k-rho", small.K0, small.r0, small.f).cpu().numpy()
+    for s in (0, 3, w.nshots - 1):
+        sub = w.subset(shots=[s])
+        q = api.Plan(grid, sub.src_xz, sub.rec_xz, ckpt_every=ckpt)
+        one = q.forward("k-rho", small.K0, small.r0, small.f).cpu().numpy()
+        np.testing.assert_array_equal(one[0], tr[s])
+
+
 def test_repeatable_bitwise(api, small):
     w = small.w
     p = api.Plan(agrid(api, w), w.src_xz, w.rec_xz)
