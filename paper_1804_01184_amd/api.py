@@ -102,6 +102,9 @@ class Plan:
             L.check(L.lib().fwi_plan_create(ctypes.byref(g), ctypes.byref(a), ctypes.byref(ex),
                                             ctypes.byref(h)))
         self._h = h
+        # held by the plan so that a plan collected at interpreter exit, when
+        # module globals may already be gone, can still release itself
+        self._destroy = L.lib().fwi_plan_destroy
         self.mode = mode
         self._ws = {}
 
@@ -110,8 +113,9 @@ class Plan:
         # until the last queued copy of them has run, so this never waits
         # for the device
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            L.lib().fwi_plan_destroy(h)
+        destroy = getattr(self, "_destroy", None)
+        if h is not None and h.value and destroy is not None:
+            destroy(h)
             self._h = None
 
     @property

@@ -417,3 +417,24 @@ def test_dense_receiver_lines(api, dense, spg, cols):
     for key in out:
         for x, y in zip(out[key], out[(1, 0)]):
             np.testing.assert_array_equal(x, y)
+
+
+def test_plan_alive_at_interpreter_exit(api):
+    """A plan still referenced when the interpreter exits releases itself
+    without an error, even after the binding's module globals are gone."""
+    import os
+    import subprocess
+    import sys
+    code = ("from paper_1804_01184_amd import api, workloads as W\n"
+            "w = W.point101()\n"
+            "p = api.Plan(api.Grid.of(w), w.src_xz, w.rec_xz)\n"
+            "K = w.rho_start * w.vp_start ** 2\n"
+            "d = p.forward('k-rho', K, w.rho_start, w.wavelet())\n"
+            "assert d.shape[0] == w.nshots and bool(d.abs().max() > 0)\n"
+            "print('plan ok', flush=True)\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True,
+                       timeout=100)
+    assert r.returncode == 0, r.stderr
+    assert "plan ok" in r.stdout
+    assert "Exception ignored" not in r.stderr and "Traceback" not in r.stderr, r.stderr
