@@ -182,7 +182,10 @@ void fwi_plan_destroy(fwi_plan *plan);
 
 fwi_status fwi_plan_get_info(const fwi_plan *plan, fwi_plan_info *info);
 
-/* Workspace bytes the call `op` needs with this plan (0 on a bad argument). */
+/* Workspace bytes the call `op` needs with this plan (0 on a bad argument).
+ * Ordinary device memory (hipMalloc, or a caching allocator on top of it)
+ * serves best: a physically contiguous allocation (hipExtMallocWithFlags with
+ * hipDeviceMallocContiguous) ran the sweeps about a third slower. */
 size_t fwi_workspace_bytes(const fwi_plan *plan, int32_t op);
 
 /* Forward modelling (paper: p = S G for every source): traces [S][nrec][nt]
