@@ -1,10 +1,12 @@
-"""Plan creation, plan info and workspace layout run under AddressSanitizer,
-UndefinedBehaviorSanitizer and LeakSanitizer (host code only; no GPU).
+"""Host code under AddressSanitizer, UndefinedBehaviorSanitizer and
+LeakSanitizer (no GPU).
 
-The library's host translation unit is rebuilt with the sanitizers on its
-host pass only and linked with the kernel objects of the in-tree build;
+Plan creation, plan info and workspace layout: the library's host
+translation unit is rebuilt with the sanitizers on its host pass only and
+linked with the kernel objects of the in-tree build;
 `tests/host/plan_sanitize.cpp` drives it over seeded random shapes,
-acquisitions and decompositions and the benchmark grids."""
+acquisitions and decompositions and the benchmark grids.  The FP64 oracle:
+`tests/host/oracle_sanitize.c` calls every entry point on small grids."""
 import os
 import shutil
 import subprocess
@@ -53,3 +55,25 @@ def test_plan_tables_under_sanitizers(tmp_path):
     assert "Sanitizer" not in r.stderr and "runtime error" not in r.stderr, r.stderr
     ok = int(r.stdout.split("plans ok ")[1].split()[0])
     assert ok >= 200, r.stdout
+
+
+def test_oracle_under_sanitizers(tmp_path):
+    """Every oracle entry point on small grids (with and without an
+    absorbing layer, per-shot wavelets, checkpoints every 1, 7 and nt
+    steps, one and two threads) under AddressSanitizer, UBSan and
+    LeakSanitizer; checkpointed gradients equal the whole-history one."""
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not found")
+    exe = str(tmp_path / "oracle_sanitize")
+    subprocess.run([gcc, "-g", "-O1", "-std=c99", "-fopenmp", "-fsanitize=address,undefined",
+                    "-fno-omit-frame-pointer", "-I", os.path.join(ROOT, "oracle"),
+                    os.path.join(ROOT, "tests", "host", "oracle_sanitize.c"),
+                    os.path.join(ROOT, "oracle", "fwi2d_oracle.c"), "-o", exe, "-lm"],
+                   check=True, capture_output=True)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:halt_on_error=1",
+               UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
+    r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=300)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "oracle ok" in r.stdout
+    assert "Sanitizer" not in r.stderr and "runtime error" not in r.stderr, r.stderr
