@@ -118,7 +118,9 @@ def test_adjoint_dot_product():
 @pytest.mark.parametrize("param", [0, 1, 2, 3, 4])
 def test_gradient_central_differences(param):
     """<g, dm> vs (J(m + h dm) - J(m - h dm)) / 2h, with the error falling
-    about four-fold when h halves (second-order differences)."""
+    about four-fold each time h halves (second-order differences): the
+    gradient is the exact derivative of the discrete misfit, so only the
+    differences' own truncation error remains (below 1e-6 at h = 5e-3)."""
     rng, g, vp, rho, src, rec, f = _small_problem(seed=4)
     obs = O.forward(g, O.VP_RHO, vp, rho, src, rec, f)
     vp0 = vp * (1 + 0.02 * rng.standard_normal(vp.shape))
@@ -129,12 +131,12 @@ def test_gradient_central_differences(param):
     d2 = rng.standard_normal(m2.shape) * m2 * 1e-2
     an = float(np.sum(g1 * d1) + np.sum(g2 * d2))
     errs = []
-    for h in (1e-2, 5e-3):
+    for h in (1e-2, 5e-3, 2.5e-3):
         Jp = O.misfit(O.forward(g, param, m1 + h * d1, m2 + h * d2, src, rec, f), obs)[0]
         Jm = O.misfit(O.forward(g, param, m1 - h * d1, m2 - h * d2, src, rec, f), obs)[0]
         errs.append(abs((Jp - Jm) / (2 * h) - an) / abs(an))
-    assert errs[1] <= 1e-4
-    assert 3.0 <= errs[0] / errs[1] <= 5.0
+    assert errs[1] <= 1e-6
+    assert 3.5 <= errs[0] / errs[1] <= 4.5 and 3.5 <= errs[1] / errs[2] <= 4.5
 
 
 def test_gradient_edge_cells_and_pml_fold():
@@ -148,11 +150,15 @@ def test_gradient_edge_cells_and_pml_fold():
     mask[0, :] = mask[-1, :] = mask[:, 0] = mask[:, -1] = 1.0
     dK = mask * rng.standard_normal(K0.shape) * K0 * 0.05
     dr = mask * rng.standard_normal(K0.shape) * r0 * 0.05
-    h = 1e-2
-    Jp = O.misfit(O.forward(g, O.K_RHO, K0 + h * dK, r0 + h * dr, src, rec, f), obs)[0]
-    Jm = O.misfit(O.forward(g, O.K_RHO, K0 - h * dK, r0 - h * dr, src, rec, f), obs)[0]
     an = float(np.sum(gK * dK) + np.sum(gr * dr))
-    assert abs((Jp - Jm) / (2 * h) - an) <= 1e-5 * abs(an)
+    errs = []
+    for h in (1e-2, 5e-3):
+        Jp = O.misfit(O.forward(g, O.K_RHO, K0 + h * dK, r0 + h * dr, src, rec, f), obs)[0]
+        Jm = O.misfit(O.forward(g, O.K_RHO, K0 - h * dK, r0 - h * dr, src, rec, f), obs)[0]
+        errs.append(abs((Jp - Jm) / (2 * h) - an) / abs(an))
+    # only the differences' own second-order error remains
+    assert errs[1] <= 2e-6
+    assert 3.5 <= errs[0] / errs[1] <= 4.5
 
 
 def test_checkpointed_equals_full_history():
