@@ -267,7 +267,8 @@ def test_analytic_green_function_and_refinement():
 
 def test_pml_reflection_bound():
     """The 101² point benchmark grid (101^2 at 5 m + 20 cells): traces match a domain so large
-    that nothing returns from its edges, to 1e-2 of the direct arrival."""
+    that nothing returns from its edges, to within the layer's design reflection
+    coefficient R = 1e-3 of the direct arrival (3.9e-4 measured)."""
     w = W.point101()
     rho = w.rho_start
     K = rho * w.vp_start ** 2
@@ -279,7 +280,7 @@ def test_pml_reflection_bound():
     shift = pad * w.dx
     db = O.forward_krho(gb, w.src_xz + shift, w.rec_xz + shift,
                         np.full((nb, nb), K[0, 0]), np.full((nb, nb), rho[0, 0]), w.wavelet())
-    assert np.abs(d - db).max() <= 1e-2 * np.abs(db).max()
+    assert np.abs(d - db).max() <= g.pml_r * np.abs(db).max()
 
 
 def test_point_scatterer_radiation_patterns():
