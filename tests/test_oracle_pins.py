@@ -305,8 +305,8 @@ def test_point_scatterer_radiation_patterns():
     sR = O.forward_krho(g, src, rec, K0, r1, f)[0] - d0
     cos_theta = (rec[0] - 250.0) @ np.array([0.0, 1.0]) / 100.0
     ampK = np.sqrt(np.sum(sK ** 2, axis=1))
-    assert ampK.min() / ampK.max() >= 0.9
+    assert ampK.min() / ampK.max() >= 0.95          # 0.969 measured
     ratio = np.sum(sR * sK, axis=1) / np.sum(sK * sK, axis=1)
-    assert np.corrcoef(ratio, -cos_theta)[0, 1] >= 0.995
+    assert np.corrcoef(ratio, -cos_theta)[0, 1] >= 0.999   # 0.99943 measured
     fwd = ratio[np.argmax(cos_theta)]
-    assert abs(fwd + 1.0) <= 0.1
+    assert abs(fwd + 1.0) <= 0.03                   # -1.008 measured
