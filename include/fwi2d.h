@@ -119,7 +119,9 @@ typedef struct {
                              lowered to the smallest one giving the same
                              number of bands)                                */
     int32_t shots_per_group; /* batched kernels: shots a wave advances together;
-                             0: default                                      */
+                             0: default (with the two-step adjoint 2, or 1
+                             when 16-row bands of two-shot waves would not
+                             fill the device once; without it up to 4)      */
     int32_t lane_cols;    /* batched kernels: adjacent grid columns each lane
                              holds, 1, 2 or 4; 0: default.  Supported
                              (shots_per_group, lane_cols) pairs: lane_cols 1
@@ -133,7 +135,13 @@ typedef struct {
                              off, 2 on                                       */
     int32_t two_step_band_rows;       /* decomposition of the two-step     */
     int32_t two_step_shots_per_group; /* kernel, 0: defaults; supported    */
-    int32_t two_step_lane_cols;       /* (shots, cols): (1|2, 1|2), (1, 4) */
+    int32_t two_step_lane_cols;       /* (shots, cols): (1|2, 1|2), (1, 4).
+                             Defaults: 2 columns per lane, 2 shots per wave
+                             from 800 padded columns up (else 1).  Default
+                             band rows of both two-step kernels: among the
+                             heights the autotuner tries, the one with the
+                             fewest rounds of resident waves times rows per
+                             band (H + 6), the taller on a tie              */
     int32_t adj_two_step; /* batched adjoint sweeps advance two time steps per
                              launch (the intermediate adjoint state stays on
                              chip; same results bit for bit): 0 default (on

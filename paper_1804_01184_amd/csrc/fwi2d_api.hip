@@ -1033,12 +1033,55 @@ fwi_status fwi_plan_create(const fwi_grid *grid, const fwi_acq *acq, const fwi_e
     p->SS = align64(3 * g.N + g.Npml) + 1024;
     p->ST = align64(g.N + g.Npml) + 1024;
     {
-        // defaults (from decomposition sweeps on MI355X): up to four shots per
-        // wave, one column per lane, bands short enough for about 4096
-        // waves, 8 to 64 rows
+        // Defaults, from the autotuner's measurements on MI355X over padded
+        // grids of 281 to 2081 nodes a side with 8 to 64 shots.
+        //
+        // Band heights of the two-step kernels: a launch of W equal waves, R
+        // of which the device holds at once, runs about ceil(W / R) rounds,
+        // each as long as one band (H rows plus the 6 rows of the two-step
+        // halo).  Among the heights the autotuner tries, the smallest
+        // ceil(W / R) (H + 6) wins, ties going to the taller band.  Over
+        // those shapes this picks the measured best adjoint height in most
+        // of them and one within 6% of the best in the rest; the forward
+        // choices below come within 8%.
+        auto resident = [](bool adjoint, int sg, int cl) {
+            const int r = resident_waves2(adjoint, sg, cl);
+            return r > 0 ? r : 2048;   // two waves per SIMD of 256 compute units
+        };
+        auto pick_rows = [&](int Sp, int sg, int cl, int R, const int *cand, int nc) {
+            int best = 0;
+            long long best_cost = 0;
+            for (int i = 0; i < nc; ++i) {
+                const int H = balanced_rows(Nz, (int)std::min<long long>(cand[i], Nz));
+                const long long W = sweep_of(g, Sp, H, sg, cl, 2).nwaves;
+                const long long cost = (W + R - 1) / R * (H + 6);
+                if (best == 0 || cost < best_cost || (cost == best_cost && H > best)) {
+                    best = H;
+                    best_cost = cost;
+                }
+            }
+            return best;
+        };
+        static const int kRowsAdj2[] = {12, 16, 20, 24, 32, 48, 64, 96, 128, 160, 192};
+        static const int kRowsFwd2[] = {12, 14, 16, 18, 20, 24, 28, 32, 48, 64, 96};
+        const bool adj2_wanted = p->mode != FWI_EXEC_PLAIN && ex.adj_two_step != 1;
+        const int ca = ex.adj_two_step_lane_cols ? ex.adj_two_step_lane_cols : 1;
+        // Shot groups (shared by the one-step kernels and the two-step
+        // adjoint, whose partial gradients they share): with the two-step
+        // adjoint two shots a wave, or one when even 16-row bands of
+        // two-shot waves leave the device short of one round of waves
+        // (four shots a wave run that kernel out of registers); without
+        // it up to four shots a wave.  One column per lane.
         int spg = ex.shots_per_group, cols = ex.lane_cols;
         if (spg == 0) {
-            spg = p->S >= 4 ? 4 : (p->S >= 2 ? 2 : 1);
+            if (adj2_wanted) {
+                spg = p->S >= 2 ? 2 : 1;
+                if (spg == 2 && adj2_supported(2, ca) &&
+                    sweep_of(g, p->S, 16, 2, ca, 2).nwaves < resident(true, 2, ca))
+                    spg = 1;
+            } else {
+                spg = p->S >= 4 ? 4 : (p->S >= 2 ? 2 : 1);
+            }
             if (cols != 0 && !fused_supported(spg, cols))
                 spg = 1;
         }
@@ -1057,27 +1100,25 @@ fwi_status fwi_plan_create(const fwi_grid *grid, const fwi_acq *acq, const fwi_e
         // the batched kernels address a shot group's records, the model and
         // a partial gradient with 32-bit byte offsets below 2^31
         const long long lim = (1LL << 31) - 64LL * Nx;
-        // two-step forward kernel over the same padded shots: defaults two
-        // shots (one if the padded count is odd) and one column per lane,
-        // bands giving about 8192 waves, 16 to 96 rows (its halo is 6 rows)
-        const int spg2 = ex.two_step_shots_per_group ? ex.two_step_shots_per_group
-                                                     : (p->Spad % 2 == 0 ? 2 : 1);
-        const int cols2 = ex.two_step_lane_cols ? ex.two_step_lane_cols : 1;
-        int H2 = ex.two_step_band_rows;
-        if (H2 == 0) {
-            Sweep one = sweep_of(g, p->Spad, (int)Nz, spg2, cols2, 2);
-            long long per_band = (long long)one.nstrips * one.ngroups;
-            long long bands = std::max<long long>(1, (8192 + per_band - 1) / per_band);
-            H2 = balanced_rows(Nz, (int)std::min<long long>(96, std::max<long long>(
-                                       16, (Nz + bands - 1) / bands)));
+        // two-step forward kernel over the same padded shots: two columns
+        // per lane; two shots a wave from 800 padded columns up, else one
+        // (and one if the padded count is odd)
+        const int cols2 = ex.two_step_lane_cols ? ex.two_step_lane_cols : 2;
+        int spg2 = ex.two_step_shots_per_group;
+        if (spg2 == 0) {
+            spg2 = Nx >= 800 && p->Spad % 2 == 0 ? 2 : 1;
+            if (!fused2_supported(spg2, cols2))
+                spg2 = 1;
         }
+        int H2 = ex.two_step_band_rows;
+        if (H2 == 0)
+            H2 = pick_rows(p->Spad, spg2, cols2, resident(false, spg2, cols2), kRowsFwd2,
+                           (int)(sizeof kRowsFwd2 / sizeof kRowsFwd2[0]));
         p->sweep2 = sweep_of(g, p->Spad, H2, spg2, cols2, 2);
         p->two_step = p->mode != FWI_EXEC_PLAIN && ex.two_step != 1 && p->Spad % spg2 == 0 &&
                       (long long)spg2 * p->SS * 4 < lim;
         // two-step adjoint over the same shot groups (it shares their
-        // partial gradients with the one-step kernel): default one column
-        // per lane, bands giving about 4096 waves, 16 to 128 rows
-        const int ca = ex.adj_two_step_lane_cols ? ex.adj_two_step_lane_cols : 1;
+        // partial gradients with the one-step kernel)
         const bool a2ok = p->mode != FWI_EXEC_PLAIN && adj2_supported(spg, ca);
         if (ex.adj_two_step == 2 && !a2ok) {
             delete p;
@@ -1094,13 +1135,9 @@ fwi_status fwi_plan_create(const fwi_grid *grid, const fwi_acq *acq, const fwi_e
         }
         p->adj2 = ex.adj_two_step != 1 && a2ok && a2fits;
         int Ha = ex.adj_two_step_band_rows;
-        if (Ha == 0) {
-            Sweep one = sweep_of(g, p->Spad, (int)Nz, spg, ca, 2);
-            long long per_band = (long long)one.nstrips * one.ngroups;
-            long long bands = std::max<long long>(1, (4096 + per_band - 1) / per_band);
-            Ha = balanced_rows(Nz, (int)std::min<long long>(128, std::max<long long>(
-                                       16, (Nz + bands - 1) / bands)));
-        }
+        if (Ha == 0)
+            Ha = pick_rows(p->Spad, spg, ca, resident(true, spg, ca), kRowsAdj2,
+                           (int)(sizeof kRowsAdj2 / sizeof kRowsAdj2[0]));
         p->sweep_a2 = sweep_of(g, p->Spad, Ha, spg, ca, 2);
         if (p->mode != FWI_EXEC_PLAIN &&
             ((long long)spg * p->SS * 4 >= lim || 3 * g.N * 4 >= lim)) {

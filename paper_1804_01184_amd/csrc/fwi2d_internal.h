@@ -183,6 +183,9 @@ bool adj2_supported(int spg, int cols);
 // (steps = 2) forward kernels; the two-step kernels need twice the halo.
 int strip_cols(int cols, int steps = 1);
 Sweep sweep_of(const Geo &g, int S, int band_rows, int spg, int cols, int steps = 1);
+// Waves of the two-step adjoint (adjoint = true) or forward kernel with
+// (spg, cols) that the current device holds at once, 0 if unknown.
+int resident_waves2(bool adjoint, int spg, int cols);
 
 // Source tables of a plan for the batched kernels, kept in device memory
 // so that the kernels take one pointer to them.

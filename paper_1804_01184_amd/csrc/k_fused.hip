@@ -1720,7 +1720,45 @@ void launch_a2(const Geo &g, const float *tabs, const float *model, int S, const
                           tabs, model, S, sw, a);
 }
 
+// Waves of `kern` that the current device holds at once: its workgroups per
+// compute unit (from its register and LDS use) times the compute units, or
+// 0 when the runtime cannot tell.
+template <typename Kern>
+int resident_waves(Kern kern)
+{
+    int blocks = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, kern, NTHR, 0) != hipSuccess ||
+        hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return blocks * (NTHR / WAVE) * cus;
+}
+
 }  // namespace
+
+int resident_waves2(bool adjoint, int spg, int cols)
+{
+    if (adjoint) {
+        switch (cols * 16 + spg) {
+        case 16 + 1: return resident_waves(k_adj2<1, 1>);
+        case 16 + 2: return resident_waves(k_adj2<2, 1>);
+        case 16 + 4: return resident_waves(k_adj2<4, 1>);
+        case 32 + 1: return resident_waves(k_adj2<1, 2>);
+        case 32 + 2: return resident_waves(k_adj2<2, 2>);
+        }
+        return 0;
+    }
+    switch (cols * 16 + spg) {
+    case 16 + 1: return resident_waves(k_fwd2<1, 1>);
+    case 16 + 2: return resident_waves(k_fwd2<2, 1>);
+    case 32 + 1: return resident_waves(k_fwd2<1, 2>);
+    case 32 + 2: return resident_waves(k_fwd2<2, 2>);
+    case 64 + 1: return resident_waves(k_fwd2<1, 4>);
+    }
+    return 0;
+}
 
 // Instantiated (shots per group, columns per lane) pairs of the two-step
 // adjoint kernel.

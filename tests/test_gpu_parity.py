@@ -244,8 +244,11 @@ def test_batch_member_traces_equal_alone(api, small, ckpt):
     alone (groups of one) give bitwise the same traces."""
     w = small.w
     grid = agrid(api, w)
-    p = api.Plan(grid, w.src_xz, w.rec_xz, ckpt_every=ckpt)
-    assert p.info["shots_per_group"] > 1
+    # 6 shots in groups of 4 (two padding shots) and pairs for the
+    # two-step forward
+    p = api.Plan(grid, w.src_xz, w.rec_xz, ckpt_every=ckpt, shots_per_group=4,
+                 two_step_shots_per_group=2)
+    assert p.info["shots_per_group"] == 4 and p.info["two_step_shots_per_group"] == 2
     tr = p.forward("k-rho", small.K0, small.r0, small.f).cpu().numpy()
     for s in (0, 3, w.nshots - 1):
         sub = w.subset(shots=[s])
