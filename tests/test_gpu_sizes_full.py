@@ -42,7 +42,7 @@ TOL = 1e-4
 LONG = pytest.mark.timeout(900)
 SHIPPED = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
                        "paper_1804_01184_amd", "tuned_gfx950.json")
-PARAMS4 = (O.K_RHO, O.VP_RHO, O.IP_RHO, O.VP_IP)
+PARAMS5 = (O.K_RHO, O.VP_RHO, O.IP_RHO, O.VP_IP, O.INVK_INVRHO)
 
 
 @pytest.fixture(scope="module")
@@ -147,7 +147,7 @@ def _plan(api, w, full, **kw):
     return api.Plan(api.Grid.of(w), w.src_xz, w.rec_xz, **{**d, **kw})
 
 
-def _check_adjoint(api, plan, ora, gK, gr, params=PARAMS4):
+def _check_adjoint(api, plan, ora, gK, gr, params=PARAMS5):
     adj = ora.adjoint_source()
     for param in params:
         m1, m2 = O.krho_to_model(param, ora.K0, ora.r0)
@@ -245,7 +245,7 @@ def test_smooth1001_adjoint(api, s1001):
     full, ora = s1001
     plan = _plan(api, ora.w, full, ckpt_every=64)
     gK, gr = ora.gradient(64)
-    _check_adjoint(api, plan, ora, gK, gr, params=(O.K_RHO, O.VP_RHO))
+    _check_adjoint(api, plan, ora, gK, gr)
 
 
 # --------------------------------------------------------------- layered-2001
