@@ -1043,7 +1043,7 @@ fwi_status fwi_plan_create(const fwi_grid *grid, const fwi_acq *acq, const fwi_e
         // ceil(W / R) (H + 6) wins, ties going to the taller band.  Over
         // those shapes this picks the measured best adjoint height in most
         // of them and one within 6% of the best in the rest; the forward
-        // choices below come within 8%.
+        // choices below come within 10%.
         auto resident = [](bool adjoint, int sg, int cl) {
             const int r = resident_waves2(adjoint, sg, cl);
             return r > 0 ? r : 2048;   // two waves per SIMD of 256 compute units
@@ -1070,8 +1070,9 @@ fwi_status fwi_plan_create(const fwi_grid *grid, const fwi_acq *acq, const fwi_e
         // adjoint, whose partial gradients they share): with the two-step
         // adjoint two shots a wave, or one when even 16-row bands of
         // two-shot waves leave the device short of one round of waves
-        // (four shots a wave run that kernel out of registers); without
-        // it up to four shots a wave.  One column per lane.
+        // (with four shots a wave that kernel needs all 256 VGPRs and ran
+        // about 1.5 times slower); without it up to four shots a wave.  One
+        // column per lane.
         int spg = ex.shots_per_group, cols = ex.lane_cols;
         if (spg == 0) {
             if (adj2_wanted) {
