@@ -1064,7 +1064,18 @@ fwi_status fwi_plan_create(const fwi_grid *grid, const fwi_acq *acq, const fwi_e
         };
         static const int kRowsAdj2[] = {12, 16, 20, 24, 32, 48, 64, 96, 128, 160, 192};
         static const int kRowsFwd2[] = {12, 14, 16, 18, 20, 24, 28, 32, 48, 64, 96};
-        const bool adj2_wanted = p->mode != FWI_EXEC_PLAIN && ex.adj_two_step != 1;
+        // the batched kernels address a shot group's records, the model and
+        // a partial gradient with 32-bit byte offsets below 2^31
+        const long long lim = (1LL << 31) - 64LL * Nx;
+        // the two-step adjoint addresses a group's three pressure levels
+        // (consecutive store levels, the padded shots' ST floats apart)
+        // through one buffer resource
+        auto adj2_fits = [&](int sg) {
+            const long long Sp = (p->S + sg - 1) / sg * sg;
+            return (2LL * Sp + sg) * p->ST * 4 < lim;
+        };
+        const bool adj2_wanted =
+            p->mode != FWI_EXEC_PLAIN && ex.adj_two_step != 1 && adj2_fits(2);
         const int ca = ex.adj_two_step_lane_cols ? ex.adj_two_step_lane_cols : 1;
         // Shot groups (shared by the one-step kernels and the two-step
         // adjoint, whose partial gradients they share): with the two-step
@@ -1098,9 +1109,6 @@ fwi_status fwi_plan_create(const fwi_grid *grid, const fwi_acq *acq, const fwi_e
         }
         p->sweep = sweep_of(g, p->S, H, spg, cols);
         p->Spad = p->mode == FWI_EXEC_PLAIN ? p->S : p->sweep.ngroups * spg;
-        // the batched kernels address a shot group's records, the model and
-        // a partial gradient with 32-bit byte offsets below 2^31
-        const long long lim = (1LL << 31) - 64LL * Nx;
         // two-step forward kernel over the same padded shots: two columns
         // per lane; two shots a wave from 800 padded columns up, else one
         // (and one if the padded count is odd)
@@ -1126,9 +1134,7 @@ fwi_status fwi_plan_create(const fwi_grid *grid, const fwi_acq *acq, const fwi_e
             return fail(FWI_EINVAL, "two-step adjoint: shots_per_group %d with lane_cols %d not "
                         "supported (or plain mode)", spg, ca);
         }
-        // its three pressure levels of a group (consecutive store levels,
-        // Spad ST floats apart) are addressed through one buffer resource
-        const bool a2fits = (2LL * p->Spad + spg) * p->ST * 4 < lim;
+        const bool a2fits = adj2_fits(spg);
         if (ex.adj_two_step == 2 && a2ok && !a2fits) {
             delete p;
             return fail(FWI_EINVAL, "two-step adjoint: three pressure levels of %d shots exceed "

@@ -137,6 +137,29 @@ int main(int argc, char **argv)
     ex.adj_two_step_band_rows = 181;
     ex.adj_two_step_lane_cols = 1;
     one(rng, 1001, 1001, 40, 4000, 64, 360, false, &ex, true);
+    // all 256 shots of the 2001 x 2001 layered model on one device: three
+    // pressure levels of the padded shots exceed 2 GiB, so the two-step
+    // adjoint is off and the shot groups are those of the one-step kernels
+    {
+        const double h = 5.0;
+        const int n = 2001, S = 256;
+        const fwi_grid g{n, n, 40, 8000, h, h, 0.5 * h / 3500.0, 3500.0, 1e-3};
+        std::vector<double> src(2 * S), rec(2 * (size_t)S * 4);
+        for (int s = 0; s < S; ++s) {
+            src[2 * s] = src[2 * s + 1] = 100.0 + 30.0 * s;
+            for (int r = 0; r < 4; ++r)
+                rec[2 * ((size_t)s * 4 + r)] = rec[2 * ((size_t)s * 4 + r) + 1] = 200.0 + 20.0 * r;
+        }
+        const fwi_acq a{S, 4, 0, src.data(), rec.data()};
+        fwi_plan *p = nullptr;
+        fwi_plan_info info;
+        if (fwi_plan_create(&g, &a, nullptr, &p) != FWI_OK || fwi_plan_get_info(p, &info) != FWI_OK)
+            fail("256-shot plan");
+        if (info.adj_two_step != 0 || info.shots_per_group != 4)
+            fail("256-shot plan: shot groups without the two-step adjoint");
+        fwi_plan_destroy(p);
+        ++n_ok;
+    }
     // a receiver whose bilinear cell reaches past the last node is refused
     {
         const double h = 5.0;
